@@ -1,0 +1,197 @@
+"""FP64 CPU oracle for batched rejection-sampling placement (test infrastructure).
+
+Only tests/, ``__graft_entry__.smoke()`` and bench.py's ``cpu_baseline`` leg
+may import this package.  The product path (the HIP library and its binding)
+never does.  The C part (oracle.c) is compiled with gcc into liboracle.so; it
+shares no code with the GPU path.
+
+Parity notes for each function are in the C source and in the tests that pin
+them (Philox known-answer vectors, box-SDF and sphere-distance closed forms,
+rigid-motion invariance, brute force on tiny scenes).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c -> liboracle.so (plain -O2, IEEE FP64, OpenMP over scenes)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC",
+                               "-shared", "-fno-fast-math", "-ffp-contract=off",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Batch(C.Structure):
+    _fields_ = [("n_scenes", C.c_int),
+                ("obj_off", C.c_void_p), ("sph_off", C.c_void_p), ("tmpl", C.c_void_p),
+                ("obj_sup", C.c_void_p), ("obj_ncand", C.c_void_p), ("sup", C.c_void_p),
+                ("box_off", C.c_void_p), ("box", C.c_void_p),
+                ("grid_off", C.c_void_p), ("grid", C.c_void_p), ("grid_src", C.c_void_p),
+                ("grid_val", C.c_void_p), ("scene_id", C.c_void_p)]
+
+
+class _GenArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("margin", C.c_double), ("retries", C.c_int),
+                ("default_ncand", C.c_int), ("band", C.c_double), ("max_steps", C.c_int)]
+
+
+class _GenOut(C.Structure):
+    _fields_ = [("status", C.c_void_p), ("n_placed", C.c_void_p),
+                ("rec_attempt", C.c_void_p), ("rec_idx", C.c_void_p),
+                ("rec_pose", C.c_void_p), ("rec_banded", C.c_void_p),
+                ("rec_clear", C.c_void_p), ("placed", C.c_void_p), ("n_cand", C.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_u01.argtypes = [C.c_uint32]
+        L.orc_u01.restype = C.c_double
+        L.orc_box_sdf.argtypes = [C.c_void_p] * 4
+        L.orc_box_sdf.restype = C.c_double
+        L.orc_grid_sample.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
+        L.orc_grid_sample.restype = C.c_double
+        L.orc_sample_poses.argtypes = [C.POINTER(_Batch), C.c_void_p, C.c_void_p, C.c_uint64,
+                                       C.c_int] + [C.c_void_p] * 4
+        L.orc_check.argtypes = [C.POINTER(_Batch)] + [C.c_void_p] * 9
+        L.orc_generate.argtypes = [C.POINTER(_Batch), C.POINTER(_GenArgs), C.POINTER(_GenOut)]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_max_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data if a is not None else None
+
+
+class _Keep:
+    """Holds the FP64 / int32 copies a ctypes batch points into."""
+
+    def __init__(self, b, scene_id=None):
+        self.obj_off = np.ascontiguousarray(b.obj_off, np.int32)
+        self.sph_off = np.ascontiguousarray(b.sph_off, np.int32)
+        self.tmpl = np.ascontiguousarray(b.tmpl, np.float64)
+        self.obj_sup = np.ascontiguousarray(b.obj_sup, np.int32)
+        self.obj_ncand = np.ascontiguousarray(b.obj_ncand, np.int32)
+        self.sup = np.ascontiguousarray(b.sup, np.float64)
+        self.box_off = np.ascontiguousarray(b.box_off, np.int32)
+        self.box = np.ascontiguousarray(b.box, np.float64).reshape(-1, 16)
+        self.scene_id = None if scene_id is None else np.ascontiguousarray(scene_id, np.int32)
+        self.grid_off = self.grid = self.grid_src = self.grid_ptrs = None
+        self._vals = None
+        if getattr(b, "grid_off", None) is not None:
+            self.grid_off = np.ascontiguousarray(b.grid_off, np.int32)
+            self.grid = np.ascontiguousarray(b.grid, np.float64).reshape(-1, 24)
+            self.grid_src = np.ascontiguousarray(b.grid_src, np.int32)
+            self._vals = [np.ascontiguousarray(v, np.float32) for v in b.grid_vals]
+            self.grid_ptrs = (C.c_void_p * len(self._vals))(*[v.ctypes.data for v in self._vals])
+        self.cb = _Batch(int(len(self.obj_off) - 1), _p(self.obj_off), _p(self.sph_off),
+                         _p(self.tmpl), _p(self.obj_sup), _p(self.obj_ncand), _p(self.sup),
+                         _p(self.box_off), _p(self.box), _p(self.grid_off), _p(self.grid),
+                         _p(self.grid_src),
+                         C.cast(self.grid_ptrs, C.c_void_p) if self.grid_ptrs is not None else None,
+                         _p(self.scene_id))
+
+
+# ---------------------------------------------------------------------------
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def u01(w: int) -> float:
+    return float(lib().orc_u01(int(w) & 0xFFFFFFFF))
+
+
+def box_sdf(R, c, h, p) -> float:
+    R = np.ascontiguousarray(R, np.float64).reshape(9)
+    c = np.ascontiguousarray(c, np.float64)
+    h = np.ascontiguousarray(h, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    return float(lib().orc_box_sdf(_p(R), _p(c), _p(h), _p(p)))
+
+
+def grid_sample(vals, origin, h, pg) -> float:
+    v = np.ascontiguousarray(vals, np.float32)
+    dims = np.array([v.shape[2], v.shape[1], v.shape[0]], np.int32)
+    o = np.ascontiguousarray(origin, np.float64)
+    pg = np.ascontiguousarray(pg, np.float64)
+    return float(lib().orc_grid_sample(_p(v), _p(dims), _p(o), float(h), _p(pg)))
+
+
+def sample_poses(b, obj_idx, cand_off, seed: int, attempt: int, scene_id=None):
+    K = _Keep(b, scene_id)
+    oi = np.ascontiguousarray(obj_idx, np.int32)
+    co = np.ascontiguousarray(cand_off, np.int32)
+    tot = int(co[-1])
+    out = [np.zeros(tot, np.float64) for _ in range(4)]
+    lib().orc_sample_poses(C.byref(K.cb), _p(oi), _p(co), C.c_uint64(seed), int(attempt),
+                           *[_p(a) for a in out])
+    return out
+
+
+def check(b, obj_idx, cand_off, n_placed, placed, poses, scene_id=None) -> np.ndarray:
+    """Clearance of each candidate pose (support frame) of object obj_idx[s]
+    against scene s's boxes/grids and its first n_placed[s] objects."""
+    K = _Keep(b, scene_id)
+    oi = np.ascontiguousarray(obj_idx, np.int32)
+    co = np.ascontiguousarray(cand_off, np.int32)
+    npl = np.ascontiguousarray(n_placed, np.int32)
+    pl = np.ascontiguousarray(placed, np.float64).reshape(-1, 4)
+    ps = [np.ascontiguousarray(a, np.float64) for a in poses]
+    clr = np.zeros(int(co[-1]), np.float64)
+    lib().orc_check(C.byref(K.cb), _p(oi), _p(co), _p(npl), _p(pl), *[_p(a) for a in ps],
+                    _p(clr))
+    return clr
+
+
+def generate(b, seed: int, margin: float = 0.005, retries: int = 10, default_ncand: int = 1024,
+             band: float = 1e-5, max_steps: int = 0, scene_id=None, threads=None) -> dict:
+    """Batched rejection-sampling placement; returns per-scene status
+    (1 valid, 2 invalid), per-object chosen (attempt, idx), poses, band flags,
+    and the world spheres of the placed objects."""
+    if threads is not None:
+        set_threads(threads)
+    K = _Keep(b, scene_id)
+    n, n_obj, n_sph = K.cb.n_scenes, len(K.sph_off) - 1, K.tmpl.shape[0]
+    out = dict(status=np.zeros(n, np.int8), n_placed=np.zeros(n, np.int32),
+               rec_attempt=np.zeros(n_obj, np.int32), rec_idx=np.zeros(n_obj, np.int32),
+               rec_pose=np.zeros((n_obj, 4), np.float64), rec_banded=np.zeros(n_obj, np.int8),
+               rec_clear=np.zeros(n_obj, np.float64),
+               placed=np.full((n_sph, 4), np.nan, np.float64), n_cand=np.zeros(n, np.int64))
+    go = _GenOut(*[_p(out[k]) for k in ("status", "n_placed", "rec_attempt", "rec_idx",
+                                         "rec_pose", "rec_banded", "rec_clear", "placed",
+                                         "n_cand")])
+    ga = _GenArgs(int(seed), float(margin), int(retries), int(default_ncand), float(band),
+                  int(max_steps))
+    lib().orc_generate(C.byref(K.cb), C.byref(ga), C.byref(go))
+    return out

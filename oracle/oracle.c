@@ -1,0 +1,354 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for batched rejection-sampling placement.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+ * its Python binding) links, imports or calls this file.  Only tests/,
+ * __graft_entry__.smoke() and the cpu_baseline leg of bench.py use it.
+ * It shares no code, header, table or helper with the GPU path.
+ *
+ * What it computes, and where the paper defines it (Sceniris, arXiv 2512.16896):
+ *   - Rejection sampling per object: sample a pose, check it for collision,
+ *     retry on collision (Sec. III "Main algorithm"; Sec. IV-A overview).
+ *   - Candidate positions are 2-D points sampled on the support polygon plus a
+ *     z offset (Sec. III "Position sampling"), sampled in the canonical support
+ *     frame and moved by the support's world pose (Sec. IV-C, last paragraph).
+ *   - Orientation: random rotation about z (Sec. III "Main algorithm").
+ *   - Batched form: N independent scenes, one pose per (scene, object)
+ *     (Sec. IV-B); retries only for the scenes that failed (Sec. IV-D).
+ *   - 10 retries per object; a scene whose object exhausts them is invalid
+ *     (Sec. V-A).
+ * Readings where the paper is silent (collision geometry = sphere sets vs.
+ * oriented boxes / placed spheres; strict margin test; first-valid selection;
+ * Philox counter layout) are the project's and are listed in the design notes.
+ *
+ * Everything is FP64 except the random bits, which are exact integers.
+ * There is no culling, no early exit inside a candidate and no blocking: every
+ * candidate's clearance is the plain minimum over all sphere/obstacle pairs.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, J. Salmon et al., "Parallel random numbers: as easy as     */
+/* 1, 2, 3", SC'11.  Ten rounds of the 4x32 Philox S-box with the published  */
+/* multipliers and Weyl key increments.                                      */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 32 random bits -> a uniform in (0,1): the top 23 bits plus one half, times
+ * 2^-23.  Exactly representable in binary32 and binary64.                   */
+double orc_u01(uint32_t w)
+{
+    return ((double)(w >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scene batch (all arrays row-major, FP64 copies of the FP32 inputs).       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n_scenes;
+    const int32_t *obj_off;   /* [n_scenes+1] objects of a scene, in placement order */
+    const int32_t *sph_off;   /* [n_obj+1] template spheres of an object            */
+    const double  *tmpl;      /* [n_sph][4] sphere (x,y,z,r) in the object frame      */
+    const int32_t *obj_sup;   /* [n_obj] support surface of the object                */
+    const int32_t *obj_ncand; /* [n_obj] candidates per attempt (NULL: default)       */
+    const double  *sup;       /* [n_sup][16] R[9] t[3] half-x half-y inset dz         */
+    const int32_t *box_off;   /* [n_scenes+1] static boxes of a scene                 */
+    const double  *box;       /* [n_box][16] R[9] c[3] h[3] pad                        */
+    const int32_t *grid_off;  /* [n_scenes+1] voxel grid instances of a scene (NULL)  */
+    const double  *grid;      /* [n_grid][24] inst. pose W[9] tw[3], origin[3], h, dims[3], pad */
+    const int32_t *grid_src;  /* [n_grid] which voxel asset the instance samples       */
+    const float  **grid_val;  /* [n_asset] node values, x fastest                     */
+    const int32_t *scene_id;  /* [n_scenes] scene number used in the random counter
+                                 (NULL: the position in the batch)                   */
+} orc_batch;
+
+typedef struct {
+    uint64_t seed;
+    double   margin;
+    int      retries;       /* attempts per object = retries + 1 */
+    int      default_ncand;
+    double   band;          /* |clearance - margin| < band marks a candidate as banded */
+    int      max_steps;     /* place at most this many objects per scene (<=0: all) */
+} orc_gen_args;
+
+/* Pose of a candidate in its support frame: position (x,y,z), yaw about z. */
+typedef struct { double x, y, z, yaw; } orc_pose;
+
+static double zrest_of(const orc_batch *b, int o)
+{
+    /* lowest point of the sphere set in the object frame, as a lift */
+    double lift = -INFINITY;
+    for (int k = b->sph_off[o]; k < b->sph_off[o + 1]; ++k) {
+        double v = b->tmpl[4 * k + 3] - b->tmpl[4 * k + 2];
+        if (v > lift) lift = v;
+    }
+    return lift;
+}
+
+/* Candidate i of attempt a for the object at position `step` of scene s. */
+static orc_pose sample_pose(const orc_batch *b, uint64_t seed, int s, int step, int o,
+                            int attempt, int i)
+{
+    const double *u = b->sup + 16 * b->obj_sup[o];
+    uint32_t sid = b->scene_id ? (uint32_t)b->scene_id[s] : (uint32_t)s;
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)attempt, (uint32_t)step, sid};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double ax = u[12] - u[14], ay = u[13] - u[14];
+    orc_pose p;
+    p.x = ax * (2.0 * orc_u01(w[0]) - 1.0);
+    p.y = ay * (2.0 * orc_u01(w[1]) - 1.0);
+    p.yaw = 2.0 * M_PI * orc_u01(w[2]);
+    p.z = u[15] + zrest_of(b, o);
+    return p;
+}
+
+/* World sphere k of object o at pose p on support u:
+ *   world = R_u * (Rz(yaw) * c_k + (x,y,z)) + t_u                             */
+static void world_sphere(const orc_batch *b, int o, int k, orc_pose p, double out[4])
+{
+    const double *u = b->sup + 16 * b->obj_sup[o];
+    const double *c = b->tmpl + 4 * k;
+    double cs = cos(p.yaw), sn = sin(p.yaw);
+    double l[3] = {cs * c[0] - sn * c[1] + p.x, sn * c[0] + cs * c[1] + p.y, c[2] + p.z};
+    for (int r = 0; r < 3; ++r)
+        out[r] = u[3 * r + 0] * l[0] + u[3 * r + 1] * l[1] + u[3 * r + 2] * l[2] + u[9 + r];
+    out[3] = c[3];
+}
+
+/* Exact signed distance from point p to an oriented box (R: box->world
+ * rotation, c: centre, h: half extents).  Standard box SDF:
+ *   q = |R^T (p - c)| - h,  sdf = || max(q,0) || + min(max(qx,qy,qz), 0).    */
+double orc_box_sdf(const double R[9], const double c[3], const double h[3], const double p[3])
+{
+    double d[3] = {p[0] - c[0], p[1] - c[1], p[2] - c[2]};
+    double q[3];
+    for (int a = 0; a < 3; ++a) {
+        double loc = R[0 * 3 + a] * d[0] + R[1 * 3 + a] * d[1] + R[2 * 3 + a] * d[2];
+        q[a] = fabs(loc) - h[a];
+    }
+    double ox = q[0] > 0 ? q[0] : 0, oy = q[1] > 0 ? q[1] : 0, oz = q[2] > 0 ? q[2] : 0;
+    double outside = sqrt(ox * ox + oy * oy + oz * oz);
+    double m = q[0];
+    if (q[1] > m) m = q[1];
+    if (q[2] > m) m = q[2];
+    double inside = m < 0 ? m : 0;
+    return outside + inside;
+}
+
+/* Trilinear interpolation of a node-centred voxel grid (value v[i,j,k] at
+ * origin + h*(i,j,k)), queried at a point already in the grid frame.  Outside
+ * the node box the grid returns +inf (nothing there).                        */
+double orc_grid_sample(const float *val, const int dims[3], const double origin[3], double h,
+                       const double pg[3])
+{
+    double f[3];
+    int i0[3];
+    for (int a = 0; a < 3; ++a) {
+        double g = (pg[a] - origin[a]) / h;
+        if (!(g >= 0.0) || g > (double)(dims[a] - 1)) return INFINITY;
+        int i = (int)floor(g);
+        if (i > dims[a] - 2) i = dims[a] - 2;
+        i0[a] = i;
+        f[a] = g - (double)i;
+    }
+    double acc = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? f[0] : 1 - f[0]) * (dy ? f[1] : 1 - f[1]) * (dz ? f[2] : 1 - f[2]);
+                size_t idx = ((size_t)(i0[2] + dz) * dims[1] + (size_t)(i0[1] + dy)) * dims[0]
+                             + (size_t)(i0[0] + dx);
+                acc += w * (double)val[idx];
+            }
+    return acc;
+}
+
+/* Clearance of one placed sphere set against the obstacles of scene s:
+ * min over its spheres of (signed distance to every box, grid and already
+ * placed sphere) minus the sphere radius.  +inf with no obstacles.          */
+static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
+                        const double *placed, int n_placed_sph)
+{
+    double best = INFINITY;
+    for (int k = 0; k < n_sph; ++k) {
+        const double *p = sph + 4 * k;
+        for (int bx = b->box_off[s]; bx < b->box_off[s + 1]; ++bx) {
+            const double *B = b->box + 16 * bx;
+            double v = orc_box_sdf(B, B + 9, B + 12, p) - p[3];
+            if (v < best) best = v;
+        }
+        if (b->grid_off) {
+            for (int g = b->grid_off[s]; g < b->grid_off[s + 1]; ++g) {
+                const double *G = b->grid + 24 * g;
+                /* world -> grid frame: pg = W p + tw */
+                double pg[3];
+                for (int r = 0; r < 3; ++r)
+                    pg[r] = G[3 * r] * p[0] + G[3 * r + 1] * p[1] + G[3 * r + 2] * p[2] + G[9 + r];
+                int dims[3] = {(int)G[16], (int)G[17], (int)G[18]};
+                double v = orc_grid_sample(b->grid_val[b->grid_src[g]], dims, G + 12, G[15], pg) - p[3];
+                if (v < best) best = v;
+            }
+        }
+        for (int j = 0; j < n_placed_sph; ++j) {
+            const double *q = placed + 4 * j;
+            double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+            double v = sqrt(dx * dx + dy * dy + dz * dz) - q[3] - p[3];
+            if (v < best) best = v;
+        }
+    }
+    return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported: sample poses for one attempt, dense clearance of given poses,   */
+/* and the whole batched rejection-sampling generation.                      */
+/* ------------------------------------------------------------------------ */
+
+/* obj_idx[s]: object to sample for scene s (-1: none); cand_off: CSR of the
+ * candidates of each scene in the output arrays.                            */
+void orc_sample_poses(const orc_batch *b, const int32_t *obj_idx, const int32_t *cand_off,
+                      uint64_t seed, int attempt, double *x, double *y, double *z, double *yaw)
+{
+    for (int s = 0; s < b->n_scenes; ++s) {
+        int o = obj_idx[s];
+        if (o < 0) continue;
+        int step = o - b->obj_off[s];
+        for (int i = 0; i < cand_off[s + 1] - cand_off[s]; ++i) {
+            orc_pose p = sample_pose(b, seed, s, step, o, attempt, i);
+            int t = cand_off[s] + i;
+            x[t] = p.x; y[t] = p.y; z[t] = p.z; yaw[t] = p.yaw;
+        }
+    }
+}
+
+/* Clearance of the given candidate poses of object obj_idx[s] against the
+ * boxes and grids of scene s and the first n_placed[s] objects of scene s,
+ * whose world spheres are in `placed` (parallel to the template table).     */
+void orc_check(const orc_batch *b, const int32_t *obj_idx, const int32_t *cand_off,
+               const int32_t *n_placed, const double *placed, const double *x, const double *y,
+               const double *z, const double *yaw, double *clr)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int s = 0; s < b->n_scenes; ++s) {
+        int o = obj_idx[s];
+        if (o < 0) continue;
+        int ns = b->sph_off[o + 1] - b->sph_off[o];
+        double *sph = (double *)malloc(sizeof(double) * 4 * (ns > 0 ? ns : 1));
+        int first = b->sph_off[b->obj_off[s]];
+        int n_pl = b->sph_off[b->obj_off[s] + n_placed[s]] - first;
+        for (int t = cand_off[s]; t < cand_off[s + 1]; ++t) {
+            orc_pose p = {x[t], y[t], z[t], yaw[t]};
+            for (int k = 0; k < ns; ++k) world_sphere(b, o, b->sph_off[o] + k, p, sph + 4 * k);
+            clr[t] = clearance(b, s, sph, ns, placed + 4 * first, n_pl);
+        }
+        free(sph);
+    }
+}
+
+typedef struct {
+    int8_t  *status;     /* [n_scenes] 0 in progress, 1 valid, 2 invalid       */
+    int32_t *n_placed;   /* [n_scenes]                                          */
+    int32_t *rec_attempt;/* [n_obj] attempt that placed the object (-1 none)    */
+    int32_t *rec_idx;    /* [n_obj] chosen candidate index (-1 none)            */
+    double  *rec_pose;   /* [n_obj][4] x y z yaw in the support frame           */
+    int8_t  *rec_banded; /* [n_obj] a candidate the decision depended on was banded */
+    double  *rec_clear;  /* [n_obj] clearance of the chosen candidate           */
+    double  *placed;     /* [n_sph][4] world spheres of placed objects          */
+    int64_t *n_cand;     /* [n_scenes] candidates evaluated                     */
+} orc_gen_out;
+
+void orc_generate(const orc_batch *b, const orc_gen_args *g, orc_gen_out *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int s = 0; s < b->n_scenes; ++s) {
+        int o0 = b->obj_off[s], o1 = b->obj_off[s + 1];
+        int first = b->sph_off[o0];
+        int maxsph = 1;
+        for (int o = o0; o < o1; ++o)
+            if (b->sph_off[o + 1] - b->sph_off[o] > maxsph) maxsph = b->sph_off[o + 1] - b->sph_off[o];
+        double *sph = (double *)malloc(sizeof(double) * 4 * maxsph);
+        int8_t status = 0;
+        int placed_obj = 0;
+        int64_t ncand = 0;
+        for (int o = o0; o < o1; ++o) {
+            out->rec_attempt[o] = -1; out->rec_idx[o] = -1; out->rec_banded[o] = 0;
+            out->rec_clear[o] = NAN;
+            for (int c = 0; c < 4; ++c) out->rec_pose[4 * o + c] = NAN;
+        }
+        for (int o = o0; o < o1 && status == 0; ++o) {
+            int step = o - o0;
+            if (g->max_steps > 0 && step >= g->max_steps) break;
+            int ns = b->sph_off[o + 1] - b->sph_off[o];
+            int nc = b->obj_ncand ? b->obj_ncand[o] : g->default_ncand;
+            int n_pl = b->sph_off[o] - first;
+            int chosen = -1, chosen_att = -1;
+            double chosen_clr = NAN;
+            orc_pose chosen_pose = {0, 0, 0, 0};
+            int8_t banded = 0;
+            for (int a = 0; a <= g->retries && chosen < 0; ++a) {
+                for (int i = 0; i < nc; ++i) {
+                    orc_pose p = sample_pose(b, g->seed, s, step, o, a, i);
+                    for (int k = 0; k < ns; ++k) world_sphere(b, o, b->sph_off[o] + k, p, sph + 4 * k);
+                    double cl = clearance(b, s, sph, ns, out->placed + 4 * first, n_pl);
+                    ++ncand;
+                    if (fabs(cl - g->margin) < g->band) banded = 1;
+                    if (cl >= g->margin) {   /* collision-free: clearance not below the margin */
+                        chosen = i; chosen_att = a; chosen_pose = p; chosen_clr = cl;
+                        break;
+                    }
+                }
+            }
+            out->rec_banded[o] = banded;
+            if (chosen < 0) { status = 2; break; }
+            out->rec_attempt[o] = chosen_att;
+            out->rec_idx[o] = chosen;
+            out->rec_clear[o] = chosen_clr;
+            out->rec_pose[4 * o + 0] = chosen_pose.x;
+            out->rec_pose[4 * o + 1] = chosen_pose.y;
+            out->rec_pose[4 * o + 2] = chosen_pose.z;
+            out->rec_pose[4 * o + 3] = chosen_pose.yaw;
+            for (int k = 0; k < ns; ++k)
+                world_sphere(b, o, b->sph_off[o] + k, chosen_pose, out->placed + 4 * (b->sph_off[o] + k));
+            ++placed_obj;
+        }
+        if (status == 0 && placed_obj == o1 - o0) status = 1;
+        out->status[s] = status;
+        out->n_placed[s] = placed_obj;
+        out->n_cand[s] = ncand;
+        free(sph);
+    }
+}
+
+/* Thread control for timing runs (OpenMP over scenes). */
+#ifdef _OPENMP
+#include <omp.h>
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
+#else
+void orc_set_threads(int n) { (void)n; }
+int orc_max_threads(void) { return 1; }
+#endif

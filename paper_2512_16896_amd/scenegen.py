@@ -1,0 +1,283 @@
+"""Seeded synthetic scene batches (inputs only).
+
+This module draws the *inputs* of a placement run: object sphere templates,
+support surfaces and their world poses, static boxes and voxel-grid furniture.
+It holds none of the placement method's arithmetic (no pose sampling, no
+collision test, no selection); both the HIP path and the CPU oracle read the
+arrays it returns.
+
+Layouts (row-major, FP32 unless noted):
+  obj_off   int32 [n+1]        objects of scene s: obj_off[s] .. obj_off[s+1]-1,
+                               in placement order
+  sph_off   int32 [n_obj+1]    template spheres of object o
+  tmpl      float32 [n_sph,4]  sphere (x, y, z, r) in the object frame
+  obj_sup   int32 [n_obj]      support surface index of object o
+  obj_ncand int32 [n_obj]      candidates drawn per attempt for object o
+  sup       float32 [n_sup,16] R[9] (row-major, support->world), t[3],
+                               half-x, half-y, inset, z lift
+  box_off   int32 [n+1]        static boxes of scene s
+  box       float32 [n_box,16] R[9] (box->world), centre[3], half extents[3], 0
+  grid_*    voxel-grid furniture (optional, multi-shelf workload only)
+
+The workloads follow the five synthetic configurations of the project (one
+table scene; 4096 batched scenes; 16384 uneven scenes; the learned-proposal
+workload on 4096-scene shapes; dense shelves with voxel grids).  Sizes that
+the paper does not give are the readings recorded in the design notes.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# Clutter knob: static box centres are drawn over the support rectangle grown
+# by this many metres on each side (calibrated so that the plain method leaves
+# a non-degenerate fraction of scenes valid on the 4096-scene workload).
+BOX_SPREAD_DEFAULT = 1.0
+
+
+@dataclasses.dataclass
+class SceneBatch:
+    obj_off: np.ndarray
+    sph_off: np.ndarray
+    tmpl: np.ndarray
+    obj_sup: np.ndarray
+    obj_ncand: np.ndarray
+    sup: np.ndarray
+    box_off: np.ndarray
+    box: np.ndarray
+    # voxel-grid furniture (None when absent)
+    grid_off: Optional[np.ndarray] = None     # int32 [n+1]
+    grid: Optional[np.ndarray] = None         # float32 [n_grid,24] see grid_instance()
+    grid_src: Optional[np.ndarray] = None     # int32 [n_grid] asset index
+    grid_vals: Optional[list] = None          # list of float32 [nz,ny,nx] assets
+    name: str = ""
+    params: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_scenes(self) -> int:
+        return int(self.obj_off.shape[0] - 1)
+
+    @property
+    def n_objects(self) -> int:
+        return int(self.sph_off.shape[0] - 1)
+
+    @property
+    def n_spheres(self) -> int:
+        return int(self.tmpl.shape[0])
+
+    @property
+    def n_boxes(self) -> int:
+        return int(self.box.shape[0])
+
+    def objects_per_scene(self) -> np.ndarray:
+        return np.diff(self.obj_off)
+
+    def spheres_per_object(self) -> np.ndarray:
+        return np.diff(self.sph_off)
+
+    def spheres_per_scene(self) -> np.ndarray:
+        return self.sph_off[self.obj_off[1:]] - self.sph_off[self.obj_off[:-1]]
+
+    def boxes_per_scene(self) -> np.ndarray:
+        return np.diff(self.box_off)
+
+
+def rotz(a: np.ndarray) -> np.ndarray:
+    """Rotation matrices about z for an array of angles -> [..., 3, 3]."""
+    c, s = np.cos(a), np.sin(a)
+    z, o = np.zeros_like(a), np.ones_like(a)
+    return np.stack([np.stack([c, -s, z], -1), np.stack([s, c, z], -1),
+                     np.stack([z, z, o], -1)], -2)
+
+
+def _support_rows(R: np.ndarray, t: np.ndarray, hx, hy, inset, lift) -> np.ndarray:
+    n = R.shape[0]
+    out = np.zeros((n, 16), np.float64)
+    out[:, 0:9] = R.reshape(n, 9)
+    out[:, 9:12] = t
+    out[:, 12] = hx
+    out[:, 13] = hy
+    out[:, 14] = inset
+    out[:, 15] = lift
+    return out.astype(np.float32)
+
+
+def _templates(rng, n_obj, S, side=(0.05, 0.25), rad=(0.01, 0.05)):
+    """Sphere sets: per object a cube side L ~ U(side); centres uniform in the
+    cube [-L/2, L/2]^3, radii ~ U(rad).  S may be an int or a per-object array."""
+    S = np.broadcast_to(np.asarray(S, np.int64), (n_obj,))
+    sph_off = np.zeros(n_obj + 1, np.int64)
+    sph_off[1:] = np.cumsum(S)
+    tot = int(sph_off[-1])
+    L = rng.uniform(side[0], side[1], size=n_obj)
+    Lrep = np.repeat(L, S)
+    c = (rng.random((tot, 3)) - 0.5) * Lrep[:, None]
+    r = rng.uniform(rad[0], rad[1], size=tot)
+    tmpl = np.concatenate([c, r[:, None]], 1)
+    return sph_off, tmpl
+
+
+def _footprint_order(obj_off, sph_off, tmpl):
+    """Placement order inside each scene: descending footprint radius
+    (largest objects first).  Returns a permutation of the objects."""
+    n_obj = sph_off.shape[0] - 1
+    rho = np.hypot(tmpl[:, 0], tmpl[:, 1]) + tmpl[:, 3]
+    fp = np.maximum.reduceat(rho, sph_off[:-1]) if n_obj else np.zeros(0)
+    scene_of = np.repeat(np.arange(obj_off.shape[0] - 1), np.diff(obj_off))
+    return np.lexsort((-fp, scene_of))
+
+
+def _reorder_objects(perm, sph_off, tmpl, *per_obj):
+    S = np.diff(sph_off)[perm]
+    new_off = np.zeros_like(sph_off)
+    new_off[1:] = np.cumsum(S)
+    idx = np.concatenate([np.arange(sph_off[o], sph_off[o + 1]) for o in perm]) \
+        if len(perm) else np.zeros(0, np.int64)
+    return (new_off, tmpl[idx]) + tuple(a[perm] for a in per_obj)
+
+
+def _boxes(rng, n, B, hx, hy, spread, sup_R, sup_t, half=(0.05, 0.5)):
+    """Static cuboids resting on each scene's support: half extents ~ U(half)^3,
+    yaw ~ U[0, 2pi), centre uniform over the support grown by `spread`."""
+    B = np.broadcast_to(np.asarray(B, np.int64), (n,))
+    hx = np.broadcast_to(np.asarray(hx, np.float64), (n,))
+    hy = np.broadcast_to(np.asarray(hy, np.float64), (n,))
+    box_off = np.zeros(n + 1, np.int64)
+    box_off[1:] = np.cumsum(B)
+    tot = int(box_off[-1])
+    scene = np.repeat(np.arange(n), B)
+    h = rng.uniform(half[0], half[1], size=(tot, 3))
+    yaw = rng.uniform(0, 2 * np.pi, size=tot)
+    ex, ey = hx[scene] + spread, hy[scene] + spread
+    cx = rng.uniform(-1, 1, size=tot) * ex
+    cy = rng.uniform(-1, 1, size=tot) * ey
+    cl = np.stack([cx, cy, h[:, 2]], 1)
+    Rl = rotz(yaw)
+    Rw = np.einsum('nij,njk->nik', sup_R[scene], Rl)
+    cw = np.einsum('nij,nj->ni', sup_R[scene], cl) + sup_t[scene]
+    box = np.zeros((tot, 16), np.float64)
+    box[:, 0:9] = Rw.reshape(tot, 9)
+    box[:, 9:12] = cw
+    box[:, 12:15] = h
+    return box_off, box.astype(np.float32)
+
+
+def _support_poses(rng, n):
+    """Per-scene world pose of the support: yaw about z, translation
+    (U[-1,1], U[-1,1], U[0.4, 1.0])."""
+    R = rotz(rng.uniform(0, 2 * np.pi, size=n))
+    t = np.stack([rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(0.4, 1.0, n)], 1)
+    return R, t
+
+
+def uniform_batch(n_scenes: int, n_obj: int, n_sph: int, n_cand: int, n_box: int,
+                  hx: float, hy: float, seed: int = 0, spread: float = BOX_SPREAD_DEFAULT,
+                  side=(0.05, 0.25), rad=(0.01, 0.05), box_half=(0.05, 0.5),
+                  inset: float = 0.0, lift: float = 0.0, name: str = "") -> SceneBatch:
+    """Every scene: one rectangular support (half extents hx, hy) at a random
+    world pose, n_box static cuboids, n_obj objects of n_sph spheres each."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5CE2]))
+    sup_R, sup_t = _support_poses(rng, n_scenes)
+    sup = _support_rows(sup_R, sup_t, hx, hy, inset, lift)
+    obj_off = np.arange(n_scenes + 1, dtype=np.int64) * n_obj
+    sph_off, tmpl = _templates(rng, n_scenes * n_obj, n_sph, side, rad)
+    perm = _footprint_order(obj_off, sph_off, tmpl)
+    sph_off, tmpl = _reorder_objects(perm, sph_off, tmpl)
+    obj_sup = np.repeat(np.arange(n_scenes), n_obj)
+    box_off, box = _boxes(rng, n_scenes, n_box, hx, hy, spread, sup_R, sup_t, box_half)
+    return SceneBatch(
+        obj_off=obj_off.astype(np.int32), sph_off=sph_off.astype(np.int32),
+        tmpl=tmpl.astype(np.float32), obj_sup=obj_sup.astype(np.int32),
+        obj_ncand=np.full(n_scenes * n_obj, n_cand, np.int32), sup=sup,
+        box_off=box_off.astype(np.int32), box=box, name=name,
+        params=dict(n_scenes=n_scenes, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand,
+                    n_box=n_box, hx=hx, hy=hy, seed=seed, spread=spread))
+
+
+def uneven_batch(n_scenes: int, seed: int = 0, spread: float = BOX_SPREAD_DEFAULT,
+                 n_obj=(5, 60), n_sph=(16, 256), n_cand=(512, 4096), n_box=(4, 32),
+                 name: str = "") -> SceneBatch:
+    """Uneven workload: per scene N ~ U{5..60} objects, B ~ U{4..32} boxes;
+    per object S ~ U{16..256} spheres and C ~ U{512..4096} candidates per
+    attempt; the 2.0 x 1.0 m support is scaled by sqrt(N / 20)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x0E7E]))
+    N = rng.integers(n_obj[0], n_obj[1] + 1, size=n_scenes)
+    B = rng.integers(n_box[0], n_box[1] + 1, size=n_scenes)
+    scale = np.sqrt(N / 20.0)
+    hx, hy = 1.0 * scale, 0.5 * scale
+    sup_R, sup_t = _support_poses(rng, n_scenes)
+    sup = _support_rows(sup_R, sup_t, hx, hy, 0.0, 0.0)
+    obj_off = np.zeros(n_scenes + 1, np.int64)
+    obj_off[1:] = np.cumsum(N)
+    n_tot = int(obj_off[-1])
+    S = rng.integers(n_sph[0], n_sph[1] + 1, size=n_tot)
+    C = rng.integers(n_cand[0], n_cand[1] + 1, size=n_tot)
+    sph_off, tmpl = _templates(rng, n_tot, S)
+    perm = _footprint_order(obj_off, sph_off, tmpl)
+    sph_off, tmpl, C = _reorder_objects(perm, sph_off, tmpl, C)
+    obj_sup = np.repeat(np.arange(n_scenes), N)
+    box_off, box = _boxes(rng, n_scenes, B, hx, hy, spread, sup_R, sup_t)
+    return SceneBatch(
+        obj_off=obj_off.astype(np.int32), sph_off=sph_off.astype(np.int32),
+        tmpl=tmpl.astype(np.float32), obj_sup=obj_sup.astype(np.int32),
+        obj_ncand=C.astype(np.int32), sup=sup, box_off=box_off.astype(np.int32),
+        box=box, name=name, params=dict(n_scenes=n_scenes, seed=seed, spread=spread))
+
+
+def table_scene(seed: int = 0, spread: float = BOX_SPREAD_DEFAULT) -> SceneBatch:
+    """One 1.2 x 0.8 m table; 8 objects x 32 spheres; 256 candidates; 4 boxes."""
+    return uniform_batch(1, 8, 32, 256, 4, 0.6, 0.4, seed=seed, spread=spread, name="table-1")
+
+
+def batched_scenes(n_scenes: int = 4096, seed: int = 0,
+                   spread: float = BOX_SPREAD_DEFAULT) -> SceneBatch:
+    """4096 scenes on a 2.0 x 1.0 m support; 20 objects x 64 spheres; 1024
+    candidates per attempt; 16 static oriented cuboids."""
+    return uniform_batch(n_scenes, 20, 64, 1024, 16, 1.0, 0.5, seed=seed, spread=spread,
+                         name=f"batched-{n_scenes}")
+
+
+def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
+    """The scenes `scenes` of a batch as a batch of their own, plus the
+    original scene indices (which the random-number counters must keep)."""
+    scenes = np.asarray(scenes, np.int64)
+    objs = np.concatenate([np.arange(b.obj_off[s], b.obj_off[s + 1]) for s in scenes])
+    boxes = np.concatenate([np.arange(b.box_off[s], b.box_off[s + 1]) for s in scenes])
+    obj_off = np.zeros(len(scenes) + 1, np.int64)
+    obj_off[1:] = np.cumsum(b.obj_off[scenes + 1] - b.obj_off[scenes])
+    box_off = np.zeros(len(scenes) + 1, np.int64)
+    box_off[1:] = np.cumsum(b.box_off[scenes + 1] - b.box_off[scenes])
+    S = (b.sph_off[objs + 1] - b.sph_off[objs]).astype(np.int64)
+    sph_off = np.zeros(len(objs) + 1, np.int64)
+    sph_off[1:] = np.cumsum(S)
+    sidx = np.concatenate([np.arange(b.sph_off[o], b.sph_off[o + 1]) for o in objs])
+    sups = np.unique(b.obj_sup[objs])
+    remap = -np.ones(b.sup.shape[0], np.int64)
+    remap[sups] = np.arange(len(sups))
+    out = SceneBatch(
+        obj_off=obj_off.astype(np.int32), sph_off=sph_off.astype(np.int32),
+        tmpl=b.tmpl[sidx].copy(), obj_sup=remap[b.obj_sup[objs]].astype(np.int32),
+        obj_ncand=b.obj_ncand[objs].copy(), sup=b.sup[sups].copy(),
+        box_off=box_off.astype(np.int32), box=b.box[boxes].copy(),
+        name=b.name + "-subset", params=dict(b.params))
+    if b.grid_off is not None:
+        grids = np.concatenate([np.arange(b.grid_off[s], b.grid_off[s + 1]) for s in scenes])
+        goff = np.zeros(len(scenes) + 1, np.int64)
+        goff[1:] = np.cumsum(b.grid_off[scenes + 1] - b.grid_off[scenes])
+        out.grid_off = goff.astype(np.int32)
+        out.grid = b.grid[grids].copy()
+        out.grid_src = b.grid_src[grids].copy()
+        out.grid_vals = b.grid_vals
+    return out, scenes.astype(np.int32)
+
+
+def random_poses(rng, n: int, hx: float, hy: float, z=(0.0, 0.3)):
+    """Arbitrary candidate poses (support frame) for checker tests."""
+    x = rng.uniform(-hx, hx, n)
+    y = rng.uniform(-hy, hy, n)
+    zz = rng.uniform(z[0], z[1], n)
+    yaw = rng.uniform(0, 2 * math.pi, n)
+    return [a.astype(np.float32) for a in (x, y, zz, yaw)]

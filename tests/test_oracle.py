@@ -1,0 +1,373 @@
+"""Pins for the FP64 oracle: published known answers, closed forms, invariants
+and an independent brute force on tiny scenes (all CPU)."""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import bruteforce as bf
+from paper_2512_16896_amd import scenegen as sg
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _kat():
+    rows = []
+    for line in open(os.path.join(GOLD, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(t, 16) for t in line.split()]
+        rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+# --------------------------------------------------------------------------
+# Random bits
+# --------------------------------------------------------------------------
+def test_philox_known_answers(orc):
+    for ctr, key, want in _kat():
+        assert orc.philox4x32_10(ctr, key).tolist() == want
+
+
+def test_philox_second_implementation_known_answers():
+    for ctr, key, want in _kat():
+        assert bf.philox(np.array([ctr]), key)[0].tolist() == want
+
+
+def test_philox_implementations_agree(orc):
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(64, 4), dtype=np.uint64)
+    key = [int(x) for x in rng.integers(0, 2 ** 32, size=2, dtype=np.uint64)]
+    got = bf.philox(ctr, key)
+    for i in range(64):
+        assert orc.philox4x32_10(ctr[i], key).tolist() == got[i].tolist()
+
+
+def test_unit_mapping_is_exact_and_open(orc):
+    assert orc.u01(0) == 0.5 * 2.0 ** -23
+    assert orc.u01(0xFFFFFFFF) == 1.0 - 0.5 * 2.0 ** -23
+    for w in [0, 1, 511, 512, 0x12345678, 0xFFFFFFFF]:
+        v = orc.u01(w)
+        assert 0.0 < v < 1.0
+        assert float(np.float32(v)) == v          # exactly representable in binary32
+    # uniformity of the mapped words (chi-square over 64 bins)
+    rng = np.random.default_rng(2)
+    ctr = np.stack([np.arange(20000), np.zeros(20000), np.zeros(20000), rng.integers(0, 9, 20000)], 1)
+    u = bf.unit(bf.philox(ctr, (7, 9))[:, 0])
+    cnt, _ = np.histogram(u, bins=64, range=(0, 1))
+    chi2 = float(((cnt - 20000 / 64) ** 2 / (20000 / 64)).sum())
+    assert chi2 < 120.0   # 63 dof: p ~ 1e-5 threshold
+
+
+# --------------------------------------------------------------------------
+# Box signed distance
+# --------------------------------------------------------------------------
+def _rot(yaw, pitch=0.0, roll=0.0):
+    cz, sz, cy, sy, cx, sx = (math.cos(yaw), math.sin(yaw), math.cos(pitch), math.sin(pitch),
+                              math.cos(roll), math.sin(roll))
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    return Rz @ Ry @ Rx
+
+
+def test_box_sdf_closed_forms(orc):
+    I = np.eye(3)
+    h = np.array([0.3, 0.2, 0.1])
+    c = np.zeros(3)
+    # face points: distance = offset along the normal
+    for t in [0.0, 0.01, 0.5]:
+        assert orc.box_sdf(I, c, h, [0.3 + t, 0.05, -0.02]) == pytest.approx(t, abs=1e-15)
+        assert orc.box_sdf(I, c, h, [0.1, -0.2 - t, 0.03]) == pytest.approx(t, abs=1e-15)
+    # edge: Euclidean norm of the two excesses
+    assert orc.box_sdf(I, c, h, [0.3 + 0.03, 0.2 + 0.04, 0.0]) == pytest.approx(0.05, abs=1e-15)
+    # corner: norm of the three excesses
+    assert orc.box_sdf(I, c, h, [0.5, 0.4, 0.3]) == pytest.approx(math.sqrt(3 * 0.04), abs=1e-15)
+    # centre: minus the smallest half extent
+    assert orc.box_sdf(I, c, h, [0, 0, 0]) == pytest.approx(-0.1, abs=1e-15)
+    # inside near a face: minus the distance to that face
+    assert orc.box_sdf(I, c, h, [0.28, 0.0, 0.0]) == pytest.approx(-0.02, abs=1e-15)
+
+
+def test_box_sdf_matches_closest_point_and_rigid_motion(orc):
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        R = _rot(*rng.uniform(-3, 3, 3))
+        c = rng.uniform(-1, 1, 3)
+        h = rng.uniform(0.05, 0.5, 3)
+        p = c + rng.uniform(-1, 1, 3)
+        d = orc.box_sdf(R, c, h, p)
+        assert d == pytest.approx(float(bf.box_distance(R, c, h, p[None])[0]), abs=1e-12)
+        # joint rigid motion of box and point leaves the distance unchanged
+        Q = _rot(*rng.uniform(-3, 3, 3))
+        t = rng.uniform(-2, 2, 3)
+        assert orc.box_sdf(Q @ R, Q @ c + t, h, Q @ p + t) == pytest.approx(d, abs=1e-12)
+
+
+def test_box_sdf_is_one_lipschitz(orc):
+    rng = np.random.default_rng(4)
+    R = _rot(0.3, 0.2, -0.1)
+    c = np.array([0.1, 0.2, 0.3])
+    h = np.array([0.2, 0.1, 0.3])
+    for _ in range(300):
+        p, q = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+        assert abs(orc.box_sdf(R, c, h, p) - orc.box_sdf(R, c, h, q)) <= np.linalg.norm(p - q) + 1e-12
+
+
+# --------------------------------------------------------------------------
+# Tiny batches built by hand
+# --------------------------------------------------------------------------
+def tiny_batch(objs, boxes=(), hx=0.5, hy=0.4, sup_R=np.eye(3), sup_t=(0, 0, 0), ncand=8,
+               n_scenes=1):
+    """objs: list of [S,4] templates (same for every scene); boxes: list of
+    (R, c, h) in world coordinates."""
+    n_obj = len(objs)
+    tm = np.concatenate([np.asarray(o, np.float64) for o in objs] * n_scenes).astype(np.float32)
+    S = [len(o) for o in objs] * n_scenes
+    sph_off = np.zeros(len(S) + 1, np.int32)
+    sph_off[1:] = np.cumsum(S)
+    sup = np.zeros((n_scenes, 16), np.float32)
+    sup[:, 0:9] = np.asarray(sup_R, np.float64).reshape(9)
+    sup[:, 9:12] = sup_t
+    sup[:, 12], sup[:, 13] = hx, hy
+    bx = np.zeros((len(boxes) * n_scenes, 16), np.float32)
+    for s in range(n_scenes):
+        for i, (R, c, h) in enumerate(boxes):
+            bx[s * len(boxes) + i, 0:9] = np.asarray(R).reshape(9)
+            bx[s * len(boxes) + i, 9:12] = c
+            bx[s * len(boxes) + i, 12:15] = h
+    return sg.SceneBatch(
+        obj_off=(np.arange(n_scenes + 1) * n_obj).astype(np.int32), sph_off=sph_off, tmpl=tm,
+        obj_sup=np.repeat(np.arange(n_scenes), n_obj).astype(np.int32),
+        obj_ncand=np.full(n_obj * n_scenes, ncand, np.int32), sup=sup,
+        box_off=(np.arange(n_scenes + 1) * len(boxes)).astype(np.int32), box=bx)
+
+
+def test_sphere_pair_clearance_closed_form(orc):
+    # object 0 placed at the origin, object 1 checked at x = D along the axis
+    b = tiny_batch([[[0, 0, 0, 0.05]], [[0, 0, 0, 0.03]]], hx=2, hy=2)
+    placed = np.array([[0.0, 0.0, 0.05, 0.05], [np.nan] * 4])
+    for D in [0.5, 0.08, 0.081, 0.2]:
+        clr = orc.check(b, [1], [0, 1], [1], placed, ([D], [0.0], [0.03], [1.234]))
+        # candidate sphere centre at z = 0.03, placed sphere centre at z = 0.05;
+        # the template radius is the binary32 value of 0.03
+        want = math.hypot(D, 0.05 - 0.03) - 0.05 - float(np.float32(0.03))
+        assert clr[0] == pytest.approx(want, abs=1e-15)
+
+
+def test_no_obstacles_is_infinite_and_first_candidate_wins(orc):
+    b = tiny_batch([[[0.01, 0.02, 0.0, 0.02], [0.0, -0.03, 0.01, 0.01]]])
+    clr = orc.check(b, [0], [0, 3], [0], np.zeros((2, 4)), ([0, 0.1, 0.2], [0, 0, 0], [0.02] * 3,
+                                                             [0, 1, 2]))
+    assert np.all(np.isinf(clr))
+    out = orc.generate(b, seed=5)
+    assert out["status"].tolist() == [1]
+    assert out["rec_attempt"].tolist() == [0] and out["rec_idx"].tolist() == [0]
+
+
+def test_pose_sampling_matches_definition(orc):
+    # x, y uniform over the (inset) rectangle, yaw = 2 pi u, z = lift + rest height
+    tm = np.array([[0.0, 0.0, -0.02, 0.03], [0.01, 0.0, 0.04, 0.01]])
+    b = tiny_batch([tm], hx=0.7, hy=0.3, ncand=16)
+    b.sup[0, 14] = 0.05
+    b.sup[0, 15] = 0.002
+    x, y, z, yaw = orc.sample_poses(b, [0], [0, 16], seed=0x1234_0000_0042, attempt=3)
+    ctr = np.stack([np.arange(16), np.full(16, 3), np.zeros(16), np.zeros(16)], 1)
+    u = bf.unit(bf.philox(ctr, (0x42, 0x1234)))
+    a_x, a_y = np.float64(np.float32(0.7)) - np.float64(np.float32(0.05)), \
+        np.float64(np.float32(0.3)) - np.float64(np.float32(0.05))
+    np.testing.assert_allclose(x, a_x * (2 * u[:, 0] - 1), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(y, a_y * (2 * u[:, 1] - 1), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(yaw, 2 * np.pi * u[:, 2], rtol=0, atol=1e-15)
+    lift = np.float64(np.float32(0.002)) + max(np.float64(np.float32(0.03)) - np.float64(np.float32(-0.02)),
+                                              np.float64(np.float32(0.01)) - np.float64(np.float32(0.04)))
+    np.testing.assert_allclose(z, lift, rtol=0, atol=1e-15)
+    assert np.all(np.abs(x) <= 0.65) and np.all(np.abs(y) <= 0.25)
+
+
+def _random_tiny(rng, n_obj, n_box, S=3, ncand=6, n_scenes=2, rot=True, box_h=(0.03, 0.15)):
+    objs = []
+    for _ in range(n_obj):
+        L = rng.uniform(0.05, 0.2)
+        c = rng.uniform(-L / 2, L / 2, (S, 3))
+        r = rng.uniform(0.01, 0.05, (S, 1))
+        objs.append(np.concatenate([c, r], 1))
+    R_sup = _rot(rng.uniform(0, 6.3)) if rot else np.eye(3)
+    t_sup = rng.uniform(-1, 1, 3) if rot else np.zeros(3)
+    boxes = []
+    for _ in range(n_box):
+        Rl = _rot(rng.uniform(0, 6.3))
+        h = rng.uniform(box_h[0], box_h[1], 3)
+        cl = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-0.2, 0.2), h[2]])
+        boxes.append((R_sup @ Rl, R_sup @ cl + t_sup, h))
+    return tiny_batch(objs, boxes, hx=0.35, hy=0.25, sup_R=R_sup, sup_t=t_sup, ncand=ncand,
+                      n_scenes=n_scenes)
+
+
+def test_check_matches_bruteforce(orc):
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        b = _random_tiny(rng, 3, 2)
+        # place the first two objects at arbitrary poses, check the third
+        placed = np.full((b.n_spheres, 4), np.nan)
+        for s in range(b.n_scenes):
+            for o in range(b.obj_off[s], b.obj_off[s] + 2):
+                pose = (rng.uniform(-0.3, 0.3), rng.uniform(-0.2, 0.2), 0.05, rng.uniform(0, 6))
+                tm = b.tmpl[b.sph_off[o]:b.sph_off[o + 1]].astype(np.float64)
+                placed[b.sph_off[o]:b.sph_off[o + 1]] = bf.world_spheres(tm, b.sup[b.obj_sup[o]].astype(np.float64), pose)
+        poses = sg.random_poses(rng, 10, 0.35, 0.25, z=(0.0, 0.2))
+        obj_idx = [b.obj_off[s] + 2 for s in range(b.n_scenes)]
+        cand_off = [0, 5, 10]
+        clr = orc.check(b, obj_idx, cand_off, [2, 2], placed, poses)
+        for s in range(b.n_scenes):
+            o = obj_idx[s]
+            tm = b.tmpl[b.sph_off[o]:b.sph_off[o + 1]].astype(np.float64)
+            first = b.sph_off[b.obj_off[s]]
+            for t in range(cand_off[s], cand_off[s + 1]):
+                sph = bf.world_spheres(tm, b.sup[b.obj_sup[o]].astype(np.float64),
+                                       [float(a[t]) for a in poses])
+                want = bf.clearance(sph, b.box[b.box_off[s]:b.box_off[s + 1]].astype(np.float64),
+                                    placed[first:b.sph_off[o]])
+                assert clr[t] == pytest.approx(want, abs=1e-12)
+
+
+def test_generate_matches_bruteforce(orc):
+    rng = np.random.default_rng(6)
+    n_ok = n_bad = 0
+    for trial in range(12):
+        b = _random_tiny(rng, 4, int(rng.integers(0, 6)), S=int(rng.integers(1, 5)),
+                         ncand=int(rng.integers(1, 9)), box_h=(0.05, 0.3))
+        seed = int(rng.integers(0, 2 ** 63))
+        out = orc.generate(b, seed=seed, retries=3)
+        ref = bf.generate(b, seed, retries=3)
+        for s, (status, picks) in enumerate(ref):
+            assert int(out["status"][s]) == status
+            objs = range(b.obj_off[s], b.obj_off[s] + len(picks))
+            got = [(int(out["rec_attempt"][o]), int(out["rec_idx"][o])) for o in objs]
+            assert got == picks
+            n_ok += status == 1
+            n_bad += status == 2
+    assert n_ok > 0 and n_bad > 0
+
+
+def test_generate_subset_keeps_scene_counters(orc):
+    b = sg.batched_scenes(n_scenes=6, seed=3)
+    full = orc.generate(b, seed=11, max_steps=3)
+    sub, ids = sg.subset(b, [4, 1])
+    part = orc.generate(sub, seed=11, max_steps=3, scene_id=ids)
+    for j, s in enumerate([4, 1]):
+        assert part["status"][j] == full["status"][s]
+        o_full = range(b.obj_off[s], b.obj_off[s] + 3)
+        o_sub = range(sub.obj_off[j], sub.obj_off[j] + 3)
+        assert [full["rec_idx"][o] for o in o_full] == [part["rec_idx"][o] for o in o_sub]
+
+
+def test_exact_rational_flags(orc):
+    """Spheres at rational positions with yaw = 0: the margin test decided with
+    exact rational arithmetic equals the oracle's decision."""
+    rng = np.random.default_rng(7)
+    m = Fraction(1, 200)
+    agree = 0
+    for _ in range(300):
+        cq = [Fraction(int(rng.integers(-40, 41)), 400) for _ in range(2)]
+        rq = Fraction(int(rng.integers(4, 20)), 400)
+        q = [Fraction(int(rng.integers(-40, 41)), 400) for _ in range(2)]
+        r = Fraction(int(rng.integers(4, 20)), 400)
+        # object 0 (one sphere at its origin) placed with its sphere at (q, r);
+        # object 1 one sphere at (cq) offset, checked at pose (0, 0, lift, 0)
+        b = tiny_batch([[[0, 0, 0, float(r)]], [[float(cq[0]), float(cq[1]), 0, float(rq)]]],
+                       hx=1, hy=1)
+        # radii are exact in binary32 only if representable; use the binary32 values
+        r32, rq32 = Fraction(float(np.float32(r))), Fraction(float(np.float32(rq)))
+        cx, cy = Fraction(float(np.float32(cq[0]))), Fraction(float(np.float32(cq[1])))
+        qx, qy = Fraction(float(q[0])), Fraction(float(q[1]))
+        placed = np.array([[float(qx), float(qy), float(r32), float(r32)], [np.nan] * 4])
+        clr = orc.check(b, [1], [0, 1], [1], placed, ([0.0], [0.0], [float(rq32)], [0.0]))[0]
+        dx, dy, dz = cx - qx, cy - qy, rq32 - r32
+        d2 = dx * dx + dy * dy + dz * dz
+        thr = (r32 + rq32 + m) ** 2
+        if abs(float(d2 - thr)) < 1e-9:
+            continue
+        assert (clr < 0.005) == (d2 < thr)
+        agree += 1
+    assert agree > 250
+
+
+def test_rigid_motion_of_whole_scene_keeps_decisions(orc):
+    rng = np.random.default_rng(8)
+    b0 = _random_tiny(rng, 4, 3, S=4, ncand=8, n_scenes=3, rot=False)
+    out0 = orc.generate(b0, seed=99)
+    R = _rot(1.1, 0.0, 0.0)
+    t = np.array([0.7, -0.4, 0.9])
+    b1 = sg.SceneBatch(**{k: getattr(b0, k) for k in
+                          ("obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "box_off")},
+                       sup=b0.sup.copy(), box=b0.box.copy())
+    b1.sup[:, 0:9] = (R @ b0.sup[:, 0:9].astype(np.float64).reshape(-1, 3, 3)).reshape(-1, 9)
+    b1.sup[:, 9:12] = b0.sup[:, 9:12].astype(np.float64) @ R.T + t
+    b1.box[:, 0:9] = (R @ b0.box[:, 0:9].astype(np.float64).reshape(-1, 3, 3)).reshape(-1, 9)
+    b1.box[:, 9:12] = b0.box[:, 9:12].astype(np.float64) @ R.T + t
+    out1 = orc.generate(b1, seed=99)
+    clear = out0["rec_banded"] == 0
+    assert np.array_equal(out0["status"], out1["status"])
+    assert np.array_equal(out0["rec_idx"][clear], out1["rec_idx"][clear])
+    ok = ~np.isnan(out0["rec_clear"])
+    np.testing.assert_allclose(out0["rec_clear"][ok], out1["rec_clear"][ok], atol=1e-6)
+
+
+def test_permuting_boxes_keeps_results(orc):
+    rng = np.random.default_rng(9)
+    b = _random_tiny(rng, 3, 4, S=3, ncand=8, n_scenes=2)
+    out = orc.generate(b, seed=3)
+    perm = np.concatenate([b.box_off[s] + rng.permutation(b.box_off[s + 1] - b.box_off[s])
+                           for s in range(b.n_scenes)])
+    b.box = b.box[perm]
+    out2 = orc.generate(b, seed=3)
+    assert np.array_equal(out["rec_idx"], out2["rec_idx"])
+    np.testing.assert_array_equal(out["rec_clear"], out2["rec_clear"])
+
+
+def test_infeasible_scene_is_invalid_after_all_attempts(orc):
+    # a box swallowing the whole support: every candidate collides
+    b = tiny_batch([[[0, 0, 0, 0.02]], [[0, 0, 0, 0.02]]],
+                   boxes=[(np.eye(3), (0, 0, 0.5), (2.0, 2.0, 0.5))], ncand=7)
+    out = orc.generate(b, seed=1, retries=10)
+    assert out["status"].tolist() == [2]
+    assert out["n_placed"].tolist() == [0]
+    assert out["n_cand"].tolist() == [11 * 7]
+    assert out["rec_idx"].tolist() == [-1, -1]
+
+
+def test_band_flags_candidates_at_the_threshold(orc):
+    # one placed sphere; candidate sphere at clearance = margin + 2e-6 -> banded
+    b = tiny_batch([[[0, 0, 0, 0.05]], [[0, 0, 0, 0.05]]], hx=1e-6, hy=1e-6, ncand=1)
+    D = 0.1 + 0.005 + 2e-6
+    placed = np.array([[D, 0.0, 0.05, 0.05], [np.nan] * 4])
+    clr = orc.check(b, [1], [0, 1], [1], placed, ([0.0], [0.0], [0.05], [0.0]))
+    assert abs(clr[0] - 0.005) < 1e-5
+
+
+def test_grid_sampler_nodes_and_affine_fields(orc):
+    rng = np.random.default_rng(10)
+    nz, ny, nx = 5, 6, 7
+    h = 0.1
+    origin = np.array([-0.2, 0.1, 0.3])
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    # node values reproduced exactly
+    vals = rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    for _ in range(20):
+        # nodes off the upper faces (there the scaled coordinate can round past
+        # the last node and the point counts as outside)
+        i, j, k = rng.integers(0, nx - 1), rng.integers(0, ny - 1), rng.integers(0, nz - 1)
+        p = origin + h * np.array([i, j, k])
+        assert orc.grid_sample(vals, origin, h, p) == pytest.approx(float(vals[k, j, i]), abs=1e-6)
+    # affine field: trilinear interpolation is exact
+    a = np.array([0.25, -0.5, 1.0])
+    aff = (origin[0] + h * xx) * a[0] + (origin[1] + h * yy) * a[1] + (origin[2] + h * zz) * a[2] - 0.125
+    for _ in range(50):
+        p = origin + h * rng.uniform(0, [nx - 1, ny - 1, nz - 1])
+        want = float(a @ p - 0.125)
+        assert orc.grid_sample(aff.astype(np.float64), origin, h, p) == pytest.approx(want, abs=2e-6)
+    # outside the node box: nothing there
+    assert math.isinf(orc.grid_sample(vals, origin, h, origin - 0.01))
