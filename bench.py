@@ -1,0 +1,136 @@
+"""Benchmark: batched scene generation on one MI355X.
+
+One step = one whole generation pass (sample -> exact check -> first-valid
+selection -> commit -> retries) over every scene of the workload, inputs
+already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched-4096]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 operation counts per unit of work (flag-mode tests):
+#   sphere-sphere pair : 3 sub + 5 (squared distance) + 2 (threshold) + 1 cmp = 11
+#   sphere-box pair    : 3 sub + 15 (box-frame rotation) + 3 (|q|-h) + 3 (max 0)
+#                        + 5 (squared norm) + 1 cmp = 30
+#   sphere transform   : 4 + 4 + 1 (yaw + position) + 18 (support pose) = 27
+FLOP_PAIR, FLOP_BOX, FLOP_XFORM = 11, 30, 27
+PEAK_FP32_VALU_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FP32 FLOP/clk (published MI355X figure)
+
+WORKLOADS = {
+    "batched-4096": dict(desc="4096 scenes; 2.0x1.0 m support at a random world pose; 20 objects "
+                              "x 64 spheres (r~U[0.01,0.05] m, centres in a cube of side "
+                              "U[0.05,0.25] m); 1024 candidates per attempt; 16 oriented cuboids "
+                              "(half extents U[0.05,0.5] m, random yaw); margin 5 mm; 10 retries",
+                         make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                      fromlist=["x"]).batched_scenes(4096, seed=seed),
+                         ncand=1024, cpu_scenes=48),
+    "table-1": dict(desc="1 scene; 1.2x0.8 m table; 8 objects x 32 spheres; 256 candidates; "
+                         "4 cuboids; margin 5 mm; 10 retries",
+                    make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                 fromlist=["x"]).table_scene(seed=seed),
+                    ncand=256, cpu_scenes=1),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched-4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(scenes would shard across GPUs with no exchange; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_16896_amd import scn
+
+    W = WORKLOADS[args.workload]
+    b = W["make"](args.seed)
+    torch.cuda.set_device(0)
+    ctx = scn.Context(0)
+    db = scn.DeviceBatch(b, "cuda:0")
+    stream = torch.cuda.current_stream()
+    gen = lambda step: scn.generate_scenes(
+        ctx, db, scn.GenArgs(seed=1000 + step, default_ncand=W["ncand"], schedule=args.schedule))
+
+    for i in range(args.warmup):
+        gen(-1 - i)
+    torch.cuda.synchronize()
+    ctx.reset_counters()
+    valid = 0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        gen(k)
+        ev[k][1].record(stream)
+        valid += db.status.eq(scn.VALID).sum()     # stays on the device
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    valid = int(valid.item())
+    cnt = ctx.read_counters()
+    wall = t1 - t0
+    launch_ms = float(np.mean([a.elapsed_time(z) for a, z in ev]))
+    steps = args.steps
+    flop_per_launch = (FLOP_PAIR * cnt["sphere_pairs"] + FLOP_BOX * cnt["box_pairs"] +
+                       FLOP_XFORM * cnt["transforms"]) / steps
+    achieved_tflops = flop_per_launch / (launch_ms * 1e-3) / 1e12
+    n = b.n_scenes
+    out = {
+        "metric": "valid scenes/sec + candidate-pose checks/sec (plain vs learned proposal)",
+        "value": valid / wall,
+        "unit": "valid scenes/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {W['desc']}", "scenes": n,
+                   "objects": int(b.n_objects), "method": "plain (uniform candidates)"},
+        "valid_fraction": valid / (n * steps),
+        "candidate_checks_per_s": cnt["candidates"] / wall,
+        "counters_per_step": {k: v / steps for k, v in cnt.items() if k != "error_word"},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": None, "kernel": "k_place (fused place kernel)",
+                     "kernel_ms": launch_ms},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from paper_2512_16896_amd import scenegen as sg
+        k = min(W["cpu_scenes"], n)
+        pick = np.arange(k)
+        sub, ids = sg.subset(b, pick)
+        oracle.build(force=False)
+        threads = oracle.max_threads()
+        tc = time.perf_counter()
+        ref = oracle.generate(sub, seed=1000, default_ncand=W["ncand"], scene_id=ids)
+        tc = time.perf_counter() - tc
+        v = int(np.sum(ref["status"] == 1))
+        out["cpu_baseline"] = {"value": v / tc, "unit": "valid scenes/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"scenes 0..{k - 1} of the same workload, seed 1000, "
+                                         f"{tc:.1f} s, {v} valid"}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * scn.h -- C ABI of libscn.so: batched candidate-pose sampling, exact
+ * collision checking and first-valid placement for procedural scene
+ * generation on one MI355X (gfx950).
+ *
+ * The method is the batched rejection-sampling placement of Sceniris
+ * (arXiv 2512.16896): for every object of every scene, sample candidate poses
+ * on the object's support surface (Sec. III "Position sampling"; Sec. IV-C),
+ * check them for collision against the static scene and the objects already
+ * placed (Sec. IV-D), keep one collision-free pose, retry the scenes that found
+ * none (Sec. IV-D), and mark a scene invalid once an object has used up its
+ * retries (Sec. V-A: 10 retries).  Objects are sphere sets; static furniture is
+ * oriented boxes and, optionally, voxel signed-distance grids.
+ *
+ * Conventions for every call
+ *   - C linkage, returns an int status: SCN_OK (0) or a negative SCN_E_* code.
+ *     Nothing throws across the ABI.  scn_last_error() gives a detail string
+ *     (thread-local) for the last failing call on this thread.
+ *   - Pointers named in scn_batch, scn_poses and the array arguments are
+ *     DEVICE pointers to caller-owned memory (e.g. torch tensors).  The library
+ *     never frees or reallocates them.  Host pointers are marked "host".
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
+ *     NULL = the null stream) unless the description says they synchronize.
+ *   - Argument and shape errors are found on the host before any launch
+ *     (SCN_E_INVALID_ARG).  Errors only the device can see (a scene larger than
+ *     the capacity the call was planned for) are recorded in a device error word
+ *     and returned by the next synchronizing call (scn_read_counters) as
+ *     SCN_E_CAPACITY.
+ *   - A context is used by one host thread at a time.
+ *   - FP32 data; metres and radians.  All arrays are row-major.
+ */
+#ifndef SCN_H
+#define SCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SCN_OK = 0,
+    SCN_E_INVALID_ARG = -1, /* bad pointer, size or shape; nothing was launched */
+    SCN_E_HIP = -2,         /* a HIP runtime call failed; see scn_last_error()  */
+    SCN_E_CAPACITY = -3,    /* a scene exceeded the planned on-chip capacity    */
+    SCN_E_NO_DEVICE = -4,   /* no usable gfx950 device                          */
+    SCN_E_UNSUPPORTED = -5  /* a size outside what the kernels support          */
+};
+
+/* Scene status values (scn_batch.status). */
+enum { SCN_SCENE_ACTIVE = 0, SCN_SCENE_VALID = 1, SCN_SCENE_INVALID = 2 };
+
+typedef struct scn_ctx scn_ctx;
+typedef void *scn_stream; /* hipStream_t */
+
+/* Record of a placed object: pose in its support frame and which candidate
+ * won.  attempt = idx = -1 when the object was not placed. 24 bytes.        */
+typedef struct {
+    float x, y, z, yaw;
+    int32_t attempt, idx;
+} scn_pose_rec;
+
+/*
+ * A batch of scenes (Sec. IV-B: one pose per object per scene instance).
+ *
+ * Read-only inputs (device):
+ *   obj_off   [n_scenes+1]   objects of scene s are obj_off[s]..obj_off[s+1]-1,
+ *                            in placement order (Sec. IV-A)
+ *   sph_off   [n_objects+1]  template spheres of object o
+ *   tmpl      [n_spheres][4] sphere (x,y,z,r) in the object frame
+ *   obj_sup   [n_objects]    support surface of object o (index into sup)
+ *   obj_ncand [n_objects]    candidates per attempt for object o; NULL = use
+ *                            scn_gen_args.default_ncand
+ *   sup       [n_supports][16]  R[9] (support->world, row-major), t[3],
+ *                            half-x, half-y, inset, lift.  Candidates are drawn
+ *                            uniformly on the rectangle [-(hx-inset), hx-inset] x
+ *                            [-(hy-inset), hy-inset] of the support plane (the
+ *                            canonical polygon moved by the support's world pose,
+ *                            Sec. IV-C; inset = the ratio_on_support erosion of
+ *                            Sec. IV-F expressed in metres), yaw ~ U[0, 2pi),
+ *                            z = lift + the height that rests the lowest sphere
+ *                            on the plane (Sec. III "Position sampling").
+ *   box_off   [n_scenes+1]   static boxes of scene s
+ *   box       [n_boxes][16]  R[9] (box->world), centre[3], half extents[3], pad
+ *   grid_off  [n_scenes+1]   voxel-grid instances of scene s (NULL: no grids)
+ *   grid      [n_grids][24]  world->grid rotation W[9], translation tw[3],
+ *                            origin[3], spacing h, nodes nx,ny,nz (as floats), pad[2]
+ *   grid_src  [n_grids]      asset index of the instance
+ *   grid_val_off [n_assets+1] (int64) offsets of each asset's node values in grid_val
+ *   grid_val  node values, x fastest (value at origin + h*(i,j,k))
+ * Mutable state (device):
+ *   placed    [n_spheres][4] world spheres of placed objects, parallel to tmpl
+ *   n_placed  [n_scenes]     objects placed so far (always a prefix)
+ *   status    [n_scenes]     SCN_SCENE_*
+ *   rec       [n_objects]    pose records
+ * Host-side planning sizes (maxima over the batch; a scene beyond them is
+ * reported as SCN_E_CAPACITY and left untouched):
+ *   max_objects_per_scene, max_spheres_per_object, max_spheres_per_scene,
+ *   max_boxes_per_scene, max_grids_per_scene, max_cand_per_object
+ */
+typedef struct scn_batch {
+    int32_t n_scenes, n_objects, n_spheres, n_supports, n_boxes, n_grids, n_grid_assets;
+    int32_t max_objects_per_scene, max_spheres_per_object, max_spheres_per_scene;
+    int32_t max_boxes_per_scene, max_grids_per_scene, max_cand_per_object;
+    const int32_t *obj_off;
+    const int32_t *sph_off;
+    const float *tmpl;
+    const int32_t *obj_sup;
+    const int32_t *obj_ncand;
+    const float *sup;
+    const int32_t *box_off;
+    const float *box;
+    const int32_t *grid_off;
+    const float *grid;
+    const int32_t *grid_src;
+    const int64_t *grid_val_off;
+    const float *grid_val;
+    float *placed;
+    int32_t *n_placed;
+    int8_t *status;
+    scn_pose_rec *rec;
+} scn_batch;
+
+/* Candidate poses in the support frame, structure of arrays (device). */
+typedef struct {
+    float *x, *y, *z, *yaw;
+} scn_poses;
+
+typedef struct {
+    uint64_t seed;         /* key of the counter-based generator                  */
+    float margin;          /* a candidate collides iff its clearance < margin      */
+    int32_t retries;       /* attempts per object = retries + 1 (paper: 10)        */
+    int32_t default_ncand; /* candidates per attempt when obj_ncand is NULL        */
+    int32_t max_steps;     /* scn_generate_scenes: objects per scene (<= 0: all)    */
+    int32_t schedule;      /* 0: autotuned / default; >0: explicit schedule id      */
+    int32_t use_graph;     /* scn_generate_scenes: replay a captured hipGraph       */
+    int32_t reserved[4];   /* zero                                                  */
+} scn_gen_args;
+
+/* Work counters accumulated on the device since the last scn_reset_counters. */
+typedef struct {
+    int64_t candidates;    /* candidate poses brought to a decision               */
+    int64_t sphere_pairs;  /* sphere-sphere tests evaluated                        */
+    int64_t box_pairs;     /* sphere-box tests evaluated                           */
+    int64_t grid_samples;  /* sphere-grid trilinear samples evaluated             */
+    int64_t attempts;      /* (scene, object, attempt) triples started            */
+    int64_t placed;        /* objects placed                                       */
+    int64_t error_word;    /* device-detected errors (bit 0: capacity)           */
+    int64_t transforms;    /* candidate spheres moved to the world frame          */
+    int64_t reserved[8];
+} scn_counters;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (must be gfx950).  Allocates a few
+ * KB of device memory for counters.  *out owned by the caller; free with
+ * scn_ctx_destroy.                                                          */
+int scn_ctx_create(scn_ctx **out, int device);
+int scn_ctx_destroy(scn_ctx *ctx);
+const char *scn_status_string(int status);
+const char *scn_last_error(void);
+
+/* Zero the device counters (asynchronous, graph-safe fill kernel).          */
+int scn_reset_counters(scn_ctx *ctx, scn_stream stream);
+/* Synchronize `stream` and copy the counters to *out (host).  Returns
+ * SCN_E_CAPACITY if the device error word is set.                          */
+int scn_read_counters(scn_ctx *ctx, scn_counters *out, scn_stream stream);
+
+/* ---- the hot path ------------------------------------------------------ */
+
+/* Sample the candidate poses of one attempt (Sec. III "Position sampling",
+ * Sec. IV-C).  obj_idx[s] (device, int32) is the object of scene s to sample
+ * for (-1: none); cand_off[n_scenes+1] (device) gives where scene s's
+ * candidates go in `out`; total = cand_off[n_scenes] (host).  Candidate i of
+ * attempt `attempt` for the object at position j = obj_idx[s] - obj_off[s] of
+ * scene s uses Philox4x32-10(key = seed, counter = (i, attempt, j, s)). */
+int scn_sample_poses(scn_ctx *ctx, const scn_batch *b, const int32_t *obj_idx,
+                     const int32_t *cand_off, int32_t total, int32_t max_cand_per_scene,
+                     uint64_t seed, int32_t attempt, scn_poses out, scn_stream stream);
+
+/* Dense exact check (Sec. IV-D) of given candidate poses of object obj_idx[s]
+ * against scene s's boxes, grids and its first n_placed[s] objects (their
+ * world spheres in b->placed).  clearance[t] (nullable) = min over the
+ * candidate's spheres and all obstacles of (signed distance - radii);
+ * +inf without obstacles.  collide[t] (nullable, uint8) = clearance < margin.
+ * Every pair is evaluated (no culling, no early exit).                      */
+int scn_check_batch(scn_ctx *ctx, const scn_batch *b, const int32_t *obj_idx,
+                    const int32_t *cand_off, int32_t total, int32_t max_cand_per_scene,
+                    scn_poses poses, float margin, float *clearance, uint8_t *collide,
+                    scn_stream stream);
+
+/* Set every scene to ACTIVE with nothing placed (graph-safe fill kernel).   */
+int scn_reset_scenes(scn_ctx *ctx, scn_batch *b, scn_stream stream);
+
+/* One placement step (Sec. IV-A): every ACTIVE scene places its next object
+ * n_placed[s]: attempts 0..retries, each with fresh candidates; the winner is
+ * the lowest-index collision-free candidate of the first attempt that has
+ * one; its world spheres are appended to b->placed and its record to b->rec.
+ * A scene whose object finds none becomes INVALID; a scene whose last object
+ * is placed becomes VALID.  chosen[s] (device, nullable) = winning index, -1
+ * if the object failed, -2 if the scene was not active.                     */
+int scn_place_step(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args, int32_t *chosen,
+                   scn_stream stream);
+
+/* The whole batch (Sec. IV-A, Fig. 2 "generates a batch of scenes"): resets
+ * the scenes and places every object of every scene in one persistent fused
+ * launch (sampling, checking, selection, commit and retries on the device,
+ * no host round trip).  Equivalent to scn_reset_scenes followed by
+ * scn_place_step until no scene is ACTIVE.                                 */
+int scn_generate_scenes(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
+                        scn_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCN_H */

@@ -1,0 +1,157 @@
+// device.h -- device-side building blocks shared by the libscn kernels:
+// counter-based random numbers, candidate poses, sphere-set transforms and the
+// sphere-vs-box / sphere-vs-sphere / sphere-vs-grid tests.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scn {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the 4x32
+// S-box; multipliers 0xD2511F53 / 0xCD9E8D57, key schedule bumped by the
+// Weyl constants 0x9E3779B9 / 0xBB67AE85 between rounds.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t a, b, c, d; };
+
+__device__ __forceinline__ U4 philox10(U4 x, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * x.a, hi0 = __umulhi(0xD2511F53u, x.a);
+        const uint32_t lo1 = 0xCD9E8D57u * x.c, hi1 = __umulhi(0xCD9E8D57u, x.c);
+        x = U4{hi1 ^ x.b ^ k0, lo1, hi0 ^ x.d ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return x;
+}
+
+// (w >> 9) + 1/2 scaled by 2^-23: a uniform in (0,1), exact in binary32.
+// Returned as the signed unit 2u - 1 in (-1, 1), also exact.
+__device__ __forceinline__ float signed_unit(uint32_t w) {
+    return fmaf((float)(w >> 9), 2.0f / 8388608.0f, 1.0f / 8388608.0f - 1.0f);
+}
+__device__ __forceinline__ float unit01(uint32_t w) {
+    return ((float)(w >> 9) + 0.5f) * (1.0f / 8388608.0f);
+}
+
+// Support surface row (16 floats): R[9] support->world, t[3], hx, hy, inset, lift.
+struct Support {
+    float R[9], t[3], hx, hy, inset, lift;
+};
+__device__ __forceinline__ Support load_support(const float* __restrict__ sup, int u) {
+    Support S;
+    const float* p = sup + 16 * u;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) S.R[i] = p[i];
+    S.t[0] = p[9]; S.t[1] = p[10]; S.t[2] = p[11];
+    S.hx = p[12]; S.hy = p[13]; S.inset = p[14]; S.lift = p[15];
+    return S;
+}
+
+// Candidate pose in the support frame: position and yaw (as cos/sin).
+struct Pose { float x, y, z, c, s, yaw; };
+
+// Candidate i of attempt a for the object at position j of scene s.
+__device__ __forceinline__ Pose sample_pose(uint64_t seed, uint32_t s, uint32_t j, uint32_t a,
+                                            uint32_t i, float ax, float ay, float z) {
+    U4 w = philox10(U4{i, a, j, s}, (uint32_t)seed, (uint32_t)(seed >> 32));
+    Pose p;
+    p.x = ax * signed_unit(w.a);
+    p.y = ay * signed_unit(w.b);
+    const float u2 = unit01(w.c);
+    p.yaw = 6.28318530717958647692f * u2;
+    sincospif(2.0f * u2, &p.s, &p.c);
+    p.z = z;
+    return p;
+}
+
+// Object-frame point -> world: R_u (Rz(yaw) c + (x,y,z)) + t_u.
+__device__ __forceinline__ void to_world(const Support& S, const Pose& P, float cx, float cy,
+                                         float cz, float& wx, float& wy, float& wz) {
+    const float lx = fmaf(P.c, cx, fmaf(-P.s, cy, P.x));
+    const float ly = fmaf(P.s, cx, fmaf(P.c, cy, P.y));
+    const float lz = cz + P.z;
+    wx = fmaf(S.R[0], lx, fmaf(S.R[1], ly, fmaf(S.R[2], lz, S.t[0])));
+    wy = fmaf(S.R[3], lx, fmaf(S.R[4], ly, fmaf(S.R[5], lz, S.t[1])));
+    wz = fmaf(S.R[6], lx, fmaf(S.R[7], ly, fmaf(S.R[8], lz, S.t[2])));
+}
+
+// Box row (16 floats): R[9] box->world, centre[3], half extents[3].
+// Box-local excess e = |R^T (p - c)| - h.
+__device__ __forceinline__ void box_excess(const float* B, float px, float py, float pz,
+                                           float& ex, float& ey, float& ez) {
+    const float dx = px - B[9], dy = py - B[10], dz = pz - B[11];
+    const float qx = fmaf(B[0], dx, fmaf(B[3], dy, B[6] * dz));
+    const float qy = fmaf(B[1], dx, fmaf(B[4], dy, B[7] * dz));
+    const float qz = fmaf(B[2], dx, fmaf(B[5], dy, B[8] * dz));
+    ex = fabsf(qx) - B[12];
+    ey = fabsf(qy) - B[13];
+    ez = fabsf(qz) - B[14];
+}
+
+// Exact signed distance to the box.
+__device__ __forceinline__ float box_sdf(const float* B, float px, float py, float pz) {
+    float ex, ey, ez;
+    box_excess(B, px, py, pz, ex, ey, ez);
+    const float ox = fmaxf(ex, 0.f), oy = fmaxf(ey, 0.f), oz = fmaxf(ez, 0.f);
+    const float out = __builtin_amdgcn_sqrtf(fmaf(ox, ox, fmaf(oy, oy, oz * oz)));
+    return out + fminf(fmaxf(ex, fmaxf(ey, ez)), 0.f);
+}
+
+// Squared outside distance |max(e,0)|^2: the sphere (radius r) comes closer
+// than margin to the box iff this is < (r + margin)^2 (inside gives 0).
+__device__ __forceinline__ float box_out2(const float* B, float px, float py, float pz) {
+    float ex, ey, ez;
+    box_excess(B, px, py, pz, ex, ey, ez);
+    const float ox = fmaxf(ex, 0.f), oy = fmaxf(ey, 0.f), oz = fmaxf(ez, 0.f);
+    return fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+}
+
+// Grid instance row (24 floats): W[9] world->grid, tw[3], origin[3], h, nx, ny, nz, pad.
+// Trilinear sample of node values at a world point; +inf outside the nodes.
+__device__ __forceinline__ float grid_sample(const float* G, const float* __restrict__ vals,
+                                             float px, float py, float pz) {
+    const float gx = fmaf(G[0], px, fmaf(G[1], py, fmaf(G[2], pz, G[9])));
+    const float gy = fmaf(G[3], px, fmaf(G[4], py, fmaf(G[5], pz, G[10])));
+    const float gz = fmaf(G[6], px, fmaf(G[7], py, fmaf(G[8], pz, G[11])));
+    const float inv_h = 1.0f / G[15];
+    const int nx = (int)G[16], ny = (int)G[17], nz = (int)G[18];
+    const float fx = (gx - G[12]) * inv_h, fy = (gy - G[13]) * inv_h, fz = (gz - G[14]) * inv_h;
+    if (!(fx >= 0.f && fy >= 0.f && fz >= 0.f && fx <= (float)(nx - 1) && fy <= (float)(ny - 1) &&
+          fz <= (float)(nz - 1)))
+        return __builtin_huge_valf();
+    const int ix = min((int)fx, nx - 2), iy = min((int)fy, ny - 2), iz = min((int)fz, nz - 2);
+    const float tx = fx - (float)ix, ty = fy - (float)iy, tz = fz - (float)iz;
+    const float* v = vals + ((size_t)iz * ny + iy) * nx + ix;
+    const size_t sy = nx, sz = (size_t)nx * ny;
+    const float c00 = fmaf(tx, v[1] - v[0], v[0]);
+    const float c10 = fmaf(tx, v[sy + 1] - v[sy], v[sy]);
+    const float c01 = fmaf(tx, v[sz + 1] - v[sz], v[sz]);
+    const float c11 = fmaf(tx, v[sz + sy + 1] - v[sz + sy], v[sz + sy]);
+    const float c0 = fmaf(ty, c10 - c00, c00);
+    const float c1 = fmaf(ty, c11 - c01, c01);
+    return fmaf(tz, c1 - c0, c0);
+}
+
+// Wave-wide reductions (64 lanes).
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+}  // namespace scn

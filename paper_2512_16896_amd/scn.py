@@ -1,0 +1,267 @@
+"""ctypes binding of libscn.so (include/scn.h).  Argument marshalling only.
+
+Every step of the hot path runs in the HIP kernels of libscn.so; this module
+turns torch tensors (device memory) and Python scalars into the C structs of
+the ABI.  If the library is missing the import fails loudly: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscn.so")
+
+SCN_OK = 0
+ACTIVE, VALID, INVALID = 0, 1, 2
+
+
+class ScnError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libscn error {code}: {msg}")
+        self.code = code
+
+
+class PoseRec(C.Structure):
+    _fields_ = [("x", C.c_float), ("y", C.c_float), ("z", C.c_float), ("yaw", C.c_float),
+                ("attempt", C.c_int32), ("idx", C.c_int32)]
+
+
+class _Batch(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in (
+        "n_scenes", "n_objects", "n_spheres", "n_supports", "n_boxes", "n_grids", "n_grid_assets",
+        "max_objects_per_scene", "max_spheres_per_object", "max_spheres_per_scene",
+        "max_boxes_per_scene", "max_grids_per_scene", "max_cand_per_object")] + \
+        [(n, C.c_void_p) for n in (
+            "obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
+            "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
+            "placed", "n_placed", "status", "rec")]
+
+
+class _Poses(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("yaw", C.c_void_p)]
+
+
+class _GenArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("margin", C.c_float), ("retries", C.c_int32),
+                ("default_ncand", C.c_int32), ("max_steps", C.c_int32),
+                ("schedule", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
+
+
+class Counters(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "candidates", "sphere_pairs", "box_pairs", "grid_samples", "attempts", "placed",
+        "error_word", "transforms")] + [("reserved", C.c_int64 * 8)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2512_16896_amd.build` (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, u64, f32 = C.c_void_p, C.c_int32, C.c_uint64, C.c_float
+    sigs = {
+        "scn_ctx_create": [C.POINTER(vp), C.c_int],
+        "scn_ctx_destroy": [vp],
+        "scn_reset_counters": [vp, vp],
+        "scn_read_counters": [vp, C.POINTER(Counters), vp],
+        "scn_sample_poses": [vp, C.POINTER(_Batch), vp, vp, i32, i32, u64, i32, _Poses, vp],
+        "scn_check_batch": [vp, C.POINTER(_Batch), vp, vp, i32, i32, _Poses, f32, vp, vp, vp],
+        "scn_reset_scenes": [vp, C.POINTER(_Batch), vp],
+        "scn_place_step": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp, vp],
+        "scn_generate_scenes": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.scn_last_error.restype = C.c_char_p
+    L.scn_status_string.restype = C.c_char_p
+    L.scn_status_string.argtypes = [C.c_int]
+    return L
+
+
+_lib = _load()
+
+# names of the C ABI entry points (what include/scn.h declares)
+EXPORTS = ("scn_ctx_create", "scn_ctx_destroy", "scn_status_string", "scn_last_error",
+           "scn_reset_counters", "scn_read_counters", "scn_sample_poses", "scn_check_batch",
+           "scn_reset_scenes", "scn_place_step", "scn_generate_scenes")
+
+
+def lib():
+    return _lib
+
+
+def _ok(code: int):
+    if code != SCN_OK:
+        raise ScnError(code, (_lib.scn_last_error() or b"").decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """An scn_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _ok(_lib.scn_ctx_create(C.byref(h), int(device)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _lib.scn_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset_counters(self, stream=None):
+        _ok(_lib.scn_reset_counters(self.h, _stream(stream)))
+
+    def read_counters(self, stream=None) -> dict:
+        c = Counters()
+        _ok(_lib.scn_read_counters(self.h, C.byref(c), _stream(stream)))
+        return c.as_dict()
+
+
+@dataclass
+class GenArgs:
+    seed: int = 0
+    margin: float = 0.005
+    retries: int = 10
+    default_ncand: int = 1024
+    max_steps: int = 0
+    schedule: int = 0
+    use_graph: int = 0
+
+    def c(self) -> _GenArgs:
+        a = _GenArgs()
+        a.seed, a.margin, a.retries = int(self.seed) & (2 ** 64 - 1), float(self.margin), int(self.retries)
+        a.default_ncand, a.max_steps = int(self.default_ncand), int(self.max_steps)
+        a.schedule, a.use_graph = int(self.schedule), int(self.use_graph)
+        return a
+
+
+class DeviceBatch:
+    """Device copies of a SceneBatch plus the mutable placement state."""
+
+    def __init__(self, b, device: str = "cuda"):
+        dev = torch.device(device)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+        self.host = b
+        self.obj_off = t(b.obj_off, torch.int32)
+        self.sph_off = t(b.sph_off, torch.int32)
+        self.tmpl = t(b.tmpl, torch.float32)
+        self.obj_sup = t(b.obj_sup, torch.int32)
+        self.obj_ncand = t(b.obj_ncand, torch.int32)
+        self.sup = t(b.sup, torch.float32)
+        self.box_off = t(b.box_off, torch.int32)
+        self.box = t(b.box.reshape(-1, 16), torch.float32) if b.n_boxes else \
+            torch.zeros((1, 16), dtype=torch.float32, device=dev)
+        self.grid_off = self.grid = self.grid_src = self.grid_val_off = self.grid_val = None
+        n_assets = 0
+        if b.grid_off is not None:
+            self.grid_off = t(b.grid_off, torch.int32)
+            self.grid = t(b.grid.reshape(-1, 24), torch.float32)
+            self.grid_src = t(b.grid_src, torch.int32)
+            vals = [np.ascontiguousarray(v, np.float32).ravel() for v in b.grid_vals]
+            off = np.zeros(len(vals) + 1, np.int64)
+            off[1:] = np.cumsum([v.size for v in vals])
+            self.grid_val_off = t(off, torch.int64)
+            self.grid_val = t(np.concatenate(vals), torch.float32)
+            n_assets = len(vals)
+        n, n_obj, n_sph = b.n_scenes, b.n_objects, b.n_spheres
+        self.placed = torch.full((max(n_sph, 1), 4), float("nan"), dtype=torch.float32, device=dev)
+        self.n_placed = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+        self.status = torch.zeros(max(n, 1), dtype=torch.int8, device=dev)
+        self.rec = torch.zeros((max(n_obj, 1), 6), dtype=torch.int32, device=dev)  # 24 B records
+        nobj = b.objects_per_scene()
+        self.c = _Batch()
+        c = self.c
+        c.n_scenes, c.n_objects, c.n_spheres = n, n_obj, n_sph
+        c.n_supports, c.n_boxes = int(b.sup.shape[0]), b.n_boxes
+        c.n_grids = 0 if b.grid is None else int(b.grid.shape[0])
+        c.n_grid_assets = n_assets
+        c.max_objects_per_scene = int(nobj.max()) if n else 0
+        c.max_spheres_per_object = int(b.spheres_per_object().max()) if n_obj else 0
+        c.max_spheres_per_scene = int(b.spheres_per_scene().max()) if n else 0
+        c.max_boxes_per_scene = int(b.boxes_per_scene().max()) if n else 0
+        c.max_grids_per_scene = int(np.diff(b.grid_off).max()) if b.grid_off is not None and n else 0
+        c.max_cand_per_object = int(b.obj_ncand.max()) if n_obj else 0
+        for name in ("obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
+                     "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
+                     "placed", "n_placed", "status", "rec"):
+            setattr(c, name, None if getattr(self, name) is None else getattr(self, name).data_ptr())
+
+    # -- views of the state ------------------------------------------------
+    def records(self):
+        r = self.rec.cpu()
+        f = r.view(torch.float32)[:, :4].numpy().copy()
+        i = r[:, 4:6].numpy().copy()
+        return f, i
+
+    @property
+    def max_cand(self) -> int:
+        return int(self.c.max_cand_per_object)
+
+
+# ---------------------------------------------------------------------------
+def sample_poses(ctx: Context, db: DeviceBatch, obj_idx: torch.Tensor, cand_off: torch.Tensor,
+                 total: int, max_cand: int, seed: int, attempt: int, stream=None):
+    out = [torch.empty(max(total, 1), dtype=torch.float32, device=obj_idx.device) for _ in range(4)]
+    p = _Poses(*[o.data_ptr() for o in out])
+    _ok(_lib.scn_sample_poses(ctx.h, C.byref(db.c), _ptr(obj_idx), _ptr(cand_off), int(total),
+                              int(max_cand), int(seed) & (2 ** 64 - 1), int(attempt), p,
+                              _stream(stream)))
+    return [o[:total] for o in out]
+
+
+def check_batch(ctx: Context, db: DeviceBatch, obj_idx: torch.Tensor, cand_off: torch.Tensor,
+                total: int, max_cand: int, poses, margin: float = 0.005, want_clearance=True,
+                want_collide=True, stream=None):
+    dev = obj_idx.device
+    clr = torch.empty(max(total, 1), dtype=torch.float32, device=dev) if want_clearance else None
+    col = torch.empty(max(total, 1), dtype=torch.uint8, device=dev) if want_collide else None
+    p = _Poses(*[q.data_ptr() for q in poses])
+    _ok(_lib.scn_check_batch(ctx.h, C.byref(db.c), _ptr(obj_idx), _ptr(cand_off), int(total),
+                             int(max_cand), p, float(margin), _ptr(clr), _ptr(col),
+                             _stream(stream)))
+    return (None if clr is None else clr[:total]), (None if col is None else col[:total])
+
+
+def reset_scenes(ctx: Context, db: DeviceBatch, stream=None):
+    _ok(_lib.scn_reset_scenes(ctx.h, C.byref(db.c), _stream(stream)))
+
+
+def place_step(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None) -> torch.Tensor:
+    chosen = torch.empty(max(db.c.n_scenes, 1), dtype=torch.int32, device=db.n_placed.device)
+    a = args.c()
+    _ok(_lib.scn_place_step(ctx.h, C.byref(db.c), C.byref(a), _ptr(chosen), _stream(stream)))
+    return chosen[:db.c.n_scenes]
+
+
+def generate_scenes(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None):
+    a = args.c()
+    _ok(_lib.scn_generate_scenes(ctx.h, C.byref(db.c), C.byref(a), _stream(stream)))

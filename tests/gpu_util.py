@@ -1,0 +1,83 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI and
+compare with the FP64 oracle under the parity rule.
+
+Parity rule (FP32 device vs FP64 oracle on identical FP32 inputs):
+  * clearance within CLR_TOL metres;
+  * collision flags identical unless the oracle's clearance lies within BAND
+    of the margin (such candidates are counted, not compared);
+  * per (scene, object) the chosen (attempt, index) is identical for every
+    object before the first one whose decision involved a banded candidate
+    (oracle flag); scene status identical for scenes without a banded step.
+"""
+import numpy as np
+
+CLR_TOL = 1e-5
+BAND = 1e-5
+MARGIN = 0.005
+
+
+def first_banded(out, b, s):
+    o0, o1 = b.obj_off[s], b.obj_off[s + 1]
+    idx = np.nonzero(out["rec_banded"][o0:o1])[0]
+    return int(idx[0]) if len(idx) else o1 - o0
+
+
+def compare_generation(b, ref, status, rec_i, rec_f):
+    """ref: oracle.generate output on batch b; status [n], rec_i [n_obj,2]
+    (attempt, idx) and rec_f [n_obj,4] (x, y, z, yaw): device results for the
+    same scenes and objects.  Returns (objects compared, scenes with a banded
+    decision)."""
+    n_cmp = n_band = 0
+    for s in range(b.n_scenes):
+        fb = first_banded(ref, b, s)
+        o0, nobj = b.obj_off[s], b.obj_off[s + 1] - b.obj_off[s]
+        if fb < nobj:
+            n_band += 1
+        for j in range(fb):
+            o = o0 + j
+            want = (int(ref["rec_attempt"][o]), int(ref["rec_idx"][o]))
+            got = (int(rec_i[o, 0]), int(rec_i[o, 1]))
+            assert got == want, f"scene {s} object {j}: device {got} oracle {want}"
+            if want[1] >= 0:
+                np.testing.assert_allclose(rec_f[o], ref["rec_pose"][o], atol=2e-6, rtol=0,
+                                           err_msg=f"scene {s} object {j} pose")
+            n_cmp += 1
+        if fb == nobj:
+            assert int(status[s]) == int(ref["status"][s]), f"scene {s} status"
+    return n_cmp, n_band
+
+
+def objects_of(b, scenes):
+    """Object indices of the given scenes of batch b, in subset order."""
+    return np.concatenate([np.arange(b.obj_off[s], b.obj_off[s + 1]) for s in scenes])
+
+
+def box_distance(B, p):
+    R = B[:9].reshape(3, 3).astype(np.float64)
+    loc = (p - B[9:12].astype(np.float64)) @ R
+    h = B[12:15].astype(np.float64)
+    closest = np.clip(loc, -h, h)
+    out = np.linalg.norm(loc - closest, axis=1)
+    inside = np.all(np.abs(loc) <= h, axis=1)
+    return np.where(inside, -np.min(h - np.abs(loc), axis=1), out)
+
+
+def audit_placements(b, placed, n_placed, margin=MARGIN, tol=CLR_TOL):
+    """Every placed object of every scene is at least margin - tol away from
+    the boxes and from every earlier placed object (property of the output)."""
+    worst = np.inf
+    for s in range(b.n_scenes):
+        o0 = b.obj_off[s]
+        boxes = b.box[b.box_off[s]:b.box_off[s + 1]]
+        for j in range(int(n_placed[s])):
+            o = o0 + j
+            sp = placed[b.sph_off[o]:b.sph_off[o + 1]].astype(np.float64)
+            assert np.all(np.isfinite(sp))
+            for B in boxes:
+                worst = min(worst, float(np.min(box_distance(B, sp[:, :3]) - sp[:, 3])))
+            prev = placed[b.sph_off[o0]:b.sph_off[o]].astype(np.float64)
+            if len(prev):
+                d = np.linalg.norm(sp[:, None, :3] - prev[None, :, :3], axis=2)
+                worst = min(worst, float(np.min(d - sp[:, None, 3] - prev[None, :, 3])))
+    assert worst >= margin - tol, worst
+    return worst
