@@ -22,7 +22,9 @@ sys.path.insert(0, ROOT)
 #   sphere-box pair    : 3 sub + 15 (box-frame rotation) + 3 (|q|-h) + 3 (max 0)
 #                        + 5 (squared norm) + 1 cmp = 30
 #   sphere transform   : 4 + 4 + 1 (yaw + position) + 18 (support pose) = 27
-FLOP_PAIR, FLOP_BOX, FLOP_XFORM = 11, 30, 27
+#   box pretest        : the sphere-box test applied to the bounding sphere = 30
+#   object pretest     : bounding sphere vs bounding sphere, like a pair = 11
+FLOP_PAIR, FLOP_BOX, FLOP_XFORM, FLOP_BOXCULL, FLOP_OBJCULL = 11, 30, 27, 30, 11
 PEAK_FP32_VALU_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FP32 FLOP/clk (published MI355X figure)
 
 WORKLOADS = {
@@ -38,6 +40,13 @@ WORKLOADS = {
                     make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                  fromlist=["x"]).table_scene(seed=seed),
                     ncand=256, cpu_scenes=1),
+    "uneven-16384": dict(desc="16384 uneven scenes in one autotuned persistent launch: objects "
+                              "U{5..60}, spheres per object U{16..256}, candidates per attempt "
+                              "U{512..4096}, cuboids U{4..32}; support 2.0x1.0 m scaled by "
+                              "sqrt(N/20); margin 5 mm; 10 retries",
+                         make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                      fromlist=["x"]).uneven_batch(16384, seed=seed),
+                         ncand=1024, cpu_scenes=24, tune=True),
 }
 
 
@@ -69,11 +78,13 @@ def main():
     gen = lambda step: scn.generate_scenes(
         ctx, db, scn.GenArgs(seed=1000 + step, default_ncand=W["ncand"], schedule=args.schedule))
 
+    tuned = None
+    if W.get("tune") and args.schedule == 0:
+        tuned = ctx.autotune(db, scn.GenArgs(seed=999, default_ncand=W["ncand"]))
     for i in range(args.warmup):
         gen(-1 - i)
     torch.cuda.synchronize()
     ctx.reset_counters()
-    valid = 0
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -82,16 +93,16 @@ def main():
         ev[k][0].record(stream)
         gen(k)
         ev[k][1].record(stream)
-        valid += db.status.eq(scn.VALID).sum()     # stays on the device
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    valid = int(valid.item())
-    cnt = ctx.read_counters()
+    cnt = ctx.read_counters()     # the place kernel counts the scenes it finished
+    valid = cnt["valid_scenes"]
     wall = t1 - t0
     launch_ms = float(np.mean([a.elapsed_time(z) for a, z in ev]))
     steps = args.steps
     flop_per_launch = (FLOP_PAIR * cnt["sphere_pairs"] + FLOP_BOX * cnt["box_pairs"] +
-                       FLOP_XFORM * cnt["transforms"]) / steps
+                       FLOP_XFORM * cnt["transforms"] + FLOP_BOXCULL * cnt["box_culls"] +
+                       FLOP_OBJCULL * (cnt["object_culls"] + cnt["sphere_culls"])) / steps
     achieved_tflops = flop_per_launch / (launch_ms * 1e-3) / 1e12
     n = b.n_scenes
     out = {
@@ -104,6 +115,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W['desc']}", "scenes": n,
                    "objects": int(b.n_objects), "method": "plain (uniform candidates)"},
+        "schedule": (f"autotuned 0x{tuned[0]:x}" if tuned else
+                     (f"0x{args.schedule:x}" if args.schedule else "default")),
         "valid_fraction": valid / (n * steps),
         "candidate_checks_per_s": cnt["candidates"] / wall,
         "counters_per_step": {k: v / steps for k, v in cnt.items() if k != "error_word"},

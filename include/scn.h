@@ -148,7 +148,12 @@ typedef struct {
     int64_t placed;        /* objects placed                                       */
     int64_t error_word;    /* device-detected errors (bit 0: capacity)           */
     int64_t transforms;    /* candidate spheres moved to the world frame          */
-    int64_t reserved[8];
+    int64_t box_culls;     /* bounding-sphere vs box pretests                      */
+    int64_t object_culls;  /* bounding-sphere vs placed-object pretests            */
+    int64_t valid_scenes;  /* scenes that became VALID                             */
+    int64_t invalid_scenes;/* scenes that became INVALID                           */
+    int64_t sphere_culls;  /* bounding-sphere vs placed-sphere pretests            */
+    int64_t reserved[3];
 } scn_counters;
 
 /* ---- context ---------------------------------------------------------- */
@@ -210,6 +215,41 @@ int scn_place_step(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args, int32_t
  * scn_place_step until no scene is ACTIVE.                                 */
 int scn_generate_scenes(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
                         scn_stream stream);
+
+/* ---- uneven batching: autotuned schedules ------------------------------ */
+
+/* Schedule ids for scn_gen_args.schedule (0 = the context's tuned choice for
+ * this batch shape, or the default):
+ *   bits 0-4  waves per workgroup: candidates of one scene in flight
+ *             (1, 2, 4, 8 or 16)
+ *   bit  5    longest-first scene order (larger scenes start first)
+ *   bits 8-11 LDS budget for a scene's placed spheres: 0 = sized for the
+ *             largest scene (every scene LDS-resident); 1..5 = 32, 48, 64,
+ *             80, 96 KB (larger scenes read their placed spheres from global
+ *             memory in a second launch); 15 = every scene from global memory */
+enum {
+    SCN_SCHED_WAVES_MASK = 0x1F,
+    SCN_SCHED_LONGEST_FIRST = 0x20,
+    SCN_SCHED_LDS_SHIFT = 8,
+    SCN_SCHED_LDS_MASK = 0xF00,
+    SCN_SCHED_LDS_NONE = 0xF
+};
+
+/* Time every schedule of the fused place kernel on this batch (a full
+ * generation per schedule, after one warm-up run) and remember the fastest
+ * for batches of the same shape bucket (largest object, largest scene,
+ * objects per scene, number of scenes) in the context.  Synchronizes
+ * `stream`; leaves the batch state of the last run.  *best_schedule and
+ * *best_ms (host, nullable) receive the choice and its time.  This is the
+ * project's autotuner for the uneven-batch launch (one persistent fused
+ * launch whose best shape depends on the batch).                         */
+int scn_autotune(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args, int32_t *best_schedule,
+                 float *best_ms, scn_stream stream);
+
+/* Persist / restore the context's tuned choices as a small JSON file
+ * (host path).                                                            */
+int scn_autotune_save(scn_ctx *ctx, const char *path);
+int scn_autotune_load(scn_ctx *ctx, const char *path);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 
 #include "internal.h"
@@ -15,6 +16,11 @@ struct scn_ctx {
     int lds_per_block;
     int n_cu;
     int64_t* d_counters;   // scn::kNumCounters int64
+    int32_t* d_order;      // longest-first scene order workspace
+    int32_t* d_hist;       // its bucket counters
+    int order_cap;
+    struct Tuned { int schedule; float ms; };
+    std::map<std::string, Tuned> tuned;   // autotuned schedule per batch shape bucket
 };
 
 namespace {
@@ -121,6 +127,8 @@ int scn_ctx_destroy(scn_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(c->d_counters);
+    if (c->d_order) (void)hipFree(c->d_order);
+    if (c->d_hist) (void)hipFree(c->d_hist);
     delete c;
     return SCN_OK;
 }
@@ -146,6 +154,11 @@ int scn_read_counters(scn_ctx* c, scn_counters* out, scn_stream stream) {
     out->placed = h[scn::kPlaced];
     out->error_word = h[scn::kErrorWord];
     out->transforms = h[scn::kTransforms];
+    out->box_culls = h[scn::kBoxCulls];
+    out->object_culls = h[scn::kObjCulls];
+    out->valid_scenes = h[scn::kValidScenes];
+    out->invalid_scenes = h[scn::kInvalidScenes];
+    out->sphere_culls = h[scn::kSphCulls];
     if (out->error_word & scn::kErrCapacity)
         return fail(SCN_E_CAPACITY, "a scene exceeded the planned capacity and was skipped");
     return SCN_OK;
@@ -190,6 +203,25 @@ int scn_reset_scenes(scn_ctx* c, scn_batch* b, scn_stream stream) {
     return SCN_OK;
 }
 
+// Shape bucket of a batch for the autotuner: sphere slots per lane, then the
+// largest scene, objects per scene and scene count rounded up to powers of two.
+static int pow2_ceil(int v) {
+    int p = 1;
+    while (p < v && p < (1 << 30)) p <<= 1;
+    return p;
+}
+static std::string shape_key(const scn_batch* b) {
+    const int S = b->max_spheres_per_object;
+    const int spl = S <= 64 ? 1 : (S <= 128 ? 2 : 4);
+    char k[128];
+    snprintf(k, sizeof k, "spl%d_sph%d_obj%d_box%d_n%d", spl, pow2_ceil(b->max_spheres_per_scene),
+             pow2_ceil(b->max_objects_per_scene), pow2_ceil(b->max_boxes_per_scene),
+             pow2_ceil(b->n_scenes));
+    return k;
+}
+
+static const int kDefaultSchedule = 8;   // 8 waves, batch order, LDS sized for the largest scene
+
 static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int max_steps,
                       scn::PlacePlan* plan) {
     if (!a) return fail(SCN_E_INVALID_ARG, "null args");
@@ -200,20 +232,63 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
     const int S = b->max_spheres_per_object;
     if (S > 256) return fail(SCN_E_UNSUPPORTED, "max_spheres_per_object %d > 256", S);
     plan->spl = S <= 64 ? 1 : (S <= 128 ? 2 : 4);
-    plan->waves = 4;
-    if (a->schedule > 0) {
-        const int w = a->schedule & 0xF;
-        if (w != 1 && w != 2 && w != 4 && w != 8)
-            return fail(SCN_E_INVALID_ARG, "schedule waves must be 1, 2, 4 or 8");
-        plan->waves = w;
+    int sched = a->schedule;
+    if (sched == 0) {
+        auto it = c->tuned.find(shape_key(b));
+        sched = it != c->tuned.end() ? it->second.schedule : kDefaultSchedule;
+    }
+    if (sched & ~(SCN_SCHED_WAVES_MASK | SCN_SCHED_LONGEST_FIRST | SCN_SCHED_LDS_MASK))
+        return fail(SCN_E_INVALID_ARG, "unknown schedule bits 0x%x", sched);
+    const int w = sched & SCN_SCHED_WAVES_MASK;
+    if (w != 1 && w != 2 && w != 4 && w != 8 && w != 16)
+        return fail(SCN_E_INVALID_ARG, "schedule waves must be 1, 2, 4, 8 or 16");
+    plan->waves = w;
+    plan->order = nullptr;
+    if (sched & SCN_SCHED_LONGEST_FIRST) {
+        if (c->order_cap < b->n_scenes) {
+            if (c->d_order) (void)hipFree(c->d_order);
+            c->d_order = nullptr;
+            c->order_cap = 0;
+            SCN_HIP(hipMalloc((void**)&c->d_order, sizeof(int32_t) * (size_t)b->n_scenes));
+            c->order_cap = b->n_scenes;
+        }
+        if (!c->d_hist)
+            SCN_HIP(hipMalloc((void**)&c->d_hist, sizeof(int32_t) * (scn::kOrderBuckets + 1)));
+        plan->order = c->d_order;
     }
     plan->cap_sph = b->max_spheres_per_scene > 0 ? b->max_spheres_per_scene : 1;
     plan->cap_obj = b->max_objects_per_scene > 0 ? b->max_objects_per_scene : 1;
     plan->max_steps = max_steps;
-    const long long bytes = 16LL * plan->cap_sph + 16LL * plan->cap_obj;
-    if (bytes > c->lds_per_block)
-        return fail(SCN_E_UNSUPPORTED, "a scene needs %lld B of LDS (> %d)", bytes, c->lds_per_block);
-    plan->lds_bytes = (int)bytes;
+    if (16LL * plan->cap_obj + 16LL * 64 > c->lds_per_block)
+        return fail(SCN_E_UNSUPPORTED, "%d objects per scene do not fit the LDS", plan->cap_obj);
+    static const int kBudgetKB[] = {0, 32, 48, 64, 80, 96};
+    const int code = (sched & SCN_SCHED_LDS_MASK) >> SCN_SCHED_LDS_SHIFT;
+    const long long all_bytes = 16LL * plan->cap_sph + 16LL * plan->cap_obj;
+    if (code == SCN_SCHED_LDS_NONE) {
+        plan->mode = scn::kPlaceAllGlobal;
+        plan->split_sph = 0;
+    } else if (code <= 5) {
+        long long budget = code == 0 ? all_bytes : 1024LL * kBudgetKB[code];
+        if (budget > c->lds_per_block) budget = c->lds_per_block;
+        if (all_bytes <= budget) {
+            plan->mode = scn::kPlaceAllLds;
+            plan->split_sph = plan->cap_sph;
+        } else {
+            plan->mode = scn::kPlaceSplit;
+            plan->split_sph = (int)(budget / 16) - plan->cap_obj;
+            if (plan->split_sph < 1) plan->split_sph = 1;
+        }
+    } else {
+        return fail(SCN_E_INVALID_ARG, "unknown LDS budget code %d", code);
+    }
+    return SCN_OK;
+}
+
+static int run_place(scn_ctx* c, scn_batch* b, const scn_gen_args* a, const scn::PlacePlan& plan,
+                     int32_t* chosen, bool reset, hipStream_t st) {
+    if (reset) SCN_HIP(scn::launch_reset(*b, st));
+    if (plan.order) SCN_HIP(scn::launch_longest_first(*b, c->d_order, c->d_hist, st));
+    SCN_HIP(scn::launch_place(*b, *a, plan, chosen, c->d_counters, st));
     return SCN_OK;
 }
 
@@ -223,8 +298,7 @@ int scn_place_step(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int32_t* cho
     if (int r = check_batch(b, true)) return r;
     scn::PlacePlan plan;
     if (int r = plan_place(c, b, a, 1, &plan)) return r;
-    SCN_HIP(scn::launch_place(*b, *a, plan, chosen, c->d_counters, (hipStream_t)stream));
-    return SCN_OK;
+    return run_place(c, b, a, plan, chosen, false, (hipStream_t)stream);
 }
 
 int scn_generate_scenes(scn_ctx* c, scn_batch* b, const scn_gen_args* a, scn_stream stream) {
@@ -232,8 +306,89 @@ int scn_generate_scenes(scn_ctx* c, scn_batch* b, const scn_gen_args* a, scn_str
     if (int r = check_batch(b, true)) return r;
     scn::PlacePlan plan;
     if (int r = plan_place(c, b, a, a ? a->max_steps : 0, &plan)) return r;
-    SCN_HIP(scn::launch_reset(*b, (hipStream_t)stream));
-    SCN_HIP(scn::launch_place(*b, *a, plan, nullptr, c->d_counters, (hipStream_t)stream));
+    return run_place(c, b, a, plan, nullptr, true, (hipStream_t)stream);
+}
+
+int scn_autotune(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int32_t* best_schedule,
+                 float* best_ms, scn_stream stream) {
+    if (int r = check_ctx(c)) return r;
+    if (int r = check_batch(b, true)) return r;
+    if (!a) return fail(SCN_E_INVALID_ARG, "null args");
+    const hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    SCN_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SCN_E_HIP, "hipEventCreate failed");
+    }
+    // time one full generation under `sched` (after a warm-up run)
+    auto time_one = [&](int sched, float* ms) -> int {
+        scn_gen_args t = *a;
+        t.schedule = sched;
+        t.max_steps = 0;
+        scn::PlacePlan plan;
+        if (int r = plan_place(c, b, &t, 0, &plan)) return r;
+        if (int r = run_place(c, b, &t, plan, nullptr, true, st)) return r;
+        if (hipEventRecord(e0, st) != hipSuccess) return fail(SCN_E_HIP, "event record");
+        if (int r = run_place(c, b, &t, plan, nullptr, true, st)) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return fail(SCN_E_HIP, "event sync");
+        return hipEventElapsedTime(ms, e0, e1) == hipSuccess ? SCN_OK
+                                                             : fail(SCN_E_HIP, "elapsed time");
+    };
+    int best = -1;
+    float best_t = 0.f;
+    int rc = SCN_OK;
+    auto consider = [&](int sched) {
+        if (rc != SCN_OK) return;
+        float ms = 0.f;
+        rc = time_one(sched, &ms);
+        if (rc == SCN_OK && (best < 0 || ms < best_t)) { best = sched; best_t = ms; }
+    };
+    // Coordinate descent: LDS budget (4 waves, longest first), then waves,
+    // then the scene order.
+    const int lpt = SCN_SCHED_LONGEST_FIRST;
+    for (int code : {0, 2, 4, (int)SCN_SCHED_LDS_NONE}) consider(4 | lpt | (code << SCN_SCHED_LDS_SHIFT));
+    const int lds_bits = best & SCN_SCHED_LDS_MASK;
+    for (int w : {2, 8, 16}) consider(w | lpt | lds_bits);
+    consider(best & ~SCN_SCHED_LONGEST_FIRST);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SCN_OK) return rc;
+    c->tuned[shape_key(b)] = scn_ctx::Tuned{best, best_t};
+    if (best_schedule) *best_schedule = best;
+    if (best_ms) *best_ms = best_t;
+    return SCN_OK;
+}
+
+int scn_autotune_save(scn_ctx* c, const char* path) {
+    if (!c || !path) return fail(SCN_E_INVALID_ARG, "null context or path");
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(SCN_E_INVALID_ARG, "cannot write %s", path);
+    fprintf(f, "{\"scn_autotune\": [\n");
+    size_t i = 0;
+    for (const auto& kv : c->tuned) {
+        fprintf(f, "  {\"shape\": \"%s\", \"schedule\": %d, \"ms\": %.4f}%s\n", kv.first.c_str(),
+                kv.second.schedule, kv.second.ms, ++i < c->tuned.size() ? "," : "");
+    }
+    fprintf(f, "]}\n");
+    fclose(f);
+    return SCN_OK;
+}
+
+int scn_autotune_load(scn_ctx* c, const char* path) {
+    if (!c || !path) return fail(SCN_E_INVALID_ARG, "null context or path");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(SCN_E_INVALID_ARG, "cannot read %s", path);
+    char line[512], shape[128];
+    int sched;
+    float ms;
+    while (fgets(line, sizeof line, f)) {
+        if (sscanf(line, " {\"shape\": \"%127[^\"]\", \"schedule\": %d, \"ms\": %f", shape, &sched,
+                   &ms) == 3)
+            c->tuned[shape] = scn_ctx::Tuned{sched, ms};
+    }
+    fclose(f);
     return SCN_OK;
 }
 

@@ -93,6 +93,16 @@ __device__ __forceinline__ void box_excess(const float* B, float px, float py, f
     ez = fabsf(qz) - B[14];
 }
 
+// Same excess with the box held in registers (R row-major, centre c, half h).
+__device__ __forceinline__ void box_excess_reg(const float* R, const float* c, const float* h,
+                                               float px, float py, float pz, float& ex, float& ey,
+                                               float& ez) {
+    const float dx = px - c[0], dy = py - c[1], dz = pz - c[2];
+    ex = fabsf(fmaf(R[0], dx, fmaf(R[3], dy, R[6] * dz))) - h[0];
+    ey = fabsf(fmaf(R[1], dx, fmaf(R[4], dy, R[7] * dz))) - h[1];
+    ez = fabsf(fmaf(R[2], dx, fmaf(R[5], dy, R[8] * dz))) - h[2];
+}
+
 // Exact signed distance to the box.
 __device__ __forceinline__ float box_sdf(const float* B, float px, float py, float pz) {
     float ex, ey, ez;

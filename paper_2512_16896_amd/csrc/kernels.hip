@@ -4,11 +4,8 @@
 //   k_sample  candidate poses of one attempt, one lane per candidate
 //   k_check   dense exact clearance, one lane per candidate, obstacles
 //             wave-uniform (scalar loads from the read-only tables)
-//   k_place   persistent fused place kernel: one workgroup per scene loops
-//             over the scene's objects and attempts; one wave per candidate
-//             with the object's spheres across the lanes; placed spheres and
-//             object bounds of the scene live in LDS; first-valid selection by
-//             an LDS atomicMin over candidate indices.
+//   k_order_* longest-first scene order (counting sort by a work estimate)
+// The persistent fused place kernel is in place.hip.
 #include <climits>
 
 #include "device.h"
@@ -201,274 +198,65 @@ hipError_t launch_check(const scn_batch& b, const int32_t* obj_idx, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// Persistent fused place kernel.
-//
-// One workgroup of W waves owns scene s for the whole launch.  For each of
-// the scene's remaining objects (up to max_steps), attempts a = 0..retries:
-// wave w evaluates candidates i = w, w+W, w+2W, ... in increasing order; a
-// lane computes the pose of one of the wave's next 64 candidates (Philox in
-// parallel), then the wave walks them one at a time with the object's
-// spheres spread over the lanes (SPL spheres per lane).  A candidate is
-// rejected at the first obstacle that any lane hits (ballot); placed objects
-// whose bounding spheres are farther apart than the margin are skipped
-// (exact: no sphere pair inside can be closer).  A collision-free candidate
-// lowers the scene's best index (LDS atomicMin) and ends that wave's search;
-// waves stop as soon as the best index is below their next candidate, so the
-// result is exactly the lowest collision-free index.
-template <int SPL>
-__global__ __launch_bounds__(512) void k_place(
-    const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
-    const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
-    const int32_t* __restrict__ obj_ncand, const float* __restrict__ sup,
-    const int32_t* __restrict__ box_off, const float* __restrict__ box,
-    float4* __restrict__ placed, int32_t* __restrict__ n_placed, int8_t* __restrict__ status,
-    scn_pose_rec* __restrict__ rec, int32_t* __restrict__ chosen,
-    unsigned long long* __restrict__ counters, uint64_t seed, float margin, int retries,
-    int default_ncand, int max_steps, int cap_sph, int cap_obj) {
-    extern __shared__ float4 lds[];
-    float4* lsph = lds;            // placed spheres of this scene: (x, y, z, r + margin)
-    float4* lbnd = lds + cap_sph;  // world bounding sphere of each placed object
-    __shared__ int s_best[2];
-
-    const int s = blockIdx.x;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = uniform_int(threadIdx.x >> 6);
-    const int W = blockDim.x >> 6;
-
-    if (status[s] != SCN_SCENE_ACTIVE) {
-        if (chosen && threadIdx.x == 0) chosen[s] = -2;
-        return;
-    }
+// Longest-first order.  Work estimate of a scene: its objects times its
+// spheres (the pair work of a scene grows with both); 256 log-spaced buckets,
+// largest first; scenes inside a bucket in arbitrary order (results do not
+// depend on the order: scenes are independent).
+__device__ __forceinline__ int work_bucket(const int32_t* __restrict__ obj_off,
+                                           const int32_t* __restrict__ sph_off,
+                                           const int32_t* __restrict__ box_off, int s) {
     const int o0 = obj_off[s], o1 = obj_off[s + 1];
-    const int nobj = o1 - o0;
-    const int first = sph_off[o0];
-    int too_big = 0;
-    for (int ob = o0 + (int)threadIdx.x; ob < o1; ob += blockDim.x)
-        too_big |= (sph_off[ob + 1] - sph_off[ob]) > kWave * SPL;
-    too_big = __syncthreads_or(too_big);
-    if (too_big || sph_off[o1] - first > cap_sph || nobj > cap_obj) {
-        if (threadIdx.x == 0) {
-            atomicOr(counters + kErrorWord, (unsigned long long)kErrCapacity);
-            if (chosen) chosen[s] = -2;
-        }
-        return;
-    }
-    int j = min(max(n_placed[s], 0), nobj);
-    const int j_end = max_steps > 0 ? min(nobj, j + max_steps) : nobj;
-
-    // Stage the already placed spheres and their objects' bounding spheres.
-    const int n_stage = sph_off[o0 + j] - first;
-    for (int i = threadIdx.x; i < n_stage; i += blockDim.x) {
-        float4 q = placed[first + i];
-        q.w += margin;
-        lsph[i] = q;
-    }
-    for (int ob = wave; ob < j; ob += W) {
-        const int a0 = sph_off[o0 + ob] - first, a1 = sph_off[o0 + ob + 1] - first;
-        float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
-        for (int k = a0 + lane; k < a1; k += kWave) {
-            const float4 q = placed[first + k];
-            lo[0] = fminf(lo[0], q.x - q.w); hi[0] = fmaxf(hi[0], q.x + q.w);
-            lo[1] = fminf(lo[1], q.y - q.w); hi[1] = fmaxf(hi[1], q.y + q.w);
-            lo[2] = fminf(lo[2], q.z - q.w); hi[2] = fmaxf(hi[2], q.z + q.w);
-        }
-        float c[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) c[d] = 0.5f * (wave_min(lo[d]) + wave_max(hi[d]));
-        float rho = 0.f;
-        for (int k = a0 + lane; k < a1; k += kWave) {
-            const float4 q = placed[first + k];
-            const float dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
-            rho = fmaxf(rho, sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) + q.w);
-        }
-        rho = wave_max(rho) * (1.0f + 1e-6f) + 1e-6f;
-        if (lane == 0) lbnd[ob] = make_float4(c[0], c[1], c[2], rho);
-    }
-    __syncthreads();
-
-    unsigned long long n_cand = 0, n_pairs = 0, n_boxp = 0, n_att = 0, n_done = 0, n_xf = 0;
-    int8_t fin = SCN_SCENE_ACTIVE;
-    int last = -2;
-    const int b0 = box_off[s], b1 = box_off[s + 1];
-    int phase = 0;
-
-    for (; j < j_end; ++j) {
-        const int o = o0 + j;
-        const int sb = sph_off[o];
-        const int S = sph_off[o + 1] - sb;
-        float cx[SPL], cy[SPL], cz[SPL], cr[SPL], rm2[SPL];
-        bool act[SPL];
-        float lift = -1e30f, lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
-#pragma unroll
-        for (int q = 0; q < SPL; ++q) {
-            const int k = lane + kWave * q;
-            act[q] = k < S;
-            const float4 c = act[q] ? tmpl[sb + k] : make_float4(0.f, 0.f, 0.f, 0.f);
-            cx[q] = c.x; cy[q] = c.y; cz[q] = c.z; cr[q] = c.w;
-            rm2[q] = (c.w + margin) * (c.w + margin);
-            if (act[q]) {
-                lift = fmaxf(lift, c.w - c.z);
-                lo[0] = fminf(lo[0], c.x - c.w); hi[0] = fmaxf(hi[0], c.x + c.w);
-                lo[1] = fminf(lo[1], c.y - c.w); hi[1] = fmaxf(hi[1], c.y + c.w);
-                lo[2] = fminf(lo[2], c.z - c.w); hi[2] = fmaxf(hi[2], c.z + c.w);
-            }
-        }
-        lift = wave_max(lift);
-        float bc[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) bc[d] = 0.5f * (wave_min(lo[d]) + wave_max(hi[d]));
-        float rho = 0.f;
-#pragma unroll
-        for (int q = 0; q < SPL; ++q) {
-            if (act[q]) {
-                const float dx = cx[q] - bc[0], dy = cy[q] - bc[1], dz = cz[q] - bc[2];
-                rho = fmaxf(rho, sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) + cr[q]);
-            }
-        }
-        rho = wave_max(rho) * (1.0f + 1e-6f) + 1e-6f;
-
-        const Support U = load_support(sup, obj_sup[o]);
-        const float ax = U.hx - U.inset, ay = U.hy - U.inset, zc = U.lift + lift;
-        const int C = obj_ncand ? obj_ncand[o] : default_ncand;
-        int found = -1, found_att = -1;
-
-        for (int a = 0; a <= retries; ++a) {
-            int* best = &s_best[phase];
-            if (threadIdx.x == 0) *best = INT_MAX;
-            __syncthreads();
-            if (wave == 0) ++n_att;
-            bool stop = false;
-            for (int base = 0; !stop; base += kWave) {
-                if (wave + W * base >= C) break;
-                const Pose L = sample_pose(seed, (uint32_t)s, (uint32_t)j, (uint32_t)a,
-                                           (uint32_t)(wave + W * (base + lane)), ax, ay, zc);
-                for (int t = 0; t < kWave; ++t) {
-                    const int i = wave + W * (base + t);
-                    if (i >= C) { stop = true; break; }
-                    const int cur = uniform_int(
-                        __hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-                    if (cur < i) { stop = true; break; }
-                    Pose P;
-                    P.x = bcast(L.x, t); P.y = bcast(L.y, t); P.z = zc;
-                    P.c = bcast(L.c, t); P.s = bcast(L.s, t);
-                    ++n_cand;
-                    n_xf += S;
-                    float wx[SPL], wy[SPL], wz[SPL];
-#pragma unroll
-                    for (int q = 0; q < SPL; ++q) to_world(U, P, cx[q], cy[q], cz[q], wx[q], wy[q], wz[q]);
-                    bool hit = false;
-                    // static boxes
-                    for (int bx = b0; bx < b1; ++bx) {
-                        const float* B = box + 16 * bx;
-#pragma unroll
-                        for (int q = 0; q < SPL; ++q)
-                            hit |= act[q] && box_out2(B, wx[q], wy[q], wz[q]) < rm2[q];
-                        n_boxp += S;
-                        if (__ballot(hit)) break;
-                    }
-                    if (!__ballot(hit) && j > 0) {
-                        float gx, gy, gz;
-                        to_world(U, P, bc[0], bc[1], bc[2], gx, gy, gz);
-                        for (int ob = 0; ob < j; ++ob) {
-                            const float4 bd = lbnd[ob];
-                            const float dx = gx - bd.x, dy = gy - bd.y, dz = gz - bd.z;
-                            const float lim = rho + bd.w + margin;
-                            if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) >= lim * lim) continue;
-                            const int a0 = sph_off[o0 + ob] - first, a1 = sph_off[o0 + ob + 1] - first;
-                            for (int k = a0; k < a1; ++k) {
-                                const float4 qs = lsph[k];
-#pragma unroll
-                                for (int q = 0; q < SPL; ++q) {
-                                    const float ex = wx[q] - qs.x, ey = wy[q] - qs.y, ez = wz[q] - qs.z;
-                                    const float rr = cr[q] + qs.w;
-                                    hit |= act[q] && fmaf(-rr, rr, fmaf(ex, ex, fmaf(ey, ey, ez * ez))) < 0.f;
-                                }
-                            }
-                            n_pairs += (unsigned long long)S * (unsigned long long)(a1 - a0);
-                            if (__ballot(hit)) break;
-                        }
-                    }
-                    if (!__ballot(hit)) {
-                        if (lane == 0) atomicMin(best, i);
-                        stop = true;
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            const int b = *best;
-            phase ^= 1;
-            if (b != INT_MAX) { found = b; found_att = a; break; }
-        }
-        if (found < 0) { fin = SCN_SCENE_INVALID; last = -1; break; }
-        if (wave == 0) {
-            const Pose P = sample_pose(seed, (uint32_t)s, (uint32_t)j, (uint32_t)found_att,
-                                       (uint32_t)found, ax, ay, zc);
-#pragma unroll
-            for (int q = 0; q < SPL; ++q) {
-                if (act[q]) {
-                    float wx, wy, wz;
-                    to_world(U, P, cx[q], cy[q], cz[q], wx, wy, wz);
-                    const int k = lane + kWave * q;
-                    placed[sb + k] = make_float4(wx, wy, wz, cr[q]);
-                    lsph[sb - first + k] = make_float4(wx, wy, wz, cr[q] + margin);
-                }
-            }
-            if (lane == 0) {
-                float gx, gy, gz;
-                to_world(U, P, bc[0], bc[1], bc[2], gx, gy, gz);
-                lbnd[j] = make_float4(gx, gy, gz, rho);
-                rec[o] = scn_pose_rec{P.x, P.y, P.z, P.yaw, found_att, found};
-            }
-            ++n_done;
-        }
-        last = found;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        n_placed[s] = j;
-        status[s] = fin != SCN_SCENE_ACTIVE ? fin : (j == nobj ? SCN_SCENE_VALID : SCN_SCENE_ACTIVE);
-        if (chosen) chosen[s] = last;
-    }
-    if (lane == 0) {
-        atomicAdd(counters + kCandidates, n_cand);
-        atomicAdd(counters + kSpherePairs, n_pairs);
-        atomicAdd(counters + kBoxPairs, n_boxp);
-        atomicAdd(counters + kTransforms, n_xf);
-        if (n_att) atomicAdd(counters + kAttempts, n_att);
-        if (n_done) atomicAdd(counters + kPlaced, n_done);
-    }
+    const float w = (float)(o1 - o0) * (float)(sph_off[o1] - sph_off[o0] + 16 * (box_off[s + 1] - box_off[s])) + 1.f;
+    const int bk = (int)(__log2f(w) * 6.0f);
+    return kOrderBuckets - 1 - min(max(bk, 0), kOrderBuckets - 1);
 }
 
-int place_max_lds_bytes() { return 160 * 1024; }
+__global__ void k_order_hist(int n, const int32_t* __restrict__ obj_off,
+                             const int32_t* __restrict__ sph_off,
+                             const int32_t* __restrict__ box_off, int32_t* __restrict__ hist) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) atomicAdd(hist + work_bucket(obj_off, sph_off, box_off, s), 1);
+}
 
-hipError_t launch_place(const scn_batch& b, const scn_gen_args& a, const PlacePlan& plan,
-                        int32_t* chosen, int64_t* counters, hipStream_t st) {
-    if (b.n_scenes == 0) return hipSuccess;
-    dim3 grid(b.n_scenes), block(kWave * plan.waves);
-    auto* ctr = (unsigned long long*)counters;
-#define SCN_LAUNCH_PLACE(SPLV)                                                                  \
-    do {                                                                                        \
-        auto kern = k_place<SPLV>;                                                              \
-        if (plan.lds_bytes > 64 * 1024) {                                                       \
-            hipError_t e = hipFuncSetAttribute((const void*)kern,                               \
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,      \
-                                               plan.lds_bytes);                                 \
-            if (e != hipSuccess) return e;                                                      \
-        }                                                                                       \
-        hipLaunchKernelGGL(kern, grid, block, plan.lds_bytes, st, b.obj_off, b.sph_off,         \
-                           (const float4*)b.tmpl, b.obj_sup, b.obj_ncand, b.sup, b.box_off,     \
-                           b.box, (float4*)b.placed, b.n_placed, b.status, b.rec, chosen, ctr,  \
-                           a.seed, a.margin, a.retries, a.default_ncand, plan.max_steps,        \
-                           plan.cap_sph, plan.cap_obj);                                         \
-    } while (0)
-    switch (plan.spl) {
-        case 1: SCN_LAUNCH_PLACE(1); break;
-        case 2: SCN_LAUNCH_PLACE(2); break;
-        case 4: SCN_LAUNCH_PLACE(4); break;
-        default: return hipErrorInvalidValue;
+// exclusive scan of the 256 bucket counts, one workgroup of 256 threads
+__global__ void k_order_scan(int32_t* __restrict__ hist) {
+    __shared__ int v[kOrderBuckets];
+    const int t = threadIdx.x;
+    v[t] = hist[t];
+    __syncthreads();
+    for (int d = 1; d < kOrderBuckets; d <<= 1) {
+        const int x = t >= d ? v[t - d] : 0;
+        __syncthreads();
+        v[t] += x;
+        __syncthreads();
     }
-#undef SCN_LAUNCH_PLACE
+    hist[t] = t == 0 ? 0 : v[t - 1];
+}
+
+__global__ void k_order_scatter(int n, const int32_t* __restrict__ obj_off,
+                                const int32_t* __restrict__ sph_off,
+                                const int32_t* __restrict__ box_off, int32_t* __restrict__ hist,
+                                int32_t* __restrict__ order) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) order[atomicAdd(hist + work_bucket(obj_off, sph_off, box_off, s), 1)] = s;
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_longest_first(const scn_batch& b, int32_t* order, int32_t* hist,
+                                hipStream_t st) {
+    const int n = b.n_scenes;
+    if (n == 0) return hipSuccess;
+    const int g = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kOrderBuckets), 0, st, hist, kOrderBuckets, 0);
+    hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, st, n, b.obj_off, b.sph_off,
+                       b.box_off, hist);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBuckets), 0, st, hist);
+    hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, st, n, b.obj_off, b.sph_off,
+                       b.box_off, hist, order);
     return hipGetLastError();
 }
 

@@ -1,0 +1,431 @@
+// place.hip -- the persistent fused place kernel and its launcher.
+//
+// One workgroup of W waves owns scene s for the whole launch and places its
+// objects one after another (the per-object rejection loop of the method).
+// For one object the candidates of all attempts form one list in
+// (attempt, index) order; the first collision-free entry of that list is the
+// winner: the lowest index of the first attempt that has a collision-free
+// candidate (retries only happen for a scene that found none).  Wave w walks
+// the entries w, w+W, w+2W, ... in batches of 64:
+//
+//   batch phase (lane t <-> candidate t of the batch): the pose (Philox), the
+//     world centre of the object's bounding sphere, and two bit masks: the
+//     boxes and the placed objects whose bounding volumes come within the
+//     margin of that bounding sphere (1-Lipschitz distance bounds: every other
+//     box / object is farther than the margin from every sphere, exactly);
+//   candidate phase (one candidate at a time, the object's spheres across the
+//     lanes, SPL per lane): sphere tests against the boxes of its mask, then
+//     for each object of its mask a lane-parallel pretest of that object's
+//     placed spheres against the bounding sphere followed by exact tests of
+//     the spheres that pass.  The candidate is rejected at the first hit any
+//     lane reports (ballot).
+//
+// A collision-free candidate lowers the scene's best entry (LDS atomicMin);
+// a wave stops once the best entry is below its next one, so every entry
+// before the winner has been decided and the result is exactly the first
+// collision-free one, whatever the number of waves.
+#include <climits>
+
+#include "device.h"
+#include "internal.h"
+
+namespace scn {
+
+__device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int lane) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// kLds = true : the scene's placed spheres live in LDS (cap_sph of them);
+//               with `split`, scenes with more spheres are left to the
+//               other launch, otherwise they are a capacity error.
+// kLds = false: placed spheres are read from global memory (L1/L2) and only
+//               the object bounds live in LDS; with `split`, scenes of at
+//               most split_sph spheres are left to the LDS launch.
+template <int SPL, bool kLds>
+__global__ __launch_bounds__(1024) void k_place(
+    const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
+    const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
+    const int32_t* __restrict__ obj_ncand, const float* __restrict__ sup,
+    const int32_t* __restrict__ box_off, const float* __restrict__ box,
+    float4* __restrict__ placed, int32_t* __restrict__ n_placed, int8_t* __restrict__ status,
+    scn_pose_rec* __restrict__ rec, int32_t* __restrict__ chosen,
+    unsigned long long* __restrict__ counters, const int32_t* __restrict__ order, uint64_t seed,
+    float margin, int retries, int default_ncand, int max_steps, int cap_sph, int cap_obj,
+    int split, int split_sph) {
+    extern __shared__ float4 lds[];
+    float4* lsph = lds;                        // placed spheres: (x, y, z, r + margin)
+    float4* lbnd = lds + (kLds ? cap_sph : 0); // world bounding sphere of each placed object
+    __shared__ int s_best;
+
+    const int s = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform_int(threadIdx.x >> 6);
+    const int W = blockDim.x >> 6;
+
+    const int o0 = obj_off[s], o1 = obj_off[s + 1];
+    const int nobj = o1 - o0;
+    const int first = sph_off[o0];
+    const int nsph = sph_off[o1] - first;
+    if (split) {   // which of the two launches owns this scene
+        if (kLds ? nsph > split_sph : nsph <= split_sph) return;
+    }
+    if (status[s] != SCN_SCENE_ACTIVE) {
+        if (chosen && threadIdx.x == 0) chosen[s] = -2;
+        return;
+    }
+    int too_big = 0;
+    for (int ob = o0 + (int)threadIdx.x; ob < o1; ob += blockDim.x)
+        too_big |= (sph_off[ob + 1] - sph_off[ob]) > kWave * SPL;
+    too_big = __syncthreads_or(too_big);
+    if (too_big || (kLds && nsph > cap_sph) || nobj > cap_obj) {
+        if (threadIdx.x == 0) {
+            atomicOr(counters + kErrorWord, (unsigned long long)kErrCapacity);
+            if (chosen) chosen[s] = -2;
+        }
+        return;
+    }
+    int j = min(max(n_placed[s], 0), nobj);
+    const int j_end = max_steps > 0 ? min(nobj, j + max_steps) : nobj;
+    // placed sphere k of this scene, radius grown by the margin
+    auto placed_sphere = [&](int k) -> float4 {
+        if constexpr (kLds) {
+            return lsph[k];
+        } else {
+            float4 q = placed[first + k];
+            q.w += margin;
+            return q;
+        }
+    };
+
+    // Stage the already placed spheres and their objects' bounding spheres.
+    const int n_stage = kLds ? sph_off[o0 + j] - first : 0;
+    for (int i = threadIdx.x; i < n_stage; i += blockDim.x) {
+        float4 q = placed[first + i];
+        q.w += margin;
+        lsph[i] = q;
+    }
+    for (int ob = wave; ob < j; ob += W) {
+        const int a0 = sph_off[o0 + ob] - first, a1 = sph_off[o0 + ob + 1] - first;
+        float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+        for (int k = a0 + lane; k < a1; k += kWave) {
+            const float4 q = placed[first + k];
+            lo[0] = fminf(lo[0], q.x - q.w); hi[0] = fmaxf(hi[0], q.x + q.w);
+            lo[1] = fminf(lo[1], q.y - q.w); hi[1] = fmaxf(hi[1], q.y + q.w);
+            lo[2] = fminf(lo[2], q.z - q.w); hi[2] = fmaxf(hi[2], q.z + q.w);
+        }
+        float c[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) c[d] = 0.5f * (wave_min(lo[d]) + wave_max(hi[d]));
+        float rho = 0.f;
+        for (int k = a0 + lane; k < a1; k += kWave) {
+            const float4 q = placed[first + k];
+            const float dx = q.x - c[0], dy = q.y - c[1], dz = q.z - c[2];
+            rho = fmaxf(rho, sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) + q.w);
+        }
+        rho = wave_max(rho) * (1.0f + 1e-6f) + 1e-6f;
+        if (lane == 0) lbnd[ob] = make_float4(c[0], c[1], c[2], rho);
+    }
+    __syncthreads();
+
+    unsigned long long n_cand = 0, n_pairs = 0, n_boxp = 0, n_att = 0, n_done = 0, n_xf = 0;
+    unsigned long long n_boxc = 0, n_objc = 0, n_sphc = 0;
+    int8_t fin = SCN_SCENE_ACTIVE;
+    int last = -2;
+    const int b0 = box_off[s], b1 = box_off[s + 1];
+    const int nbox_mask = min(b1 - b0, kWave);   // boxes covered by the batch masks
+
+    for (; j < j_end; ++j) {
+        const int o = o0 + j;
+        const int sb = sph_off[o];
+        const int S = sph_off[o + 1] - sb;
+        const int nq = (S + kWave - 1) / kWave;   // sphere slots per lane this object uses
+        float cx[SPL], cy[SPL], cz[SPL], cr[SPL], rm2[SPL];
+        bool act[SPL];
+        float lift = -1e30f, lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            const int k = lane + kWave * q;
+            act[q] = k < S;
+            // Lanes without a sphere carry a zero-radius point 1e18 m up the
+            // object's z axis: rigid motions keep it ~1e18 m from everything,
+            // so it never tests as a hit and needs no predicate in the loops.
+            const float4 c = act[q] ? tmpl[sb + k] : make_float4(0.f, 0.f, 1e18f, 0.f);
+            cx[q] = c.x; cy[q] = c.y; cz[q] = c.z; cr[q] = c.w;
+            rm2[q] = act[q] ? (c.w + margin) * (c.w + margin) : 0.f;
+            if (act[q]) {
+                lift = fmaxf(lift, c.w - c.z);
+                lo[0] = fminf(lo[0], c.x - c.w); hi[0] = fmaxf(hi[0], c.x + c.w);
+                lo[1] = fminf(lo[1], c.y - c.w); hi[1] = fmaxf(hi[1], c.y + c.w);
+                lo[2] = fminf(lo[2], c.z - c.w); hi[2] = fmaxf(hi[2], c.z + c.w);
+            }
+        }
+        lift = wave_max(lift);
+        float bc[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) bc[d] = 0.5f * (wave_min(lo[d]) + wave_max(hi[d]));
+        float rho = 0.f;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            if (act[q]) {
+                const float dx = cx[q] - bc[0], dy = cy[q] - bc[1], dz = cz[q] - bc[2];
+                rho = fmaxf(rho, sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) + cr[q]);
+            }
+        }
+        rho = wave_max(rho) * (1.0f + 1e-6f) + 1e-6f;
+        const float reach = rho + margin;
+
+        const Support U = load_support(sup, obj_sup[o]);
+        const float ax = U.hx - U.inset, ay = U.hy - U.inset, zc = U.lift + lift;
+        const int C = obj_ncand ? obj_ncand[o] : default_ncand;
+        const int total = C > 0 ? (retries + 1) * C : 0;   // entries (attempt, index)
+        const int nob_mask = min(j, kWave);                 // objects covered by the masks
+
+        if (threadIdx.x == 0) s_best = INT_MAX;
+        __syncthreads();
+
+        // Exact sphere tests of the candidate (spheres wx/wy/wz in the lanes)
+        // against placed object ob; true when a lane hit.
+        float wx[SPL], wy[SPL], wz[SPL];
+        float Gx = 0.f, Gy = 0.f, Gz = 0.f;
+        auto test_object = [&](int ob, bool& hit) {
+            const int a0 = sph_off[o0 + ob] - first, a1 = sph_off[o0 + ob + 1] - first;
+            for (int c0 = a0; c0 < a1; c0 += kWave) {
+                // lane-parallel pretest of up to 64 placed spheres
+                bool rel = false;
+                if (c0 + lane < a1) {
+                    const float4 q = placed_sphere(c0 + lane);
+                    const float dx = q.x - Gx, dy = q.y - Gy, dz = q.z - Gz;
+                    const float lim = rho + q.w;
+                    rel = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim;
+                }
+                unsigned long long rm = __ballot(rel);
+                n_sphc += (unsigned long long)min(kWave, a1 - c0);
+                while (rm) {
+                    const int k0 = c0 + __builtin_ctzll(rm);
+                    rm &= rm - 1;
+                    int k1 = k0;
+                    if (rm) {
+                        k1 = c0 + __builtin_ctzll(rm);
+                        rm &= rm - 1;
+                    }
+                    const float4 qa = placed_sphere(k0), qb = placed_sphere(k1);
+                    float m = __builtin_huge_valf();
+#pragma unroll
+                    for (int q = 0; q < SPL; ++q) {
+                        if (q > 0 && q >= nq) break;
+                        {
+                            const float ex = wx[q] - qa.x, ey = wy[q] - qa.y, ez = wz[q] - qa.z;
+                            const float rr = cr[q] + qa.w;
+                            m = fminf(m, fmaf(-rr, rr, fmaf(ex, ex, fmaf(ey, ey, ez * ez))));
+                        }
+                        {
+                            const float ex = wx[q] - qb.x, ey = wy[q] - qb.y, ez = wz[q] - qb.z;
+                            const float rr = cr[q] + qb.w;
+                            m = fminf(m, fmaf(-rr, rr, fmaf(ex, ex, fmaf(ey, ey, ez * ez))));
+                        }
+                    }
+                    hit |= m < 0.f;
+                    n_pairs += (unsigned long long)S * (k1 != k0 ? 2u : 1u);
+                    if (__ballot(hit)) return;
+                }
+            }
+        };
+
+        bool stop = false;
+        for (int base = 0; !stop; base += kWave) {
+            if (wave + W * base >= total) break;
+            if (uniform_int(__hip_atomic_load(&s_best, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP)) < wave + W * base)
+                break;
+            // ---- batch phase: lane t holds candidate entry wave + W (base + t) ----
+            const int g = wave + W * (base + lane);
+            const bool live = g < total;
+            const int ga = live ? g / C : 0;
+            const int gi = live ? g - ga * C : 0;
+            const Pose L = sample_pose(seed, (uint32_t)s, (uint32_t)j, (uint32_t)ga, (uint32_t)gi,
+                                       ax, ay, zc);
+            float lx, ly, lz;   // world centre of this candidate's bounding sphere
+            to_world(U, L, bc[0], bc[1], bc[2], lx, ly, lz);
+            unsigned long long bmask = 0, omask = 0;
+            for (int bi = 0; bi < nbox_mask; ++bi) {
+                const float* B = box + 16 * (b0 + bi);
+                if (box_out2(B, lx, ly, lz) < reach * reach) bmask |= 1ull << bi;
+            }
+            for (int ob = 0; ob < nob_mask; ++ob) {
+                const float4 bd = lbnd[ob];
+                const float dx = lx - bd.x, dy = ly - bd.y, dz = lz - bd.z;
+                const float lim = reach + bd.w;
+                if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) omask |= 1ull << ob;
+            }
+            {
+                const unsigned long long nlive = __popcll(__ballot(live));
+                n_boxc += nlive * (unsigned long long)nbox_mask;
+                n_objc += nlive * (unsigned long long)nob_mask;
+            }
+            // ---- candidate phase ----
+            for (int t = 0; t < kWave; ++t) {
+                const int gt = wave + W * (base + t);
+                if (gt >= total) { stop = true; break; }
+                if (uniform_int(__hip_atomic_load(&s_best, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP)) < gt) {
+                    stop = true;
+                    break;
+                }
+                Pose P;
+                P.x = bcast(L.x, t); P.y = bcast(L.y, t); P.z = zc;
+                P.c = bcast(L.c, t); P.s = bcast(L.s, t);
+                Gx = bcast(lx, t); Gy = bcast(ly, t); Gz = bcast(lz, t);
+                unsigned long long bm = bcast64(bmask, t), om = bcast64(omask, t);
+                ++n_cand;
+                n_xf += S;
+#pragma unroll
+                for (int q = 0; q < SPL; ++q)
+                    if (q == 0 || q < nq) to_world(U, P, cx[q], cy[q], cz[q], wx[q], wy[q], wz[q]);
+                bool hit = false;
+                // boxes of the mask, then any boxes beyond the first 64
+                while (bm) {
+                    const int bi = __builtin_ctzll(bm);
+                    bm &= bm - 1;
+                    const float* B = box + 16 * (b0 + bi);
+#pragma unroll
+                    for (int q = 0; q < SPL; ++q)
+                        if (q == 0 || q < nq) hit |= box_out2(B, wx[q], wy[q], wz[q]) < rm2[q];
+                    n_boxp += S;
+                    if (__ballot(hit)) break;
+                }
+                for (int bx = b0 + kWave; bx < b1 && !__ballot(hit); ++bx) {
+                    const float* B = box + 16 * bx;
+                    n_boxc += 1;
+                    if (!(box_out2(B, Gx, Gy, Gz) < reach * reach)) continue;
+#pragma unroll
+                    for (int q = 0; q < SPL; ++q)
+                        if (q == 0 || q < nq) hit |= box_out2(B, wx[q], wy[q], wz[q]) < rm2[q];
+                    n_boxp += S;
+                }
+                // placed objects of the mask, then any beyond the first 64
+                if (!__ballot(hit)) {
+                    while (om) {
+                        const int ob = __builtin_ctzll(om);
+                        om &= om - 1;
+                        test_object(ob, hit);
+                        if (__ballot(hit)) break;
+                    }
+                    for (int ob = kWave; ob < j && !__ballot(hit); ++ob) {
+                        const float4 bd = lbnd[ob];
+                        const float dx = Gx - bd.x, dy = Gy - bd.y, dz = Gz - bd.z;
+                        const float lim = reach + bd.w;
+                        n_objc += 1;
+                        if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) test_object(ob, hit);
+                    }
+                }
+                if (!__ballot(hit)) {
+                    if (lane == 0) atomicMin(&s_best, gt);
+                    stop = true;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        const int best = s_best;
+        if (wave == 0) n_att += best == INT_MAX ? (unsigned)(retries + 1) : (unsigned)(best / C + 1);
+        if (best == INT_MAX) { fin = SCN_SCENE_INVALID; last = -1; break; }
+        const int fa = best / C, fi = best - fa * C;
+        if (wave == 0) {
+            const Pose P = sample_pose(seed, (uint32_t)s, (uint32_t)j, (uint32_t)fa, (uint32_t)fi,
+                                       ax, ay, zc);
+#pragma unroll
+            for (int q = 0; q < SPL; ++q) {
+                if (act[q]) {
+                    float px, py, pz;
+                    to_world(U, P, cx[q], cy[q], cz[q], px, py, pz);
+                    const int k = lane + kWave * q;
+                    placed[sb + k] = make_float4(px, py, pz, cr[q]);
+                    if constexpr (kLds) lsph[sb - first + k] = make_float4(px, py, pz, cr[q] + margin);
+                }
+            }
+            if (lane == 0) {
+                float gx, gy, gz;
+                to_world(U, P, bc[0], bc[1], bc[2], gx, gy, gz);
+                lbnd[j] = make_float4(gx, gy, gz, rho);
+                rec[o] = scn_pose_rec{P.x, P.y, P.z, P.yaw, fa, fi};
+            }
+            ++n_done;
+        }
+        last = fi;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        n_placed[s] = j;
+        const int8_t st = fin != SCN_SCENE_ACTIVE ? fin
+                                                  : (j == nobj ? SCN_SCENE_VALID : SCN_SCENE_ACTIVE);
+        status[s] = st;
+        if (chosen) chosen[s] = last;
+        if (st == SCN_SCENE_VALID) atomicAdd(counters + kValidScenes, 1ull);
+        if (st == SCN_SCENE_INVALID) atomicAdd(counters + kInvalidScenes, 1ull);
+    }
+    if (lane == 0) {
+        atomicAdd(counters + kCandidates, n_cand);
+        atomicAdd(counters + kSpherePairs, n_pairs);
+        atomicAdd(counters + kBoxPairs, n_boxp);
+        atomicAdd(counters + kTransforms, n_xf);
+        atomicAdd(counters + kBoxCulls, n_boxc);
+        atomicAdd(counters + kObjCulls, n_objc);
+        atomicAdd(counters + kSphCulls, n_sphc);
+        if (n_att) atomicAdd(counters + kAttempts, n_att);
+        if (n_done) atomicAdd(counters + kPlaced, n_done);
+    }
+}
+
+template <int SPL, bool kLds>
+static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
+                                   const PlacePlan& plan, int cap_sph, int split, int32_t* chosen,
+                                   unsigned long long* ctr, hipStream_t st) {
+    auto kern = k_place<SPL, kLds>;
+    const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj);
+    if (bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(b.n_scenes), dim3(kWave * plan.waves), bytes, st, b.obj_off,
+                       b.sph_off, (const float4*)b.tmpl, b.obj_sup, b.obj_ncand, b.sup,
+                       b.box_off, b.box, (float4*)b.placed, b.n_placed, b.status, b.rec, chosen,
+                       ctr, plan.order, a.seed, a.margin, a.retries, a.default_ncand,
+                       plan.max_steps, cap_sph, plan.cap_obj, split, plan.split_sph);
+    return hipGetLastError();
+}
+
+template <int SPL>
+static hipError_t launch_place_spl(const scn_batch& b, const scn_gen_args& a,
+                                   const PlacePlan& plan, int32_t* chosen,
+                                   unsigned long long* ctr, hipStream_t st) {
+    switch (plan.mode) {
+        case kPlaceAllLds:
+            return launch_place_one<SPL, true>(b, a, plan, plan.cap_sph, 0, chosen, ctr, st);
+        case kPlaceAllGlobal:
+            return launch_place_one<SPL, false>(b, a, plan, 0, 0, chosen, ctr, st);
+        case kPlaceSplit: {
+            // larger scenes first (they run longest), then the LDS-resident ones
+            hipError_t e = launch_place_one<SPL, false>(b, a, plan, 0, 1, chosen, ctr, st);
+            if (e != hipSuccess) return e;
+            return launch_place_one<SPL, true>(b, a, plan, plan.split_sph, 1, chosen, ctr, st);
+        }
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_place(const scn_batch& b, const scn_gen_args& a, const PlacePlan& plan,
+                        int32_t* chosen, int64_t* counters, hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    auto* ctr = (unsigned long long*)counters;
+    switch (plan.spl) {
+        case 1: return launch_place_spl<1>(b, a, plan, chosen, ctr, st);
+        case 2: return launch_place_spl<2>(b, a, plan, chosen, ctr, st);
+        case 4: return launch_place_spl<4>(b, a, plan, chosen, ctr, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace scn

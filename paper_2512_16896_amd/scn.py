@@ -58,7 +58,8 @@ class _GenArgs(C.Structure):
 class Counters(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "candidates", "sphere_pairs", "box_pairs", "grid_samples", "attempts", "placed",
-        "error_word", "transforms")] + [("reserved", C.c_int64 * 8)]
+        "error_word", "transforms", "box_culls", "object_culls", "valid_scenes",
+        "invalid_scenes", "sphere_culls")] + [("reserved", C.c_int64 * 3)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}
@@ -80,6 +81,10 @@ def _load():
         "scn_reset_scenes": [vp, C.POINTER(_Batch), vp],
         "scn_place_step": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp, vp],
         "scn_generate_scenes": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp],
+        "scn_autotune": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), C.POINTER(C.c_int32),
+                         C.POINTER(C.c_float), vp],
+        "scn_autotune_save": [vp, C.c_char_p],
+        "scn_autotune_load": [vp, C.c_char_p],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -96,7 +101,10 @@ _lib = _load()
 # names of the C ABI entry points (what include/scn.h declares)
 EXPORTS = ("scn_ctx_create", "scn_ctx_destroy", "scn_status_string", "scn_last_error",
            "scn_reset_counters", "scn_read_counters", "scn_sample_poses", "scn_check_batch",
-           "scn_reset_scenes", "scn_place_step", "scn_generate_scenes")
+           "scn_reset_scenes", "scn_place_step", "scn_generate_scenes", "scn_autotune",
+           "scn_autotune_save", "scn_autotune_load")
+
+SCHED_LONGEST_FIRST = 0x20
 
 
 def lib():
@@ -144,6 +152,20 @@ class Context:
         c = Counters()
         _ok(_lib.scn_read_counters(self.h, C.byref(c), _stream(stream)))
         return c.as_dict()
+
+    def autotune(self, db: "DeviceBatch", args: "GenArgs", stream=None):
+        """Time every schedule on this batch; returns (schedule, ms)."""
+        sched, ms = C.c_int32(), C.c_float()
+        a = args.c()
+        _ok(_lib.scn_autotune(self.h, C.byref(db.c), C.byref(a), C.byref(sched), C.byref(ms),
+                              _stream(stream)))
+        return int(sched.value), float(ms.value)
+
+    def save_tuning(self, path: str):
+        _ok(_lib.scn_autotune_save(self.h, path.encode()))
+
+    def load_tuning(self, path: str):
+        _ok(_lib.scn_autotune_load(self.h, path.encode()))
 
 
 @dataclass

@@ -22,17 +22,22 @@ def first_banded(out, b, s):
     return int(idx[0]) if len(idx) else o1 - o0
 
 
-def compare_generation(b, ref, status, rec_i, rec_f):
+def compare_generation(b, ref, status, rec_i, rec_f, max_steps=None):
     """ref: oracle.generate output on batch b; status [n], rec_i [n_obj,2]
     (attempt, idx) and rec_f [n_obj,4] (x, y, z, yaw): device results for the
-    same scenes and objects.  Returns (objects compared, scenes with a banded
-    decision)."""
+    same scenes and objects.  With max_steps the oracle placed only the first
+    max_steps objects of each scene: only those are compared (the device may
+    have gone on).  Returns (objects compared, scenes with a banded decision)."""
     n_cmp = n_band = 0
     for s in range(b.n_scenes):
         fb = first_banded(ref, b, s)
         o0, nobj = b.obj_off[s], b.obj_off[s + 1] - b.obj_off[s]
         if fb < nobj:
             n_band += 1
+        if max_steps is not None:
+            if int(ref["status"][s]) == 0:       # oracle stopped early on purpose
+                fb = min(fb, max_steps)
+                nobj = -1                        # no final status to compare
         for j in range(fb):
             o = o0 + j
             want = (int(ref["rec_attempt"][o]), int(ref["rec_idx"][o]))
