@@ -34,7 +34,7 @@ WORKLOADS = {
                               "(half extents U[0.05,0.5] m, random yaw); margin 5 mm; 10 retries",
                          make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                       fromlist=["x"]).batched_scenes(4096, seed=seed),
-                         ncand=1024, cpu_scenes=48),
+                         ncand=1024, cpu_scenes=160),
     "table-1": dict(desc="1 scene; 1.2x0.8 m table; 8 objects x 32 spheres; 256 candidates; "
                          "4 cuboids; margin 5 mm; 10 retries",
                     make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
@@ -48,6 +48,23 @@ WORKLOADS = {
                                                       fromlist=["x"]).uneven_batch(16384, seed=seed),
                          ncand=1024, cpu_scenes=24, tune=True),
 }
+
+
+def recorded_traffic(workload: str, schedule: int):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE runs kept in
+    profiles/traffic.json -- only while the place kernel's sources are the ones
+    those counters were taken on (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    key = f"k_place {workload} {'default' if schedule == 0 else hex(schedule)}"
+    try:
+        rec = json.load(open(path))[key]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
 def main():
@@ -122,7 +139,8 @@ def main():
         "counters_per_step": {k: v / steps for k, v in cnt.items() if k != "error_word"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": None, "kernel": "k_place (fused place kernel)",
+                     "traffic": recorded_traffic(args.workload, args.schedule),
+                     "kernel": "k_place (fused place kernel)",
                      "kernel_ms": launch_ms},
     }
     if not args.no_cpu_baseline:
