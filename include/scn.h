@@ -251,6 +251,105 @@ int scn_autotune(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args, int32_t *
 int scn_autotune_save(scn_ctx *ctx, const char *path);
 int scn_autotune_load(scn_ctx *ctx, const char *path);
 
+/* ---- learned pose proposal: the network ------------------------------- */
+
+/* A 4-layer perceptron over a state's features (a 64 x 64 height map of the
+ * support plus a 32-d object descriptor, dims[0] = 4128 values) to 4096 pose-
+ * bin logits (32 x-cells x 16 y-cells x 8 yaw cells), ReLU between layers,
+ * BF16 weights and activations with FP32 accumulation.  All pointers are
+ * device pointers to caller-owned buffers:
+ *   w[l]  FP32 master weights [dims[l+1]][dims[l]]      b[l]  FP32 biases [dims[l+1]]
+ *   wb[l] BF16 copy of w[l] (same layout)               wt[l] BF16 transpose [dims[l]][dims[l+1]]
+ *   m_w, v_w, m_b, v_b  AdamW moments like w / b (only needed for training).
+ * dims[0..3] must be multiples of 32 (K of the matrix-core GEMMs).          */
+#define SCN_MLP_LAYERS 4
+typedef struct {
+    int32_t dims[SCN_MLP_LAYERS + 1];
+    float *w[SCN_MLP_LAYERS], *b[SCN_MLP_LAYERS];
+    uint16_t *wb[SCN_MLP_LAYERS], *wt[SCN_MLP_LAYERS];
+    float *m_w[SCN_MLP_LAYERS], *v_w[SCN_MLP_LAYERS], *m_b[SCN_MLP_LAYERS], *v_b[SCN_MLP_LAYERS];
+    int64_t step; /* AdamW steps taken; advanced by scn_mlp_train_step (host field) */
+} scn_mlp;
+
+typedef struct {
+    float lr, beta1, beta2, eps, weight_decay;
+} scn_adamw;
+
+/* Kaiming-uniform weights from Philox4x32-10 (bound sqrt(6 / fan_in)), zero
+ * biases and moments, step = 0.                                              */
+int scn_mlp_init(scn_ctx *ctx, scn_mlp *net, uint64_t seed, scn_stream stream);
+
+/* logits[M][dims[4]] (FP32) of the BF16 feature rows x[M][dims[0]].  Uses a
+ * context workspace for the activations (grown on first use of a larger M). */
+int scn_mlp_forward(scn_ctx *ctx, const scn_mlp *net, const uint16_t *x, int32_t M,
+                    float *logits, scn_stream stream);
+
+/* Gradients of the mean binary cross-entropy over the labelled bins:
+ * label_bins[M][L] (int32, -1 = no label), label_tgt[M][L] (1 accepted, 0
+ * rejected); loss = mean over labels of softplus(z) - t z with z the logit of
+ * the labelled bin.  gw[l] [dims[l+1]][dims[l]], gb[l] [dims[l+1]] (FP32,
+ * caller-owned) receive dLoss/dW and dLoss/db; *loss (device) the loss.      */
+int scn_mlp_backward(scn_ctx *ctx, const scn_mlp *net, const uint16_t *x, int32_t M,
+                     const int32_t *label_bins, const float *label_tgt, int32_t L,
+                     float *const *gw, float *const *gb, float *loss, scn_stream stream);
+
+/* One AdamW step (decoupled weight decay, bias-corrected moments) on the
+ * gradients of scn_mlp_backward; refreshes the BF16 copies; ++net->step.    */
+int scn_mlp_train_step(scn_ctx *ctx, scn_mlp *net, const uint16_t *x, int32_t M,
+                       const int32_t *label_bins, const float *label_tgt, int32_t L,
+                       const scn_adamw *opt, float *loss, scn_stream stream);
+
+/* ---- learned pose proposal: state features, ranking, labels ----------- */
+
+#define SCN_HMAP_CELLS 4096 /* 64 x 64 height map of the support                */
+#define SCN_DESC 32         /* object descriptor length                          */
+#define SCN_FEATURES 4128   /* network input: height map + descriptor            */
+#define SCN_BINS 4096       /* pose bins: 32 x-cells x 16 y-cells x 8 yaw cells  */
+
+/* desc[o][32] (FP32) for every object: sphere-set moments of its template
+ * (count/256; mean, min, max, std radius; sum r^3; r^3-weighted centroid;
+ * centre covariance; AABB half extents; rest lift; resting top height;
+ * footprint radius; zeros), lengths in decimetres.                          */
+int scn_descriptors(scn_ctx *ctx, const scn_batch *b, float *desc, scn_stream stream);
+
+/* hmap[s][64][64] (FP32, metres above the support plane of the scene's first
+ * object): the state where scene s has its first n_state[s] objects placed
+ * (n_state NULL: b->n_placed).  Cell (ix, iy) is centred at
+ * (-hx + (ix+1/2) 2hx/64, -hy + (iy+1/2) 2hy/64) in the support frame; the value
+ * is the highest box top or placed-sphere surface above that point, or 0.   */
+int scn_heightmaps(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state, float *hmap,
+                   scn_stream stream);
+
+/* x[s][SCN_FEATURES] (BF16) = [10 * hmap[s], desc[obj_idx[s]]]; zeros for
+ * obj_idx[s] < 0.                                                            */
+int scn_features(scn_ctx *ctx, int32_t n, const float *hmap, const float *desc,
+                 const int32_t *obj_idx, uint16_t *x, scn_stream stream);
+
+/* bins[m][k]: the k best pose bins of logits[m][SCN_BINS] in rank order
+ * (logit descending, ties to the lower bin); rows with active[m] < 0 are left
+ * untouched (active nullable).  1 <= k <= SCN_BINS.                          */
+int scn_proposal_topk(scn_ctx *ctx, const float *logits, int32_t M, int32_t k,
+                      const int32_t *active, int32_t *bins, scn_stream stream);
+
+/* Accept / reject labels for the learned proposal (from the exact checker):
+ * for each scene s in the state with its first n_state[s] objects placed
+ * (n_state NULL: b->n_placed), L uniform candidates of the next object
+ * (counter (i, 0x20000 | round, n_state[s], s)); bins[s][i] = the candidate's
+ * pose bin, accept[s][i] = 1 if its clearance >= margin else 0.  Scenes with
+ * no next object get bins -1.                                                */
+int scn_harvest_labels(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state, int32_t L,
+                       uint64_t seed, int32_t round, float margin, int32_t *bins,
+                       float *accept, scn_stream stream);
+
+/* The whole batch with the learned proposal (Sec. IV-A loop; proposal, then
+ * uniform fallback): for each object position j, every active scene ranks the
+ * pose bins of its state with the network, its top_k bins (one pose drawn in
+ * each) are checked in rank order before the uniform attempts, and the exact
+ * check alone decides validity.  Records of proposal picks have attempt = -2
+ * and idx = rank.  Synchronous with `stream` only through its own launches. */
+int scn_generate_scenes_learned(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
+                                const scn_mlp *net, int32_t top_k, scn_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

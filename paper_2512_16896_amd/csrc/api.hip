@@ -11,23 +11,9 @@
 #include "internal.h"
 #include "scn.h"
 
-struct scn_ctx {
-    int device;
-    int lds_per_block;
-    int n_cu;
-    int64_t* d_counters;   // scn::kNumCounters int64
-    int32_t* d_order;      // longest-first scene order workspace
-    int32_t* d_hist;       // its bucket counters
-    int order_cap;
-    struct Tuned { int schedule; float ms; };
-    std::map<std::string, Tuned> tuned;   // autotuned schedule per batch shape bucket
-};
+static thread_local std::string g_err;
 
-namespace {
-
-thread_local std::string g_err;
-
-int fail(int code, const char* fmt, ...) {
+int scn_fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -37,18 +23,28 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-#define SCN_HIP(call)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(SCN_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
-    } while (0)
-
-int check_ctx(scn_ctx* c) {
-    if (!c) return fail(SCN_E_INVALID_ARG, "null context");
-    if (hipSetDevice(c->device) != hipSuccess) return fail(SCN_E_HIP, "hipSetDevice failed");
+int scn_check_ctx(scn_ctx* c) {
+    if (!c) return scn_fail(SCN_E_INVALID_ARG, "null context");
+    if (hipSetDevice(c->device) != hipSuccess) return scn_fail(SCN_E_HIP, "hipSetDevice failed");
     return SCN_OK;
 }
+
+int scn_workspace(scn_ctx* c, size_t bytes, void** out) {
+    if (bytes > c->ws_bytes) {
+        if (c->ws) (void)hipFree(c->ws);
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+        SCN_HIP(hipMalloc(&c->ws, bytes));
+        c->ws_bytes = bytes;
+    }
+    *out = c->ws;
+    return SCN_OK;
+}
+
+namespace {
+
+#define fail scn_fail
+#define check_ctx scn_check_ctx
 
 int check_batch(const scn_batch* b, bool need_state) {
     if (!b) return fail(SCN_E_INVALID_ARG, "null batch");
@@ -129,6 +125,7 @@ int scn_ctx_destroy(scn_ctx* c) {
     (void)hipFree(c->d_counters);
     if (c->d_order) (void)hipFree(c->d_order);
     if (c->d_hist) (void)hipFree(c->d_hist);
+    if (c->ws) (void)hipFree(c->ws);
     delete c;
     return SCN_OK;
 }
@@ -299,6 +296,19 @@ int scn_place_step(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int32_t* cho
     scn::PlacePlan plan;
     if (int r = plan_place(c, b, a, 1, &plan)) return r;
     return run_place(c, b, a, plan, chosen, false, (hipStream_t)stream);
+}
+
+// Plan + launch of the fused place kernel with an optional proposal list
+// (used by the learned generation pipeline; not part of the ABI).
+__attribute__((visibility("hidden"))) int scn_place_internal(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps,
+                       int32_t* chosen, bool reset, const int32_t* prop_bins, int prop_k,
+                       hipStream_t st) {
+    if (int r = check_batch(b, true)) return r;
+    scn::PlacePlan plan;
+    if (int r = plan_place(c, b, a, max_steps, &plan)) return r;
+    plan.prop_bins = prop_bins;
+    plan.prop_k = prop_bins ? prop_k : 0;
+    return run_place(c, b, a, plan, chosen, reset, st);
 }
 
 int scn_generate_scenes(scn_ctx* c, scn_batch* b, const scn_gen_args* a, scn_stream stream) {

@@ -4,7 +4,39 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <string>
+
 #include "scn.h"
+
+// The library context (opaque in scn.h).
+struct scn_ctx {
+    int device;
+    int lds_per_block;
+    int n_cu;
+    int64_t* d_counters;   // scn::kNumCounters int64
+    int32_t* d_order;      // longest-first scene order workspace
+    int32_t* d_hist;       // its bucket counters
+    int order_cap;
+    void* ws;              // grow-only workspace arena (network activations, staging)
+    size_t ws_bytes;
+    struct Tuned { int schedule; float ms; };
+    std::map<std::string, Tuned> tuned;   // autotuned schedule per batch shape bucket
+};
+
+// Error reporting shared by the host files: records a message for
+// scn_last_error() and returns `code`.
+int scn_fail(int code, const char* fmt, ...);
+int scn_check_ctx(scn_ctx* c);
+// Context workspace of at least `bytes` (grown with hipMalloc when needed).
+int scn_workspace(scn_ctx* c, size_t bytes, void** out);
+
+#define SCN_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return scn_fail(SCN_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
 
 namespace scn {
 
@@ -32,7 +64,25 @@ struct PlacePlan {
     int split_sph;    // split mode: largest scene (in spheres) kept in LDS
     int cap_obj;      // objects a scene may hold
     int max_steps;    // objects to place per scene in this launch (<= 0: all)
+    const int32_t* prop_bins = nullptr;  // learned proposal: [n_scenes][prop_k] bins, rank order
+    int prop_k = 0;
 };
+
+// learned-proposal kernels (learned.hip)
+hipError_t launch_descriptor(const scn_batch& b, float* desc, hipStream_t st);
+hipError_t launch_hmap_boxes(const scn_batch& b, float* hmap, hipStream_t st);
+hipError_t launch_hmap_raise(const scn_batch& b, const int32_t* obj_idx, const int32_t* n_state,
+                             float* hmap, hipStream_t st);
+hipError_t launch_next_object(const scn_batch& b, int32_t* obj_idx, hipStream_t st);
+hipError_t launch_last_object(const scn_batch& b, const int32_t* before, int32_t* obj_idx,
+                              hipStream_t st);
+hipError_t launch_features(int n, const float* hmap, const float* desc, const int32_t* obj_idx,
+                           int ld, void* x, hipStream_t st);
+hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active, int32_t* bins,
+                       hipStream_t st);
+hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,
+                          int round, float margin, int32_t* bins, float* accept, hipStream_t st);
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t st);
 
 hipError_t launch_reset(const scn_batch& b, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int n, int64_t v, hipStream_t st);
@@ -46,6 +96,25 @@ hipError_t launch_place(const scn_batch& b, const scn_gen_args& a, const PlacePl
 // Longest-first scene order: a counting sort of the scenes by an estimate of
 // their placement work.  hist needs kOrderBuckets + 1 int32 of device memory.
 constexpr int kOrderBuckets = 256;
+// network kernels (mlp.hip)
+hipError_t launch_gemm(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
+                       const float* bias, bool relu, float* C32, void* C16, int ldc,
+                       hipStream_t st);
+hipError_t launch_transpose_bf16(int rows, int cols, const void* in, int ldi, void* out, int ldo,
+                                 hipStream_t st);
+hipError_t launch_f32_to_bf16(int n, const float* in, void* out, hipStream_t st);
+hipError_t launch_bce(int M, int N, int L, const float* z, const int32_t* bins, const float* tgt,
+                      float inv_count, float* dz32, float* loss, hipStream_t st);
+hipError_t launch_relu_bwd(int n, const float* da, const void* act, void* dp, hipStream_t st);
+hipError_t launch_colsum_bf16(int M, int N, const void* d, float* db, hipStream_t st);
+hipError_t launch_colsum_f32(int M, int N, const float* d, float* db, hipStream_t st);
+hipError_t launch_adamw(int rows, int cols, float* w, const float* g, float* m1, float* m2,
+                        void* wb, void* wt, float lr, float b1, float b2, float eps, float wd,
+                        float c1, float c2, hipStream_t st);
+hipError_t launch_init_layer(int rows, int cols, uint64_t seed, int layer, float* w, void* wb,
+                             void* wt, hipStream_t st);
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);
+
 hipError_t launch_longest_first(const scn_batch& b, int32_t* order, int32_t* hist,
                                 hipStream_t st);
 

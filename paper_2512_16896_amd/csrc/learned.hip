@@ -1,0 +1,423 @@
+// learned.hip -- state features, proposal ranking and label harvesting for
+// the learned pose proposal.
+//
+//   k_descriptor     32 sphere-set moments per object (object frame)
+//   k_hmap_boxes     64 x 64 height map of a scene's support from its boxes
+//   k_hmap_raise     raise the map by one placed object's spheres
+//   k_features       BF16 network input rows: [10 x height map, descriptor]
+//   k_topk           top-k pose bins per state (bitonic sort in LDS)
+//   k_harvest        uniform label candidates of a state with their bins and
+//                    accept / reject from the exact checker (distance form)
+#include <climits>
+
+#include "device.h"
+#include "internal.h"
+
+namespace scn {
+
+// ---------------------------------------------------------------------------
+// Descriptor (one wave per object; values in decimetres where lengths):
+//  0 S/256 | 1-4 mean/min/max/std radius x10 | 5 sum r^3 x1e3 |
+//  6-8 r^3-weighted centroid x10 | 9-14 centre covariance xx,yy,zz,xy,xz,yz x100 |
+//  15-17 sphere-set AABB half extents x10 | 18 rest lift x10 |
+//  19 resting top height x10 | 20 footprint radius x10 | 21-31 zero
+__global__ __launch_bounds__(64) void k_descriptor(int n_obj, const int32_t* __restrict__ sph_off,
+                                                   const float4* __restrict__ tmpl,
+                                                   float* __restrict__ desc) {
+    const int o = blockIdx.x;
+    if (o >= n_obj) return;
+    const int lane = threadIdx.x;
+    const int k0 = sph_off[o], k1 = sph_off[o + 1];
+    const int S = k1 - k0;
+    float sr = 0.f, sr2 = 0.f, rmin = 1e30f, rmax = -1e30f, v = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+    float sx = 0.f, sy = 0.f, sz = 0.f, sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
+    float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+    float lift = -1e30f, top = -1e30f, foot = 0.f;
+    for (int k = k0 + lane; k < k1; k += kWave) {
+        const float4 c = tmpl[k];
+        const float r3 = c.w * c.w * c.w;
+        sr += c.w; sr2 += c.w * c.w; rmin = fminf(rmin, c.w); rmax = fmaxf(rmax, c.w);
+        v += r3; wx += r3 * c.x; wy += r3 * c.y; wz += r3 * c.z;
+        sx += c.x; sy += c.y; sz += c.z;
+        sxx += c.x * c.x; syy += c.y * c.y; szz += c.z * c.z;
+        sxy += c.x * c.y; sxz += c.x * c.z; syz += c.y * c.z;
+        lo[0] = fminf(lo[0], c.x - c.w); hi[0] = fmaxf(hi[0], c.x + c.w);
+        lo[1] = fminf(lo[1], c.y - c.w); hi[1] = fmaxf(hi[1], c.y + c.w);
+        lo[2] = fminf(lo[2], c.z - c.w); hi[2] = fmaxf(hi[2], c.z + c.w);
+        lift = fmaxf(lift, c.w - c.z);
+        top = fmaxf(top, c.z + c.w);
+        foot = fmaxf(foot, sqrtf(c.x * c.x + c.y * c.y) + c.w);
+    }
+    auto sum = [](float x) {
+        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, kWave);
+        return x;
+    };
+    sr = sum(sr); sr2 = sum(sr2); v = sum(v); wx = sum(wx); wy = sum(wy); wz = sum(wz);
+    sx = sum(sx); sy = sum(sy); sz = sum(sz);
+    sxx = sum(sxx); syy = sum(syy); szz = sum(szz); sxy = sum(sxy); sxz = sum(sxz); syz = sum(syz);
+    rmin = wave_min(rmin); rmax = wave_max(rmax);
+    for (int d = 0; d < 3; ++d) { lo[d] = wave_min(lo[d]); hi[d] = wave_max(hi[d]); }
+    lift = wave_max(lift); top = wave_max(top); foot = wave_max(foot);
+    if (lane != 0) return;
+    float* D = desc + 32 * (size_t)o;
+    const float n = (float)(S > 0 ? S : 1);
+    const float mr = sr / n;
+    const float mx = sx / n, my = sy / n, mz = sz / n;
+    const float iv = v > 0.f ? 1.f / v : 0.f;
+    D[0] = (float)S / 256.f;
+    D[1] = 10.f * mr;
+    D[2] = 10.f * (S ? rmin : 0.f);
+    D[3] = 10.f * (S ? rmax : 0.f);
+    D[4] = 10.f * sqrtf(fmaxf(sr2 / n - mr * mr, 0.f));
+    D[5] = 1e3f * v;
+    D[6] = 10.f * wx * iv; D[7] = 10.f * wy * iv; D[8] = 10.f * wz * iv;
+    D[9] = 100.f * (sxx / n - mx * mx);
+    D[10] = 100.f * (syy / n - my * my);
+    D[11] = 100.f * (szz / n - mz * mz);
+    D[12] = 100.f * (sxy / n - mx * my);
+    D[13] = 100.f * (sxz / n - mx * mz);
+    D[14] = 100.f * (syz / n - my * mz);
+    for (int d = 0; d < 3; ++d) D[15 + d] = 10.f * 0.5f * (S ? hi[d] - lo[d] : 0.f);
+    D[18] = 10.f * (S ? lift : 0.f);
+    D[19] = 10.f * (S ? top + lift : 0.f);
+    D[20] = 10.f * foot;
+    for (int d = 21; d < 32; ++d) D[d] = 0.f;
+}
+
+hipError_t launch_descriptor(const scn_batch& b, float* desc, hipStream_t st) {
+    if (b.n_objects == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_descriptor, dim3(b.n_objects), dim3(64), 0, st, b.n_objects, b.sph_off,
+                       (const float4*)b.tmpl, desc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Height map of scene s over its first object's support: cell (ix, iy), ix
+// along x in [0,64), iy along y, centre (-hx + (ix + 1/2) 2hx/64, -hy + ...);
+// value = max(0, box tops, sphere tops) above the support plane, metres.
+// A box covers a cell when the cell centre at the box centre's height lies in
+// the box's x/y extent (box frame); its top is the box's highest point.
+// A sphere (support-frame centre p, radius r) covers a cell when the cell
+// centre is within r of p in x/y; its top there is p_z + sqrt(r^2 - d^2).
+struct SupportFrame {
+    float R[9], t[3], hx, hy;
+};
+__device__ __forceinline__ SupportFrame scene_support(const int32_t* __restrict__ obj_off,
+                                                      const int32_t* __restrict__ obj_sup,
+                                                      const float* __restrict__ sup, int s) {
+    SupportFrame F;
+    const int o = obj_off[s] < obj_off[s + 1] ? obj_off[s] : -1;
+    const float* p = sup + 16 * (o >= 0 ? obj_sup[o] : 0);
+    for (int i = 0; i < 9; ++i) F.R[i] = p[i];
+    F.t[0] = p[9]; F.t[1] = p[10]; F.t[2] = p[11];
+    F.hx = p[12]; F.hy = p[13];
+    return F;
+}
+// world point -> support frame: R^T (p - t)
+__device__ __forceinline__ void to_support(const SupportFrame& F, float x, float y, float z,
+                                           float& sx, float& sy, float& sz) {
+    const float dx = x - F.t[0], dy = y - F.t[1], dz = z - F.t[2];
+    sx = F.R[0] * dx + F.R[3] * dy + F.R[6] * dz;
+    sy = F.R[1] * dx + F.R[4] * dy + F.R[7] * dz;
+    sz = F.R[2] * dx + F.R[5] * dy + F.R[8] * dz;
+}
+
+__global__ __launch_bounds__(256) void k_hmap_boxes(
+    int n, const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
+    const float* __restrict__ sup, const int32_t* __restrict__ box_off,
+    const float* __restrict__ box, float* __restrict__ hmap) {
+    const int s = blockIdx.x;
+    if (s >= n) return;
+    const SupportFrame F = scene_support(obj_off, obj_sup, sup, s);
+    const int b0 = box_off[s], b1 = box_off[s + 1];
+    for (int cell = threadIdx.x; cell < 4096; cell += blockDim.x) {
+        const int ix = cell >> 6, iy = cell & 63;
+        const float cx = -F.hx + (ix + 0.5f) * (2.f * F.hx / 64.f);
+        const float cy = -F.hy + (iy + 0.5f) * (2.f * F.hy / 64.f);
+        float h = 0.f;
+        for (int b = b0; b < b1; ++b) {
+            const float* B = box + 16 * b;
+            // box centre and axes in the support frame
+            float bcx, bcy, bcz;
+            to_support(F, B[9], B[10], B[11], bcx, bcy, bcz);
+            float ax[3][3];   // ax[a] = support-frame direction of box axis a
+            for (int a = 0; a < 3; ++a) {
+                float ux, uy, uz;
+                ux = F.R[0] * B[a] + F.R[3] * B[3 + a] + F.R[6] * B[6 + a];
+                uy = F.R[1] * B[a] + F.R[4] * B[3 + a] + F.R[7] * B[6 + a];
+                uz = F.R[2] * B[a] + F.R[5] * B[3 + a] + F.R[8] * B[6 + a];
+                ax[a][0] = ux; ax[a][1] = uy; ax[a][2] = uz;
+            }
+            const float dx = cx - bcx, dy = cy - bcy;   // at the centre's height
+            const float qx = ax[0][0] * dx + ax[0][1] * dy;
+            const float qy = ax[1][0] * dx + ax[1][1] * dy;
+            if (fabsf(qx) <= B[12] && fabsf(qy) <= B[13]) {
+                const float topz = bcz + fabsf(ax[0][2]) * B[12] + fabsf(ax[1][2]) * B[13] +
+                                   fabsf(ax[2][2]) * B[14];
+                h = fmaxf(h, topz);
+            }
+        }
+        hmap[(size_t)s * 4096 + cell] = h;
+    }
+}
+
+// Raise the height map of each scene by its object obj_idx[s] (-1: none),
+// whose world spheres are in placed.  One wave per scene, one sphere per lane
+// at a time; monotone max through integer atomics on non-negative floats.
+__global__ __launch_bounds__(64) void k_hmap_raise(
+    int n, const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
+    const float* __restrict__ sup, const int32_t* __restrict__ sph_off,
+    const float4* __restrict__ placed, const int32_t* __restrict__ obj_idx,
+    const int32_t* __restrict__ n_state, float* __restrict__ hmap) {
+    const int s = blockIdx.x;
+    if (s >= n) return;
+    // one object (obj_idx) or the scene's first n_state[s] objects
+    int k0, k1;
+    if (n_state) {
+        const int m = min(max(n_state[s], 0), obj_off[s + 1] - obj_off[s]);
+        k0 = sph_off[obj_off[s]];
+        k1 = sph_off[obj_off[s] + m];
+    } else {
+        const int o = obj_idx[s];
+        if (o < obj_off[s] || o >= obj_off[s + 1]) return;
+        k0 = sph_off[o];
+        k1 = sph_off[o + 1];
+    }
+    const SupportFrame F = scene_support(obj_off, obj_sup, sup, s);
+    const float cw = 2.f * F.hx / 64.f, ch = 2.f * F.hy / 64.f;
+    int* H = (int*)(hmap + (size_t)s * 4096);
+    for (int k = k0 + threadIdx.x; k < k1; k += kWave) {
+        const float4 q = placed[k];
+        float px, py, pz;
+        to_support(F, q.x, q.y, q.z, px, py, pz);
+        const float r = q.w;
+        // cells whose centre can lie within r of (px, py)
+        const int ix0 = max(0, (int)floorf((px - r + F.hx) / cw - 0.5f));
+        const int ix1 = min(63, (int)ceilf((px + r + F.hx) / cw - 0.5f));
+        const int iy0 = max(0, (int)floorf((py - r + F.hy) / ch - 0.5f));
+        const int iy1 = min(63, (int)ceilf((py + r + F.hy) / ch - 0.5f));
+        for (int ix = ix0; ix <= ix1; ++ix) {
+            const float cx = -F.hx + (ix + 0.5f) * cw;
+            for (int iy = iy0; iy <= iy1; ++iy) {
+                const float cy = -F.hy + (iy + 0.5f) * ch;
+                const float d2 = (cx - px) * (cx - px) + (cy - py) * (cy - py);
+                if (d2 < r * r) {
+                    const float top = pz + sqrtf(r * r - d2);
+                    if (top > 0.f) atomicMax(H + ix * 64 + iy, __float_as_int(top));
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_hmap_boxes(const scn_batch& b, float* hmap, hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hmap_boxes, dim3(b.n_scenes), dim3(256), 0, st, b.n_scenes, b.obj_off,
+                       b.obj_sup, b.sup, b.box_off, b.box, hmap);
+    return hipGetLastError();
+}
+
+hipError_t launch_hmap_raise(const scn_batch& b, const int32_t* obj_idx, const int32_t* n_state,
+                             float* hmap, hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hmap_raise, dim3(b.n_scenes), dim3(64), 0, st, b.n_scenes, b.obj_off,
+                       b.obj_sup, b.sup, b.sph_off, (const float4*)b.placed, obj_idx, n_state,
+                       hmap);
+    return hipGetLastError();
+}
+
+// The object each scene places next (n_placed[s]) if the scene is active, else -1.
+__global__ void k_next_object(int n, const int32_t* __restrict__ obj_off,
+                              const int32_t* __restrict__ n_placed,
+                              const int8_t* __restrict__ status, int32_t* __restrict__ obj_idx) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int o = obj_off[s] + n_placed[s];
+    obj_idx[s] = (status[s] == SCN_SCENE_ACTIVE && o < obj_off[s + 1]) ? o : -1;
+}
+
+hipError_t launch_next_object(const scn_batch& b, int32_t* obj_idx, hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_next_object, dim3((b.n_scenes + 255) / 256), dim3(256), 0, st, b.n_scenes,
+                       b.obj_off, b.n_placed, b.status, obj_idx);
+    return hipGetLastError();
+}
+
+// The most recently placed object of each scene: obj_off[s] + n_placed[s] - 1
+// when that is at least `first_new` objects into the scene (else -1).
+__global__ void k_last_object(int n, const int32_t* __restrict__ obj_off,
+                              const int32_t* __restrict__ n_placed, int32_t* __restrict__ obj_idx,
+                              const int32_t* __restrict__ before) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    obj_idx[s] = n_placed[s] > before[s] ? obj_off[s] + n_placed[s] - 1 : -1;
+}
+
+hipError_t launch_last_object(const scn_batch& b, const int32_t* before, int32_t* obj_idx,
+                              hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_last_object, dim3((b.n_scenes + 255) / 256), dim3(256), 0, st, b.n_scenes,
+                       b.obj_off, b.n_placed, obj_idx, before);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_i32, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Feature rows x[s] = [10 * hmap[s] (4096), desc[obj_idx[s]] (32)] as BF16;
+// zeros for scenes with obj_idx < 0.  Row length ld >= 4128.
+__global__ __launch_bounds__(256) void k_features(int n, const float* __restrict__ hmap,
+                                                 const float* __restrict__ desc,
+                                                 const int32_t* __restrict__ obj_idx, int ld,
+                                                 __bf16* __restrict__ x) {
+    const int s = blockIdx.x;
+    if (s >= n) return;
+    const int o = obj_idx[s];
+    __bf16* row = x + (size_t)s * ld;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+        float v = 0.f;
+        if (o >= 0) {
+            if (i < 4096) v = 10.f * hmap[(size_t)s * 4096 + i];
+            else if (i < 4128) v = desc[32 * (size_t)o + (i - 4096)];
+        }
+        row[i] = (__bf16)v;
+    }
+}
+
+hipError_t launch_features(int n, const float* hmap, const float* desc, const int32_t* obj_idx,
+                           int ld, void* x, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_features, dim3(n), dim3(256), 0, st, n, hmap, desc, obj_idx, ld,
+                       (__bf16*)x);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Top-k bins per row of logits [M][4096] (k <= 4096): bins in rank order
+// (logit descending, ties to the lower bin).  Rows with active[m] == 0 are
+// skipped (active may be nullptr).  One workgroup of 1024 threads per row; a
+// bitonic sort of 4096 64-bit keys in LDS.
+__device__ __forceinline__ unsigned orderable(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ __launch_bounds__(1024) void k_topk(int M, const float* __restrict__ logits, int k,
+                                               const int32_t* __restrict__ active,
+                                               int32_t* __restrict__ bins) {
+    __shared__ unsigned long long key[4096];
+    const int m = blockIdx.x;
+    if (m >= M) return;
+    if (active && active[m] < 0) return;
+    const float* z = logits + (size_t)m * 4096;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
+        float v = z[i];
+        if (v != v) v = -__builtin_huge_valf();   // NaN ranks last
+        // larger key = better: logit first, then the lower bin
+        key[i] = ((unsigned long long)orderable(v) << 32) | (unsigned)(4095 - i);
+    }
+    __syncthreads();
+    // bitonic sort, descending
+    for (int size = 2; size <= 4096; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool desc = (i & size) == 0;
+                    const unsigned long long a = key[i], b = key[j];
+                    if (desc ? (a < b) : (a > b)) { key[i] = b; key[j] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < k; i += blockDim.x)
+        bins[(size_t)m * k + i] = 4095 - (int)(key[i] & 0xFFFFFFFFu);
+}
+
+hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active, int32_t* bins,
+                       hipStream_t st) {
+    if (M == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_topk, dim3(M), dim3(1024), 0, st, M, logits, k, active, bins);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Label harvesting.  For every scene s with obj_idx[s] >= 0, L uniform
+// candidates of that object (Philox tag 2 in the attempt word: counter
+// (i, 0x20000 | round, step, s)) are checked exactly against the scene's boxes
+// and its first n_placed[s] objects; bins[s][i] receives the pose bin and
+// accept[s][i] 1 (collision-free) or 0.  Lane per candidate, wave-uniform
+// obstacles (like the dense checker).
+__global__ __launch_bounds__(64) void k_harvest(
+    const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
+    const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
+    const float* __restrict__ sup, const int32_t* __restrict__ box_off,
+    const float* __restrict__ box, const float4* __restrict__ placed,
+    const int32_t* __restrict__ n_state, int L, uint64_t seed, int round, float margin,
+    int32_t* __restrict__ bins_out, float* __restrict__ accept_out) {
+    const int s = blockIdx.x;
+    const int i = blockIdx.y * 64 + threadIdx.x;
+    const int o = obj_off[s] + max(n_state[s], 0);   // the next object of the state
+    if (o >= obj_off[s + 1]) {
+        if (i < L) { bins_out[(size_t)s * L + i] = -1; accept_out[(size_t)s * L + i] = 0.f; }
+        return;
+    }
+    const int ii = i < L ? i : L - 1;
+    const Support U = load_support(sup, obj_sup[o]);
+    float lift = -1e30f;
+    for (int k = sph_off[o]; k < sph_off[o + 1]; ++k) lift = fmaxf(lift, tmpl[k].w - tmpl[k].z);
+    const int j = o - obj_off[s];
+    const U4 w = philox10(U4{(uint32_t)ii, 0x20000u | (uint32_t)round, (uint32_t)j, (uint32_t)s},
+                          (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float u0 = unit01(w.a), u1 = unit01(w.b), u2 = unit01(w.c);
+    Pose P;
+    P.x = (U.hx - U.inset) * signed_unit(w.a);
+    P.y = (U.hy - U.inset) * signed_unit(w.b);
+    P.yaw = 6.28318530717958647692f * u2;
+    sincospif(2.0f * u2, &P.s, &P.c);
+    P.z = U.lift + lift;
+    const int bin = (min((int)(u0 * 32.f), 31) * 16 + min((int)(u1 * 16.f), 15)) * 8 +
+                    min((int)(u2 * 8.f), 7);
+    const int first = sph_off[obj_off[s]];
+    const int pl_end = sph_off[o];   // the state's placed objects precede o
+    float clr = __builtin_huge_valf();
+    for (int k = sph_off[o]; k < sph_off[o + 1]; ++k) {
+        const float4 c = tmpl[k];
+        float wx, wy, wz;
+        to_world(U, P, c.x, c.y, c.z, wx, wy, wz);
+        float best = __builtin_huge_valf();
+        for (int bx = box_off[s]; bx < box_off[s + 1]; ++bx)
+            best = fminf(best, box_sdf(box + 16 * bx, wx, wy, wz));
+        for (int q = first; q < pl_end; ++q) {
+            const float4 p = placed[q];
+            const float dx = wx - p.x, dy = wy - p.y, dz = wz - p.z;
+            best = fminf(best, __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) - p.w);
+        }
+        clr = fminf(clr, best - c.w);
+    }
+    if (i < L) {
+        bins_out[(size_t)s * L + i] = bin;
+        accept_out[(size_t)s * L + i] = clr >= margin ? 1.f : 0.f;
+    }
+}
+
+hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,
+                          int round, float margin, int32_t* bins, float* accept, hipStream_t st) {
+    if (b.n_scenes == 0 || L <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_harvest, dim3(b.n_scenes, (L + 63) / 64), dim3(64), 0, st, b.obj_off,
+                       b.sph_off, (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box,
+                       (const float4*)b.placed, n_state, L, seed, round, margin, bins, accept);
+    return hipGetLastError();
+}
+
+}  // namespace scn

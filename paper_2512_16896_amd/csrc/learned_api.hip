@@ -1,0 +1,142 @@
+// learned_api.hip -- C ABI of the learned pose proposal: state features,
+// ranking, label harvesting and the learned generation pipeline.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "scn.h"
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int check_scenes(const scn_batch* b) {
+    if (!b) return scn_fail(SCN_E_INVALID_ARG, "null batch");
+    if (b->n_scenes < 0 || b->n_objects < 0) return scn_fail(SCN_E_INVALID_ARG, "negative sizes");
+    if (b->n_scenes > 0 && (!b->obj_off || !b->box_off || !b->sup || !b->obj_sup))
+        return scn_fail(SCN_E_INVALID_ARG, "obj_off/box_off/sup/obj_sup required");
+    if (b->n_objects > 0 && (!b->sph_off || !b->tmpl))
+        return scn_fail(SCN_E_INVALID_ARG, "sph_off/tmpl required");
+    if (b->n_boxes > 0 && !b->box) return scn_fail(SCN_E_INVALID_ARG, "box required");
+    return SCN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int scn_descriptors(scn_ctx* c, const scn_batch* b, float* desc, scn_stream stream) {
+    if (int r = scn_check_ctx(c)) return r;
+    if (int r = check_scenes(b)) return r;
+    if (b->n_objects > 0 && !desc) return scn_fail(SCN_E_INVALID_ARG, "desc required");
+    SCN_HIP(scn::launch_descriptor(*b, desc, (hipStream_t)stream));
+    return SCN_OK;
+}
+
+int scn_heightmaps(scn_ctx* c, const scn_batch* b, const int32_t* n_state, float* hmap,
+                   scn_stream stream) {
+    if (int r = scn_check_ctx(c)) return r;
+    if (int r = check_scenes(b)) return r;
+    if (b->n_scenes == 0) return SCN_OK;
+    if (!hmap) return scn_fail(SCN_E_INVALID_ARG, "hmap required");
+    const int32_t* ns = n_state ? n_state : b->n_placed;
+    if (!ns || !b->placed) return scn_fail(SCN_E_INVALID_ARG, "n_state (or n_placed) and placed required");
+    const hipStream_t st = (hipStream_t)stream;
+    SCN_HIP(scn::launch_hmap_boxes(*b, hmap, st));
+    SCN_HIP(scn::launch_hmap_raise(*b, nullptr, ns, hmap, st));
+    return SCN_OK;
+}
+
+int scn_features(scn_ctx* c, int32_t n, const float* hmap, const float* desc,
+                 const int32_t* obj_idx, uint16_t* x, scn_stream stream) {
+    if (int r = scn_check_ctx(c)) return r;
+    if (n < 0) return scn_fail(SCN_E_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && (!hmap || !desc || !obj_idx || !x))
+        return scn_fail(SCN_E_INVALID_ARG, "hmap, desc, obj_idx and x required");
+    SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, (hipStream_t)stream));
+    return SCN_OK;
+}
+
+int scn_proposal_topk(scn_ctx* c, const float* logits, int32_t M, int32_t k,
+                      const int32_t* active, int32_t* bins, scn_stream stream) {
+    if (int r = scn_check_ctx(c)) return r;
+    if (M < 0 || k < 1 || k > SCN_BINS) return scn_fail(SCN_E_INVALID_ARG, "bad M or k");
+    if (M > 0 && (!logits || !bins)) return scn_fail(SCN_E_INVALID_ARG, "logits and bins required");
+    SCN_HIP(scn::launch_topk(M, logits, k, active, bins, (hipStream_t)stream));
+    return SCN_OK;
+}
+
+int scn_harvest_labels(scn_ctx* c, const scn_batch* b, const int32_t* n_state, int32_t L,
+                       uint64_t seed, int32_t round, float margin, int32_t* bins, float* accept,
+                       scn_stream stream) {
+    if (int r = scn_check_ctx(c)) return r;
+    if (int r = check_scenes(b)) return r;
+    if (L <= 0 || round < 0 || round > 0xFFFF || !(margin >= 0.f))
+        return scn_fail(SCN_E_INVALID_ARG, "bad L, round or margin");
+    if (b->n_scenes == 0) return SCN_OK;
+    const int32_t* ns = n_state ? n_state : b->n_placed;
+    if (!ns || !b->placed || !bins || !accept)
+        return scn_fail(SCN_E_INVALID_ARG, "n_state (or n_placed), placed, bins and accept required");
+    if (L > 65535 * 64) return scn_fail(SCN_E_UNSUPPORTED, "L too large");
+    SCN_HIP(scn::launch_harvest(*b, ns, L, seed, round, margin, bins, accept, (hipStream_t)stream));
+    return SCN_OK;
+}
+
+// Defined in api.hip: plan and launch of the fused place kernel.
+__attribute__((visibility("hidden"))) int scn_place_internal(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps,
+                       int32_t* chosen, bool reset, const int32_t* prop_bins, int prop_k,
+                       hipStream_t st);
+
+int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
+                                const scn_mlp* net, int32_t top_k, scn_stream stream) {
+    if (int r = scn_check_ctx(c)) return r;
+    if (int r = check_scenes(b)) return r;
+    if (!a || !net) return scn_fail(SCN_E_INVALID_ARG, "args and network required");
+    if (top_k < 1 || top_k > SCN_BINS) return scn_fail(SCN_E_INVALID_ARG, "top_k out of range");
+    if (net->dims[0] != SCN_FEATURES || net->dims[SCN_MLP_LAYERS] != SCN_BINS)
+        return scn_fail(SCN_E_INVALID_ARG, "network must map %d features to %d bins",
+                        SCN_FEATURES, SCN_BINS);
+    if (!b->placed || !b->n_placed || !b->status || !b->rec)
+        return scn_fail(SCN_E_INVALID_ARG, "placed/n_placed/status/rec required");
+    const hipStream_t st = (hipStream_t)stream;
+    const int n = b->n_scenes;
+    if (n == 0) return SCN_OK;
+    int hidden = 0;
+    for (int l = 1; l < SCN_MLP_LAYERS; ++l) hidden = net->dims[l] > hidden ? net->dims[l] : hidden;
+    // pipeline buffers, after the network's own activation space
+    const size_t act = 3 * align256((size_t)n * hidden * 2) + 256;
+    const size_t bytes = act + align256((size_t)n * SCN_HMAP_CELLS * 4) +
+                         align256((size_t)b->n_objects * SCN_DESC * 4) +
+                         align256((size_t)n * SCN_FEATURES * 2) + align256((size_t)n * SCN_BINS * 4) +
+                         align256((size_t)n * top_k * 4) + 3 * align256((size_t)n * 4);
+    void* ws;
+    if (int r = scn_workspace(c, bytes, &ws)) return r;
+    char* p = (char*)ws + act;
+    auto take = [&](size_t sz) { void* q = p; p += align256(sz); return q; };
+    float* hmap = (float*)take((size_t)n * SCN_HMAP_CELLS * 4);
+    float* desc = (float*)take((size_t)b->n_objects * SCN_DESC * 4);
+    uint16_t* x = (uint16_t*)take((size_t)n * SCN_FEATURES * 2);
+    float* logits = (float*)take((size_t)n * SCN_BINS * 4);
+    int32_t* bins = (int32_t*)take((size_t)n * top_k * 4);
+    int32_t* obj_idx = (int32_t*)take((size_t)n * 4);
+    int32_t* before = (int32_t*)take((size_t)n * 4);
+    int32_t* placed_now = (int32_t*)take((size_t)n * 4);
+
+    SCN_HIP(scn::launch_reset(*b, st));
+    SCN_HIP(scn::launch_descriptor(*b, desc, st));
+    SCN_HIP(scn::launch_hmap_boxes(*b, hmap, st));
+    const int steps = a->max_steps > 0 && a->max_steps < b->max_objects_per_scene
+                          ? a->max_steps : b->max_objects_per_scene;
+    for (int j = 0; j < steps; ++j) {
+        SCN_HIP(scn::launch_next_object(*b, obj_idx, st));
+        SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, st));
+        if (int r = scn_mlp_forward(c, net, x, n, logits, stream)) return r;
+        SCN_HIP(scn::launch_topk(n, logits, top_k, obj_idx, bins, st));
+        SCN_HIP(scn::launch_copy_i32(b->n_placed, before, n, st));
+        if (int r = scn_place_internal(c, b, a, 1, nullptr, false, bins, top_k, st)) return r;
+        SCN_HIP(scn::launch_last_object(*b, before, placed_now, st));
+        SCN_HIP(scn::launch_hmap_raise(*b, placed_now, nullptr, hmap, st));
+    }
+    return SCN_OK;
+}
+
+}  // extern "C"

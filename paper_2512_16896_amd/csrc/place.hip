@@ -31,6 +31,37 @@
 
 namespace scn {
 
+// Pose of entry g of an object's candidate list.  Entries 0..prop_k-1 are the
+// learned proposal's bins in rank order: one pose drawn uniformly inside the
+// bin (x cell, y cell, yaw cell of the 32 x 16 x 8 grid) with Philox counter
+// (rank, 0x10000, j, s); the entries after them are the uniform attempts, entry
+// prop_k + a C + i being candidate i of attempt a (counter (i, a, j, s)).
+__device__ __forceinline__ Pose entry_pose(int g, int prop_k, const int32_t* __restrict__ bins,
+                                           int C, uint64_t seed, uint32_t s, uint32_t j, float ax,
+                                           float ay, float zc, int* att, int* idx) {
+    if (g < prop_k) {
+        const int bin = min(max(bins[g], 0), 4095);
+        const U4 w = philox10(U4{(uint32_t)g, 0x10000u, j, s}, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const float u0 = ((float)(bin >> 7) + unit01(w.a)) * (1.f / 32.f);
+        const float u1 = ((float)((bin >> 3) & 15) + unit01(w.b)) * (1.f / 16.f);
+        const float u2 = ((float)(bin & 7) + unit01(w.c)) * (1.f / 8.f);
+        Pose p;
+        p.x = ax * fmaf(2.f, u0, -1.f);
+        p.y = ay * fmaf(2.f, u1, -1.f);
+        p.yaw = 6.28318530717958647692f * u2;
+        sincospif(2.0f * u2, &p.s, &p.c);
+        p.z = zc;
+        *att = -2;
+        *idx = g;
+        return p;
+    }
+    const int e = g - prop_k;
+    const int a = e / C, i = e - a * C;
+    *att = a;
+    *idx = i;
+    return sample_pose(seed, s, j, (uint32_t)a, (uint32_t)i, ax, ay, zc);
+}
+
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int lane) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
@@ -53,7 +84,7 @@ __global__ __launch_bounds__(1024) void k_place(
     scn_pose_rec* __restrict__ rec, int32_t* __restrict__ chosen,
     unsigned long long* __restrict__ counters, const int32_t* __restrict__ order, uint64_t seed,
     float margin, int retries, int default_ncand, int max_steps, int cap_sph, int cap_obj,
-    int split, int split_sph) {
+    int split, int split_sph, const int32_t* __restrict__ prop_bins, int prop_k) {
     extern __shared__ float4 lds[];
     float4* lsph = lds;                        // placed spheres: (x, y, z, r + margin)
     float4* lbnd = lds + (kLds ? cap_sph : 0); // world bounding sphere of each placed object
@@ -179,7 +210,10 @@ __global__ __launch_bounds__(1024) void k_place(
         const Support U = load_support(sup, obj_sup[o]);
         const float ax = U.hx - U.inset, ay = U.hy - U.inset, zc = U.lift + lift;
         const int C = obj_ncand ? obj_ncand[o] : default_ncand;
-        const int total = C > 0 ? (retries + 1) * C : 0;   // entries (attempt, index)
+        // proposals of this scene (only when it has them this step)
+        const int pk = prop_bins ? prop_k : 0;
+        const int32_t* pb = prop_bins ? prop_bins + (size_t)s * prop_k : nullptr;
+        const int total = pk + (C > 0 ? (retries + 1) * C : 0);   // entries of the list
         const int nob_mask = min(j, kWave);                 // objects covered by the masks
 
         if (threadIdx.x == 0) s_best = INT_MAX;
@@ -242,10 +276,9 @@ __global__ __launch_bounds__(1024) void k_place(
             // ---- batch phase: lane t holds candidate entry wave + W (base + t) ----
             const int g = wave + W * (base + lane);
             const bool live = g < total;
-            const int ga = live ? g / C : 0;
-            const int gi = live ? g - ga * C : 0;
-            const Pose L = sample_pose(seed, (uint32_t)s, (uint32_t)j, (uint32_t)ga, (uint32_t)gi,
-                                       ax, ay, zc);
+            int ga, gi;
+            const Pose L = entry_pose(live ? g : 0, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
+                                      ay, zc, &ga, &gi);
             float lx, ly, lz;   // world centre of this candidate's bounding sphere
             to_world(U, L, bc[0], bc[1], bc[2], lx, ly, lz);
             unsigned long long bmask = 0, omask = 0;
@@ -329,12 +362,16 @@ __global__ __launch_bounds__(1024) void k_place(
         }
         __syncthreads();
         const int best = s_best;
-        if (wave == 0) n_att += best == INT_MAX ? (unsigned)(retries + 1) : (unsigned)(best / C + 1);
+        if (wave == 0)
+            n_att += (pk ? 1u : 0u) +
+                     (best == INT_MAX ? (unsigned)(retries + 1)
+                                      : (best < pk ? 0u : (unsigned)((best - pk) / C + 1)));
         if (best == INT_MAX) { fin = SCN_SCENE_INVALID; last = -1; break; }
-        const int fa = best / C, fi = best - fa * C;
+        int fa, fi;
+        const Pose Pw = entry_pose(best, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax, ay, zc,
+                                   &fa, &fi);
         if (wave == 0) {
-            const Pose P = sample_pose(seed, (uint32_t)s, (uint32_t)j, (uint32_t)fa, (uint32_t)fi,
-                                       ax, ay, zc);
+            const Pose P = Pw;
 #pragma unroll
             for (int q = 0; q < SPL; ++q) {
                 if (act[q]) {
@@ -393,7 +430,8 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                        b.sph_off, (const float4*)b.tmpl, b.obj_sup, b.obj_ncand, b.sup,
                        b.box_off, b.box, (float4*)b.placed, b.n_placed, b.status, b.rec, chosen,
                        ctr, plan.order, a.seed, a.margin, a.retries, a.default_ncand,
-                       plan.max_steps, cap_sph, plan.cap_obj, split, plan.split_sph);
+                       plan.max_steps, cap_sph, plan.cap_obj, split, plan.split_sph,
+                       plan.prop_bins, plan.prop_k);
     return hipGetLastError();
 }
 

@@ -65,6 +65,21 @@ class Counters(C.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}
 
 
+N_LAYERS = 4
+FEATURES, BINS, DESC, HMAP_CELLS = 4128, 4096, 32, 4096
+
+
+class Mlp(C.Structure):
+    _fields_ = [("dims", C.c_int32 * (N_LAYERS + 1))] + \
+        [(n, C.c_void_p * N_LAYERS) for n in ("w", "b", "wb", "wt", "m_w", "v_w", "m_b", "v_b")] + \
+        [("step", C.c_int64)]
+
+
+class AdamW(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -85,6 +100,17 @@ def _load():
                          C.POINTER(C.c_float), vp],
         "scn_autotune_save": [vp, C.c_char_p],
         "scn_autotune_load": [vp, C.c_char_p],
+        "scn_mlp_init": [vp, C.POINTER(Mlp), u64, vp],
+        "scn_mlp_forward": [vp, C.POINTER(Mlp), vp, i32, vp, vp],
+        "scn_mlp_backward": [vp, C.POINTER(Mlp), vp, i32, vp, vp, i32, vp, vp, vp, vp],
+        "scn_mlp_train_step": [vp, C.POINTER(Mlp), vp, i32, vp, vp, i32, C.POINTER(AdamW), vp, vp],
+        "scn_descriptors": [vp, C.POINTER(_Batch), vp, vp],
+        "scn_heightmaps": [vp, C.POINTER(_Batch), vp, vp, vp],
+        "scn_features": [vp, i32, vp, vp, vp, vp, vp],
+        "scn_proposal_topk": [vp, vp, i32, i32, vp, vp, vp],
+        "scn_harvest_labels": [vp, C.POINTER(_Batch), vp, i32, u64, i32, f32, vp, vp, vp],
+        "scn_generate_scenes_learned": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs),
+                                        C.POINTER(Mlp), i32, vp],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -102,7 +128,10 @@ _lib = _load()
 EXPORTS = ("scn_ctx_create", "scn_ctx_destroy", "scn_status_string", "scn_last_error",
            "scn_reset_counters", "scn_read_counters", "scn_sample_poses", "scn_check_batch",
            "scn_reset_scenes", "scn_place_step", "scn_generate_scenes", "scn_autotune",
-           "scn_autotune_save", "scn_autotune_load")
+           "scn_autotune_save", "scn_autotune_load", "scn_mlp_init", "scn_mlp_forward",
+           "scn_mlp_backward", "scn_mlp_train_step", "scn_descriptors", "scn_heightmaps",
+           "scn_features", "scn_proposal_topk", "scn_harvest_labels",
+           "scn_generate_scenes_learned")
 
 SCHED_LONGEST_FIRST = 0x20
 
@@ -287,3 +316,135 @@ def place_step(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None) -> tor
 def generate_scenes(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None):
     a = args.c()
     _ok(_lib.scn_generate_scenes(ctx.h, C.byref(db.c), C.byref(a), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Learned pose proposal
+class Network:
+    """Device tensors of the proposal network (scn_mlp) -- FP32 master weights
+    and biases, BF16 copies (W and W^T, as int16 storage) and AdamW moments."""
+
+    def __init__(self, dims=(FEATURES, 512, 512, 512, BINS), device="cuda", train=True):
+        dev = torch.device(device)
+        self.dims = tuple(int(d) for d in dims)
+        L = len(self.dims) - 1
+        assert L == N_LAYERS
+        f32 = lambda *s: torch.zeros(*s, dtype=torch.float32, device=dev)
+        b16 = lambda *s: torch.zeros(*s, dtype=torch.bfloat16, device=dev)
+        self.w = [f32(self.dims[l + 1], self.dims[l]) for l in range(L)]
+        self.b = [f32(self.dims[l + 1]) for l in range(L)]
+        self.wb = [b16(self.dims[l + 1], self.dims[l]) for l in range(L)]
+        self.wt = [b16(self.dims[l], self.dims[l + 1]) for l in range(L)]
+        self.mw = [f32(self.dims[l + 1], self.dims[l]) for l in range(L)] if train else None
+        self.vw = [f32(self.dims[l + 1], self.dims[l]) for l in range(L)] if train else None
+        self.mb = [f32(self.dims[l + 1]) for l in range(L)] if train else None
+        self.vb = [f32(self.dims[l + 1]) for l in range(L)] if train else None
+        self.c = Mlp()
+        for l, d in enumerate(self.dims):
+            self.c.dims[l] = d
+        for l in range(L):
+            self.c.w[l], self.c.b[l] = self.w[l].data_ptr(), self.b[l].data_ptr()
+            self.c.wb[l], self.c.wt[l] = self.wb[l].data_ptr(), self.wt[l].data_ptr()
+            if train:
+                self.c.m_w[l], self.c.v_w[l] = self.mw[l].data_ptr(), self.vw[l].data_ptr()
+                self.c.m_b[l], self.c.v_b[l] = self.mb[l].data_ptr(), self.vb[l].data_ptr()
+        self.c.step = 0
+
+    def init(self, ctx: Context, seed: int, stream=None):
+        _ok(_lib.scn_mlp_init(ctx.h, C.byref(self.c), int(seed) & (2 ** 64 - 1), _stream(stream)))
+
+    def load(self, ws, bs):
+        """Set FP32 weights/biases (host arrays) and refresh the BF16 copies
+        (the copies are conversions of the given values)."""
+        for l in range(N_LAYERS):
+            self.w[l].copy_(torch.as_tensor(np.asarray(ws[l], np.float32)))
+            self.b[l].copy_(torch.as_tensor(np.asarray(bs[l], np.float32)))
+            self.wb[l].copy_(self.w[l].to(torch.bfloat16))
+            self.wt[l].copy_(self.w[l].t().contiguous().to(torch.bfloat16))
+        if self.mw is not None:
+            for t in self.mw + self.vw + self.mb + self.vb:
+                t.zero_()
+        self.c.step = 0
+
+    def state(self):
+        return {"dims": self.dims, "step": int(self.c.step),
+                "w": [t.cpu() for t in self.w], "b": [t.cpu() for t in self.b]}
+
+
+def mlp_forward(ctx: Context, net: Network, x: torch.Tensor, stream=None) -> torch.Tensor:
+    M = int(x.shape[0])
+    out = torch.empty((max(M, 1), net.dims[-1]), dtype=torch.float32, device=x.device)
+    _ok(_lib.scn_mlp_forward(ctx.h, C.byref(net.c), _ptr(x), M, _ptr(out), _stream(stream)))
+    return out[:M]
+
+
+def mlp_backward(ctx: Context, net: Network, x, bins, tgt, stream=None):
+    M, L = int(bins.shape[0]), int(bins.shape[1])
+    gw = [torch.empty_like(w) for w in net.w]
+    gb = [torch.empty_like(b) for b in net.b]
+    loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+    pw = (C.c_void_p * N_LAYERS)(*[g.data_ptr() for g in gw])
+    pb = (C.c_void_p * N_LAYERS)(*[g.data_ptr() for g in gb])
+    _ok(_lib.scn_mlp_backward(ctx.h, C.byref(net.c), _ptr(x), M, _ptr(bins), _ptr(tgt), L,
+                              C.cast(pw, C.c_void_p), C.cast(pb, C.c_void_p), _ptr(loss),
+                              _stream(stream)))
+    return loss, gw, gb
+
+
+def mlp_train_step(ctx: Context, net: Network, x, bins, tgt, lr=1e-3, betas=(0.9, 0.999),
+                   eps=1e-8, weight_decay=1e-4, loss=None, stream=None):
+    M, L = int(bins.shape[0]), int(bins.shape[1])
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+    opt = AdamW(float(lr), float(betas[0]), float(betas[1]), float(eps), float(weight_decay))
+    _ok(_lib.scn_mlp_train_step(ctx.h, C.byref(net.c), _ptr(x), M, _ptr(bins), _ptr(tgt), L,
+                                C.byref(opt), _ptr(loss), _stream(stream)))
+    return loss
+
+
+def descriptors(ctx: Context, db: DeviceBatch, stream=None) -> torch.Tensor:
+    out = torch.empty((max(db.c.n_objects, 1), DESC), dtype=torch.float32, device=db.tmpl.device)
+    _ok(_lib.scn_descriptors(ctx.h, C.byref(db.c), _ptr(out), _stream(stream)))
+    return out[:db.c.n_objects]
+
+
+def heightmaps(ctx: Context, db: DeviceBatch, n_state: Optional[torch.Tensor] = None,
+               stream=None) -> torch.Tensor:
+    out = torch.empty((max(db.c.n_scenes, 1), HMAP_CELLS), dtype=torch.float32,
+                      device=db.tmpl.device)
+    _ok(_lib.scn_heightmaps(ctx.h, C.byref(db.c), _ptr(n_state), _ptr(out), _stream(stream)))
+    return out[:db.c.n_scenes]
+
+
+def features(ctx: Context, hmap, desc, obj_idx, stream=None) -> torch.Tensor:
+    n = int(obj_idx.shape[0])
+    out = torch.empty((max(n, 1), FEATURES), dtype=torch.bfloat16, device=obj_idx.device)
+    _ok(_lib.scn_features(ctx.h, n, _ptr(hmap), _ptr(desc), _ptr(obj_idx), _ptr(out),
+                          _stream(stream)))
+    return out[:n]
+
+
+def proposal_topk(ctx: Context, logits, k: int, active=None, stream=None) -> torch.Tensor:
+    M = int(logits.shape[0])
+    out = torch.full((max(M, 1), k), -1, dtype=torch.int32, device=logits.device)
+    _ok(_lib.scn_proposal_topk(ctx.h, _ptr(logits), M, int(k), _ptr(active), _ptr(out),
+                               _stream(stream)))
+    return out[:M]
+
+
+def harvest_labels(ctx: Context, db: DeviceBatch, n_state, L: int, seed: int, round_: int = 0,
+                   margin: float = 0.005, stream=None):
+    n = db.c.n_scenes
+    bins = torch.empty((max(n, 1), L), dtype=torch.int32, device=db.tmpl.device)
+    acc = torch.empty((max(n, 1), L), dtype=torch.float32, device=db.tmpl.device)
+    _ok(_lib.scn_harvest_labels(ctx.h, C.byref(db.c), _ptr(n_state), int(L),
+                                int(seed) & (2 ** 64 - 1), int(round_), float(margin), _ptr(bins),
+                                _ptr(acc), _stream(stream)))
+    return bins[:n], acc[:n]
+
+
+def generate_scenes_learned(ctx: Context, db: DeviceBatch, args: GenArgs, net: Network,
+                            top_k: int = 64, stream=None):
+    a = args.c()
+    _ok(_lib.scn_generate_scenes_learned(ctx.h, C.byref(db.c), C.byref(a), C.byref(net.c),
+                                         int(top_k), _stream(stream)))

@@ -1,0 +1,253 @@
+"""GPU: the learned pose proposal against the FP64 oracle -- network forward,
+gradients, AdamW, descriptors, height maps, features, top-k, label harvest,
+and the learned generation itself."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import BAND, MARGIN
+from oracle import learned as ol
+from paper_2512_16896_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (4128, 512, 512, 512, 4096)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    from paper_2512_16896_amd import scn
+    ctx = scn.Context(0)
+    yield scn, ctx, torch
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def _weights(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    W = [(rng.uniform(-1, 1, (DIMS[l + 1], DIMS[l])) * math.sqrt(6 / DIMS[l]) * scale)
+         .astype(np.float32) for l in range(4)]
+    b = [(rng.standard_normal(DIMS[l + 1]) * 0.05).astype(np.float32) for l in range(4)]
+    return W, b
+
+
+def _features(seed, M):
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([np.maximum(rng.standard_normal((M, 4096)), 0) * 2,
+                        rng.standard_normal((M, 32))], 1)
+    return ol.bf16(x)
+
+
+def _net(scn, torch, W, b):
+    net = scn.Network(DIMS)
+    net.load(W, b)
+    return net
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_mlp_forward_matches_oracle(dev):
+    scn, ctx, torch = dev
+    W, b = _weights(1)
+    net = _net(scn, torch, W, b)
+    x = _features(2, 96)
+    z = scn.mlp_forward(ctx, net, torch.tensor(x, dtype=torch.bfloat16, device="cuda")).cpu().numpy()
+    ref, _ = ol.forward(x, W, b)
+    assert _rel(z, ref) < 2 ** -7
+    assert np.max(np.abs(z - ref)) < 2 ** -6 * np.max(np.abs(ref))
+    # a ragged M (not a multiple of the 64-row tile)
+    z2 = scn.mlp_forward(ctx, net, torch.tensor(x[:37], dtype=torch.bfloat16, device="cuda")).cpu().numpy()
+    np.testing.assert_allclose(z2, z[:37], rtol=0, atol=1e-6 * np.max(np.abs(z)))
+
+
+def test_mlp_backward_matches_oracle(dev):
+    scn, ctx, torch = dev
+    W, b = _weights(3)
+    net = _net(scn, torch, W, b)
+    M, L = 64, 8
+    x = _features(4, M)
+    rng = np.random.default_rng(5)
+    bins = rng.integers(0, 4096, size=(M, L)).astype(np.int32)
+    bins[3, 5] = -1
+    tgt = rng.integers(0, 2, size=(M, L)).astype(np.float32)
+    loss, gw, gb = scn.mlp_backward(ctx, net, torch.tensor(x, dtype=torch.bfloat16, device="cuda"),
+                                    torch.tensor(bins, device="cuda"), torch.tensor(tgt, device="cuda"))
+    rl, rgw, rgb = ol.backward(x, W, b, bins, tgt)
+    assert float(loss.item()) == pytest.approx(rl, rel=2e-3)
+    for l in range(4):
+        assert _rel(gw[l].cpu().numpy(), rgw[l]) < 1e-2, l
+        assert _rel(gb[l].cpu().numpy(), rgb[l]) < 1e-2, l
+
+
+def test_train_step_matches_oracle_adamw(dev):
+    scn, ctx, torch = dev
+    W, b = _weights(6)
+    net = _net(scn, torch, W, b)
+    M, L = 32, 4
+    x = _features(7, M)
+    rng = np.random.default_rng(8)
+    bins = rng.integers(0, 4096, size=(M, L)).astype(np.int32)
+    tgt = rng.integers(0, 2, size=(M, L)).astype(np.float32)
+    lr = 1e-3
+    scn.mlp_train_step(ctx, net, torch.tensor(x, dtype=torch.bfloat16, device="cuda"),
+                       torch.tensor(bins, device="cuda"), torch.tensor(tgt, device="cuda"), lr=lr)
+    assert net.c.step == 1
+    _, rgw, rgb = ol.backward(x, W, b, bins, tgt)
+    for l in range(4):
+        nw = net.w[l].cpu().numpy().astype(np.float64)
+        want, _, _ = ol.adamw_step(W[l].astype(np.float64), rgw[l], 0, 0, 0, lr, 0.9, 0.999, 1e-8, 1e-4)
+        # the first AdamW step moves each weight by about lr * sign(g): compare the moves
+        assert _rel(nw - W[l], want - W[l]) < 0.05, l
+        # BF16 copies follow the new master weights
+        wb = net.wb[l].float().cpu().numpy()
+        np.testing.assert_array_equal(wb, ol.bf16(nw).astype(np.float32))
+        np.testing.assert_array_equal(net.wt[l].float().cpu().numpy(), wb.T)
+
+
+def test_init_is_kaiming_uniform(dev):
+    scn, ctx, torch = dev
+    net = scn.Network(DIMS)
+    net.init(ctx, seed=1234)
+    for l in range(4):
+        w = net.w[l].cpu().numpy()
+        bound = math.sqrt(6 / DIMS[l])
+        assert np.all(np.abs(w) < bound)
+        assert abs(w.mean()) < 0.01 * bound and abs(w.std() - bound / math.sqrt(3)) < 0.02 * bound
+        assert np.all(net.b[l].cpu().numpy() == 0)
+        np.testing.assert_array_equal(net.wb[l].float().cpu().numpy(), ol.bf16(w).astype(np.float32))
+        np.testing.assert_array_equal(net.wt[l].float().cpu().numpy(), net.wb[l].float().cpu().numpy().T)
+
+
+def test_descriptors_match_oracle(dev):
+    scn, ctx, torch = dev
+    b = sg.uneven_batch(6, seed=2, n_obj=(3, 9), n_sph=(1, 256))
+    db = scn.DeviceBatch(b)
+    d = scn.descriptors(ctx, db).cpu().numpy()
+    for o in range(b.n_objects):
+        ref = ol.descriptor(b.tmpl[b.sph_off[o]:b.sph_off[o + 1]])
+        np.testing.assert_allclose(d[o], ref, rtol=2e-5, atol=2e-6)
+
+
+def _oracle_states(orc, b, seed):
+    gen = orc.generate(b, seed=seed)
+    rng = np.random.default_rng(seed)
+    n_state = np.minimum(gen["n_placed"], rng.integers(0, 21, size=b.n_scenes)).astype(np.int32)
+    placed = np.nan_to_num(gen["placed"], nan=0.0).astype(np.float32)
+    return n_state, placed
+
+
+def test_heightmaps_and_features_match_oracle(dev, orc):
+    scn, ctx, torch = dev
+    b = sg.batched_scenes(10, seed=12)
+    n_state, placed = _oracle_states(orc, b, 3)
+    db = scn.DeviceBatch(b)
+    db.placed.copy_(torch.tensor(placed))
+    H = scn.heightmaps(ctx, db, torch.tensor(n_state, device="cuda")).cpu().numpy()
+    desc = scn.descriptors(ctx, db)
+    obj_idx = np.where(n_state < 20, b.obj_off[:-1] + n_state, -1).astype(np.int32)
+    X = scn.features(ctx, torch.tensor(H, device="cuda"), desc,
+                     torch.tensor(obj_idx, device="cuda")).float().cpu().numpy()
+    for s in range(b.n_scenes):
+        ref = ol.heightmap(b, placed.astype(np.float64), s, int(n_state[s])).reshape(-1)
+        bad = np.abs(H[s] - ref) > 1e-5
+        assert np.mean(bad) < 2e-3, (s, np.sum(bad))        # cells exactly on an edge may flip
+        if obj_idx[s] >= 0:
+            o = obj_idx[s]
+            rx = ol.features(ref, ol.descriptor(b.tmpl[b.sph_off[o]:b.sph_off[o + 1]]))
+            # equal up to one BF16 step where the FP32 and FP64 values straddle a rounding edge
+            close = np.abs(X[s] - rx) <= 2 ** -7 * np.maximum(np.abs(rx), 1e-30)
+            assert np.mean(~close) < 5e-3
+        else:
+            assert np.all(X[s] == 0)
+
+
+def test_topk_matches_oracle_with_ties(dev):
+    scn, ctx, torch = dev
+    rng = np.random.default_rng(9)
+    z = rng.standard_normal((40, 4096)).astype(np.float32)
+    z[3, 100:200] = 5.0                       # a block of ties at the top
+    z[4, :] = 0.0                             # all equal
+    got = scn.proposal_topk(ctx, torch.tensor(z, device="cuda"), 64).cpu().numpy()
+    for m in range(40):
+        assert got[m].tolist() == ol.topk(z[m].astype(np.float64), 64).tolist()
+    act = torch.tensor([0 if m % 2 else -1 for m in range(40)], dtype=torch.int32, device="cuda")
+    got2 = scn.proposal_topk(ctx, torch.tensor(z, device="cuda"), 5, active=act).cpu().numpy()
+    assert np.all(got2[0::2] == -1) and got2[1].tolist() == ol.topk(z[1].astype(np.float64), 5).tolist()
+
+
+def test_harvest_labels_match_oracle(dev, orc):
+    scn, ctx, torch = dev
+    b = sg.batched_scenes(8, seed=13)
+    n_state, placed = _oracle_states(orc, b, 4)
+    db = scn.DeviceBatch(b)
+    db.placed.copy_(torch.tensor(placed))
+    L = 96
+    bins, acc = scn.harvest_labels(ctx, db, torch.tensor(n_state, device="cuda"), L, seed=77, round_=3)
+    bins, acc = bins.cpu().numpy(), acc.cpu().numpy()
+    n_cmp = 0
+    for s in range(b.n_scenes):
+        one, _ = sg.subset(b, [s])
+        o0 = b.obj_off[s]
+        sp = placed[b.sph_off[o0]:b.sph_off[b.obj_off[s + 1]]].astype(np.float64)
+        clr_of = lambda o, poses: orc.check(one, [o - o0], [0, L], [int(n_state[s])], sp, poses,
+                                            scene_id=[s])
+        rb, ra = ol.harvest_labels(b, placed, s, int(n_state[s]), L, 77, 3, MARGIN, clr_of)
+        assert bins[s].tolist() == rb.tolist()
+        if rb[0] < 0:
+            continue
+        o = o0 + int(n_state[s])
+        poses = None
+        # compare accept flags outside the band of the margin
+        clr = clr_of(o, _harvest_poses(b, s, int(n_state[s]), L, 77, 3))
+        clear = np.abs(clr - MARGIN) >= BAND
+        assert np.array_equal(acc[s][clear], ra[clear])
+        n_cmp += int(clear.sum())
+    assert n_cmp > 0
+
+
+def _harvest_poses(b, s, j, L, seed, round_):
+    from oracle import bruteforce as bf
+    o = b.obj_off[s] + j
+    ctr = np.stack([np.arange(L), np.full(L, 0x20000 | round_), np.full(L, j), np.full(L, s)], 1)
+    u = bf.unit(bf.philox(ctr, (seed & 0xFFFFFFFF, seed >> 32)))
+    sup = b.sup[b.obj_sup[o]].astype(np.float64)
+    tm = b.tmpl[b.sph_off[o]:b.sph_off[o + 1]].astype(np.float64)
+    lift = sup[15] + np.max(tm[:, 3] - tm[:, 2])
+    return ((sup[12] - sup[14]) * (2 * u[:, 0] - 1), (sup[13] - sup[14]) * (2 * u[:, 1] - 1),
+            np.full(L, lift), 2 * np.pi * u[:, 2])
+
+
+def test_learned_generation_matches_oracle(dev, orc):
+    scn, ctx, torch = dev
+    W, bb = _weights(21, scale=1.0)
+    net = _net(scn, torch, W, bb)
+    b = sg.batched_scenes(12, seed=14)
+    db = scn.DeviceBatch(b)
+    scn.generate_scenes_learned(ctx, db, scn.GenArgs(seed=31), net, top_k=64)
+    torch.cuda.synchronize()
+    rec_f, rec_i = db.records()
+    status = db.status.cpu().numpy()
+    ref = ol.generate_learned(b, [w.astype(np.float64) for w in W], [v.astype(np.float64) for v in bb],
+                              31, 64, orc)
+    n_cmp = n_prop = 0
+    for s in range(b.n_scenes):
+        objs = range(b.obj_off[s], b.obj_off[s + 1])
+        sure = True
+        for o in objs:
+            if ref["unsure"][o]:
+                sure = False
+                break
+            assert tuple(rec_i[o]) == tuple(ref["rec"][o]), (s, o - b.obj_off[s])
+            if ref["rec"][o][1] >= 0:
+                np.testing.assert_allclose(rec_f[o], ref["pose"][o], atol=2e-6, rtol=0)
+                n_prop += ref["rec"][o][0] == -2
+            n_cmp += 1
+            if ref["rec"][o][1] < 0:
+                break
+        if sure:
+            assert status[s] == ref["status"][s]
+    assert n_cmp > 0.5 * b.n_objects and n_prop > 0
