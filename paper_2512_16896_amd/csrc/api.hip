@@ -256,7 +256,10 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
     plan->cap_sph = b->max_spheres_per_scene > 0 ? b->max_spheres_per_scene : 1;
     plan->cap_obj = b->max_objects_per_scene > 0 ? b->max_objects_per_scene : 1;
     plan->max_steps = max_steps;
-    if (16LL * plan->cap_obj + 16LL * 64 > c->lds_per_block)
+    // dynamic LDS available to the place kernel: the block limit minus the
+    // kernel's own static shared variables
+    const long long lds_cap = c->lds_per_block - 1024;
+    if (16LL * plan->cap_obj + 16LL * 64 > lds_cap)
         return fail(SCN_E_UNSUPPORTED, "%d objects per scene do not fit the LDS", plan->cap_obj);
     static const int kBudgetKB[] = {0, 32, 48, 64, 80, 96};
     const int code = (sched & SCN_SCHED_LDS_MASK) >> SCN_SCHED_LDS_SHIFT;
@@ -266,7 +269,7 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
         plan->split_sph = 0;
     } else if (code <= 5) {
         long long budget = code == 0 ? all_bytes : 1024LL * kBudgetKB[code];
-        if (budget > c->lds_per_block) budget = c->lds_per_block;
+        if (budget > lds_cap) budget = lds_cap;
         if (all_bytes <= budget) {
             plan->mode = scn::kPlaceAllLds;
             plan->split_sph = plan->cap_sph;

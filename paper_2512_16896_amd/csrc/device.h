@@ -147,6 +147,18 @@ __device__ __forceinline__ float grid_sample(const float* G, const float* __rest
     return fmaf(tz, c1 - c0, c0);
 }
 
+// Squared distance from a world point to a grid instance's node box (0 inside).
+__device__ __forceinline__ float grid_box_d2(const float* G, float px, float py, float pz) {
+    const float gx = fmaf(G[0], px, fmaf(G[1], py, fmaf(G[2], pz, G[9])));
+    const float gy = fmaf(G[3], px, fmaf(G[4], py, fmaf(G[5], pz, G[10])));
+    const float gz = fmaf(G[6], px, fmaf(G[7], py, fmaf(G[8], pz, G[11])));
+    const float ex = G[15] * (G[16] - 1.f), ey = G[15] * (G[17] - 1.f), ez = G[15] * (G[18] - 1.f);
+    const float dx = fmaxf(fmaxf(G[12] - gx, gx - (G[12] + ex)), 0.f);
+    const float dy = fmaxf(fmaxf(G[13] - gy, gy - (G[13] + ey)), 0.f);
+    const float dz = fmaxf(fmaxf(G[14] - gz, gz - (G[14] + ez)), 0.f);
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
 // Wave-wide reductions (64 lanes).
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll

@@ -29,18 +29,21 @@ __global__ __launch_bounds__(64) void k_descriptor(int n_obj, const int32_t* __r
     const int lane = threadIdx.x;
     const int k0 = sph_off[o], k1 = sph_off[o + 1];
     const int S = k1 - k0;
-    float sr = 0.f, sr2 = 0.f, rmin = 1e30f, rmax = -1e30f, v = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
-    float sx = 0.f, sy = 0.f, sz = 0.f, sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, sxz = 0.f, syz = 0.f;
+    auto sum = [](float x) {
+        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, kWave);
+        return x;
+    };
+    // first pass: sums, extremes and weighted sums
+    float sr = 0.f, rmin = 1e30f, rmax = -1e30f, v = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
     float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
     float lift = -1e30f, top = -1e30f, foot = 0.f;
     for (int k = k0 + lane; k < k1; k += kWave) {
         const float4 c = tmpl[k];
         const float r3 = c.w * c.w * c.w;
-        sr += c.w; sr2 += c.w * c.w; rmin = fminf(rmin, c.w); rmax = fmaxf(rmax, c.w);
+        sr += c.w; rmin = fminf(rmin, c.w); rmax = fmaxf(rmax, c.w);
         v += r3; wx += r3 * c.x; wy += r3 * c.y; wz += r3 * c.z;
         sx += c.x; sy += c.y; sz += c.z;
-        sxx += c.x * c.x; syy += c.y * c.y; szz += c.z * c.z;
-        sxy += c.x * c.y; sxz += c.x * c.z; syz += c.y * c.z;
         lo[0] = fminf(lo[0], c.x - c.w); hi[0] = fmaxf(hi[0], c.x + c.w);
         lo[1] = fminf(lo[1], c.y - c.w); hi[1] = fmaxf(hi[1], c.y + c.w);
         lo[2] = fminf(lo[2], c.z - c.w); hi[2] = fmaxf(hi[2], c.z + c.w);
@@ -48,35 +51,41 @@ __global__ __launch_bounds__(64) void k_descriptor(int n_obj, const int32_t* __r
         top = fmaxf(top, c.z + c.w);
         foot = fmaxf(foot, sqrtf(c.x * c.x + c.y * c.y) + c.w);
     }
-    auto sum = [](float x) {
-        for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, kWave);
-        return x;
-    };
-    sr = sum(sr); sr2 = sum(sr2); v = sum(v); wx = sum(wx); wy = sum(wy); wz = sum(wz);
+    sr = sum(sr); v = sum(v); wx = sum(wx); wy = sum(wy); wz = sum(wz);
     sx = sum(sx); sy = sum(sy); sz = sum(sz);
-    sxx = sum(sxx); syy = sum(syy); szz = sum(szz); sxy = sum(sxy); sxz = sum(sxz); syz = sum(syz);
     rmin = wave_min(rmin); rmax = wave_max(rmax);
     for (int d = 0; d < 3; ++d) { lo[d] = wave_min(lo[d]); hi[d] = wave_max(hi[d]); }
     lift = wave_max(lift); top = wave_max(top); foot = wave_max(foot);
-    if (lane != 0) return;
-    float* D = desc + 32 * (size_t)o;
     const float n = (float)(S > 0 ? S : 1);
     const float mr = sr / n;
     const float mx = sx / n, my = sy / n, mz = sz / n;
+    // second pass: centred second moments
+    float vr = 0.f, cxx = 0.f, cyy = 0.f, czz = 0.f, cxy = 0.f, cxz = 0.f, cyz = 0.f;
+    for (int k = k0 + lane; k < k1; k += kWave) {
+        const float4 c = tmpl[k];
+        const float dr = c.w - mr, dx = c.x - mx, dy = c.y - my, dz = c.z - mz;
+        vr += dr * dr;
+        cxx += dx * dx; cyy += dy * dy; czz += dz * dz;
+        cxy += dx * dy; cxz += dx * dz; cyz += dy * dz;
+    }
+    vr = sum(vr); cxx = sum(cxx); cyy = sum(cyy); czz = sum(czz);
+    cxy = sum(cxy); cxz = sum(cxz); cyz = sum(cyz);
+    if (lane != 0) return;
+    float* D = desc + 32 * (size_t)o;
     const float iv = v > 0.f ? 1.f / v : 0.f;
     D[0] = (float)S / 256.f;
     D[1] = 10.f * mr;
     D[2] = 10.f * (S ? rmin : 0.f);
     D[3] = 10.f * (S ? rmax : 0.f);
-    D[4] = 10.f * sqrtf(fmaxf(sr2 / n - mr * mr, 0.f));
+    D[4] = 10.f * sqrtf(vr / n);
     D[5] = 1e3f * v;
     D[6] = 10.f * wx * iv; D[7] = 10.f * wy * iv; D[8] = 10.f * wz * iv;
-    D[9] = 100.f * (sxx / n - mx * mx);
-    D[10] = 100.f * (syy / n - my * my);
-    D[11] = 100.f * (szz / n - mz * mz);
-    D[12] = 100.f * (sxy / n - mx * my);
-    D[13] = 100.f * (sxz / n - mx * mz);
-    D[14] = 100.f * (syz / n - my * mz);
+    D[9] = 100.f * cxx / n;
+    D[10] = 100.f * cyy / n;
+    D[11] = 100.f * czz / n;
+    D[12] = 100.f * cxy / n;
+    D[13] = 100.f * cxz / n;
+    D[14] = 100.f * cyz / n;
     for (int d = 0; d < 3; ++d) D[15 + d] = 10.f * 0.5f * (S ? hi[d] - lo[d] : 0.f);
     D[18] = 10.f * (S ? lift : 0.f);
     D[19] = 10.f * (S ? top + lift : 0.f);

@@ -62,6 +62,7 @@ __device__ __forceinline__ Pose entry_pose(int g, int prop_k, const int32_t* __r
     return sample_pose(seed, s, j, (uint32_t)a, (uint32_t)i, ax, ay, zc);
 }
 
+
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int lane) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
@@ -74,7 +75,9 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 // kLds = false: placed spheres are read from global memory (L1/L2) and only
 //               the object bounds live in LDS; with `split`, scenes of at
 //               most split_sph spheres are left to the LDS launch.
-template <int SPL, bool kLds>
+// kGrids: the batch has voxel-grid furniture (the grid code is compiled out
+// otherwise, which keeps the register count of grid-free launches low).
+template <int SPL, bool kLds, bool kGrids>
 __global__ __launch_bounds__(1024) void k_place(
     const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
     const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
@@ -84,7 +87,13 @@ __global__ __launch_bounds__(1024) void k_place(
     scn_pose_rec* __restrict__ rec, int32_t* __restrict__ chosen,
     unsigned long long* __restrict__ counters, const int32_t* __restrict__ order, uint64_t seed,
     float margin, int retries, int default_ncand, int max_steps, int cap_sph, int cap_obj,
-    int split, int split_sph, const int32_t* __restrict__ prop_bins, int prop_k) {
+    int split, int split_sph, const int32_t* __restrict__ prop_bins, int prop_k,
+    const int32_t* __restrict__ grid_off, const float* __restrict__ grid,
+    const int32_t* __restrict__ grid_src, const int64_t* __restrict__ grid_val_off,
+    const float* __restrict__ grid_val) {
+    // placed objects covered by the batch masks: 64 per word; the dense
+    // multi-shelf (grid) scenes carry 100 objects, so they get two words
+    constexpr int kObjWords = kGrids ? 2 : 1;
     extern __shared__ float4 lds[];
     float4* lsph = lds;                        // placed spheres: (x, y, z, r + margin)
     float4* lbnd = lds + (kLds ? cap_sph : 0); // world bounding sphere of each placed object
@@ -161,11 +170,13 @@ __global__ __launch_bounds__(1024) void k_place(
     __syncthreads();
 
     unsigned long long n_cand = 0, n_pairs = 0, n_boxp = 0, n_att = 0, n_done = 0, n_xf = 0;
-    unsigned long long n_boxc = 0, n_objc = 0, n_sphc = 0;
+    unsigned long long n_boxc = 0, n_objc = 0, n_sphc = 0, n_grid = 0;
     int8_t fin = SCN_SCENE_ACTIVE;
     int last = -2;
     const int b0 = box_off[s], b1 = box_off[s + 1];
     const int nbox_mask = min(b1 - b0, kWave);   // boxes covered by the batch masks
+    const int g0 = grid_off ? grid_off[s] : 0;
+    const int ngrid_mask = kGrids ? min(grid_off[s + 1] - g0, kWave) : 0;   // grids (<= 64)
 
     for (; j < j_end; ++j) {
         const int o = o0 + j;
@@ -214,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_place(
         const int pk = prop_bins ? prop_k : 0;
         const int32_t* pb = prop_bins ? prop_bins + (size_t)s * prop_k : nullptr;
         const int total = pk + (C > 0 ? (retries + 1) * C : 0);   // entries of the list
-        const int nob_mask = min(j, kWave);                 // objects covered by the masks
+        const int nob_mask = min(j, kWave * kObjWords);     // objects covered by the masks
 
         if (threadIdx.x == 0) s_best = INT_MAX;
         __syncthreads();
@@ -281,20 +292,26 @@ __global__ __launch_bounds__(1024) void k_place(
                                       ay, zc, &ga, &gi);
             float lx, ly, lz;   // world centre of this candidate's bounding sphere
             to_world(U, L, bc[0], bc[1], bc[2], lx, ly, lz);
-            unsigned long long bmask = 0, omask = 0;
+            unsigned long long bmask = 0, gmask = 0, omask[kObjWords] = {};
             for (int bi = 0; bi < nbox_mask; ++bi) {
                 const float* B = box + 16 * (b0 + bi);
                 if (box_out2(B, lx, ly, lz) < reach * reach) bmask |= 1ull << bi;
+            }
+            // grids: only spheres whose centres lie inside a grid's node box
+            // sample it (outside it reads +inf), so a bounding sphere that
+            // misses the node box needs no sample
+            if constexpr (kGrids) for (int gi = 0; gi < ngrid_mask; ++gi) {
+                if (grid_box_d2(grid + 24 * (g0 + gi), lx, ly, lz) <= rho * rho) gmask |= 1ull << gi;
             }
             for (int ob = 0; ob < nob_mask; ++ob) {
                 const float4 bd = lbnd[ob];
                 const float dx = lx - bd.x, dy = ly - bd.y, dz = lz - bd.z;
                 const float lim = reach + bd.w;
-                if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) omask |= 1ull << ob;
+                if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) omask[ob >> 6] |= 1ull << (ob & 63);
             }
             {
                 const unsigned long long nlive = __popcll(__ballot(live));
-                n_boxc += nlive * (unsigned long long)nbox_mask;
+                n_boxc += nlive * (unsigned long long)(nbox_mask + ngrid_mask);
                 n_objc += nlive * (unsigned long long)nob_mask;
             }
             // ---- candidate phase ----
@@ -310,7 +327,7 @@ __global__ __launch_bounds__(1024) void k_place(
                 P.x = bcast(L.x, t); P.y = bcast(L.y, t); P.z = zc;
                 P.c = bcast(L.c, t); P.s = bcast(L.s, t);
                 Gx = bcast(lx, t); Gy = bcast(ly, t); Gz = bcast(lz, t);
-                unsigned long long bm = bcast64(bmask, t), om = bcast64(omask, t);
+                unsigned long long bm = bcast64(bmask, t), gm = bcast64(gmask, t);
                 ++n_cand;
                 n_xf += S;
 #pragma unroll
@@ -337,15 +354,32 @@ __global__ __launch_bounds__(1024) void k_place(
                         if (q == 0 || q < nq) hit |= box_out2(B, wx[q], wy[q], wz[q]) < rm2[q];
                     n_boxp += S;
                 }
-                // placed objects of the mask, then any beyond the first 64
+                // voxel grids of the mask: trilinear field minus radius vs margin
+                if constexpr (kGrids) while (gm && !__ballot(hit)) {
+                    const int gi = __builtin_ctzll(gm);
+                    gm &= gm - 1;
+                    const float* G = grid + 24 * (g0 + gi);
+                    const float* vals = grid_val + grid_val_off[grid_src[g0 + gi]];
+#pragma unroll
+                    for (int q = 0; q < SPL; ++q)
+                        if (q == 0 || q < nq)
+                            hit |= grid_sample(G, vals, wx[q], wy[q], wz[q]) < cr[q] + margin;
+                    n_grid += S;
+                }
+                // placed objects of the masks, then any beyond them
                 if (!__ballot(hit)) {
-                    while (om) {
-                        const int ob = __builtin_ctzll(om);
-                        om &= om - 1;
-                        test_object(ob, hit);
+#pragma unroll
+                    for (int w = 0; w < kObjWords; ++w) {
+                        unsigned long long om = bcast64(omask[w], t);
+                        while (om) {
+                            const int ob = 64 * w + __builtin_ctzll(om);
+                            om &= om - 1;
+                            test_object(ob, hit);
+                            if (__ballot(hit)) break;
+                        }
                         if (__ballot(hit)) break;
                     }
-                    for (int ob = kWave; ob < j && !__ballot(hit); ++ob) {
+                    for (int ob = kWave * kObjWords; ob < j && !__ballot(hit); ++ob) {
                         const float4 bd = lbnd[ob];
                         const float dx = Gx - bd.x, dy = Gy - bd.y, dz = Gz - bd.z;
                         const float lim = reach + bd.w;
@@ -410,6 +444,7 @@ __global__ __launch_bounds__(1024) void k_place(
         atomicAdd(counters + kBoxCulls, n_boxc);
         atomicAdd(counters + kObjCulls, n_objc);
         atomicAdd(counters + kSphCulls, n_sphc);
+        if (n_grid) atomicAdd(counters + kGridSamples, n_grid);
         if (n_att) atomicAdd(counters + kAttempts, n_att);
         if (n_done) atomicAdd(counters + kPlaced, n_done);
     }
@@ -419,7 +454,7 @@ template <int SPL, bool kLds>
 static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                    const PlacePlan& plan, int cap_sph, int split, int32_t* chosen,
                                    unsigned long long* ctr, hipStream_t st) {
-    auto kern = k_place<SPL, kLds>;
+    auto kern = b.grid_off ? k_place<SPL, kLds, true> : k_place<SPL, kLds, false>;
     const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj);
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -431,7 +466,8 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                        b.box_off, b.box, (float4*)b.placed, b.n_placed, b.status, b.rec, chosen,
                        ctr, plan.order, a.seed, a.margin, a.retries, a.default_ncand,
                        plan.max_steps, cap_sph, plan.cap_obj, split, plan.split_sph,
-                       plan.prop_bins, plan.prop_k);
+                       plan.prop_bins, plan.prop_k, b.grid_off, b.grid, b.grid_src,
+                       b.grid_val_off, b.grid_val);
     return hipGetLastError();
 }
 

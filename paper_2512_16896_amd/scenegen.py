@@ -130,12 +130,22 @@ def _footprint_order(obj_off, sph_off, tmpl):
     return np.lexsort((-fp, scene_of))
 
 
+def _ranges(starts, lengths):
+    """Concatenation of arange(starts[i], starts[i] + lengths[i])."""
+    lengths = np.asarray(lengths, np.int64)
+    tot = int(lengths.sum())
+    if tot == 0:
+        return np.zeros(0, np.int64)
+    first = np.zeros(len(lengths), np.int64)
+    first[1:] = np.cumsum(lengths)[:-1]
+    return np.repeat(np.asarray(starts, np.int64) - first, lengths) + np.arange(tot)
+
+
 def _reorder_objects(perm, sph_off, tmpl, *per_obj):
     S = np.diff(sph_off)[perm]
     new_off = np.zeros_like(sph_off)
     new_off[1:] = np.cumsum(S)
-    idx = np.concatenate([np.arange(sph_off[o], sph_off[o + 1]) for o in perm]) \
-        if len(perm) else np.zeros(0, np.int64)
+    idx = _ranges(sph_off[perm], S)
     return (new_off, tmpl[idx]) + tuple(a[perm] for a in per_obj)
 
 
@@ -240,12 +250,96 @@ def batched_scenes(n_scenes: int = 4096, seed: int = 0,
                          name=f"batched-{n_scenes}")
 
 
+# ---------------------------------------------------------------------------
+# Dense multi-shelf scenes with voxel signed-distance furniture
+BAY_GRID_N = 64
+BAY_GRID_H = 0.96 / 63             # node spacing (m): 64 nodes span 0.96 m
+BAY_GRID_ORIGIN = (-0.48, -0.48, -0.16)
+BAY_HALF = (0.4, 0.2)              # shelf surface 0.8 x 0.4 m
+BAY_PITCH = 0.40                   # vertical distance between shelf surfaces
+# solids of one bay in its own frame (origin at the centre of the board top,
+# z up, open towards -y): two boards, two side walls, a back wall
+BAY_SOLIDS = [((0.0, 0.0, -0.016), (0.43, 0.23, 0.016)),
+              ((0.0, 0.0, 0.316), (0.43, 0.23, 0.016)),
+              ((-0.416, 0.0, 0.15), (0.016, 0.23, 0.182)),
+              ((0.416, 0.0, 0.15), (0.016, 0.23, 0.182)),
+              ((0.0, 0.216, 0.15), (0.43, 0.016, 0.182))]
+
+
+def bay_sdf_asset() -> np.ndarray:
+    """Node values [nz, ny, nx] (x fastest) of the bay's signed distance:
+    the minimum over its solids of the axis-aligned box distance, at nodes
+    origin + h (i, j, k).  Boards are 2.1 node spacings thick."""
+    n, h = BAY_GRID_N, BAY_GRID_H
+    o = np.asarray(BAY_GRID_ORIGIN)
+    z, y, x = np.meshgrid(o[2] + h * np.arange(n), o[1] + h * np.arange(n),
+                          o[0] + h * np.arange(n), indexing="ij")
+    p = np.stack([x, y, z], -1)
+    best = np.full(x.shape, np.inf)
+    for c, hh in BAY_SOLIDS:
+        q = np.abs(p - np.asarray(c)) - np.asarray(hh)
+        d = np.linalg.norm(np.maximum(q, 0), axis=-1) + np.minimum(q.max(-1), 0)
+        best = np.minimum(best, d)
+    return best.astype(np.float32)
+
+
+def shelf_scenes(n_scenes: int = 65536, seed: int = 0, n_obj: int = 100, n_sph: int = 128,
+                 n_cand: int = 2048, n_shelves: int = 6, side=(0.03, 0.08),
+                 rad=(0.005, 0.02), margin: float = 0.005, chunk: int = 2048) -> SceneBatch:
+    """Every scene: a shelf unit of n_shelves stacked 0.8 x 0.4 m surfaces at a
+    random world pose (yaw, translation); its furniture is one voxel-SDF grid
+    instance per bay (one shared 64^3 asset); n_obj objects of n_sph spheres
+    (cube side ~ U(side), radii ~ U(rad)) assigned round-robin to the shelves
+    in placement order; objects rest margin + 1 mm above the board (the board
+    is part of the field)."""
+    lift = margin + 0.001
+    n_tot_obj = n_scenes * n_obj
+    tmpl = np.empty((n_tot_obj * n_sph, 4), np.float32)
+    sph_off = (np.arange(n_tot_obj + 1, dtype=np.int64) * n_sph)
+    sup = np.zeros((n_scenes * n_shelves, 16), np.float32)
+    grid = np.zeros((n_scenes * n_shelves, 24), np.float32)
+    for c0 in range(0, n_scenes, chunk):
+        c1 = min(n_scenes, c0 + chunk)
+        m = c1 - c0
+        rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5E1F, c0 // chunk]))
+        yaw = rng.uniform(0, 2 * np.pi, m)
+        base = np.stack([rng.uniform(-1, 1, m), rng.uniform(-1, 1, m), rng.uniform(0.0, 0.3, m)], 1)
+        R = rotz(yaw)
+        for k in range(n_shelves):
+            t = base + np.einsum('nij,j->ni', R, np.array([0.0, 0.0, BAY_PITCH * k]))
+            rows = np.arange(c0, c1) * n_shelves + k
+            sup[rows] = _support_rows(R, t, BAY_HALF[0], BAY_HALF[1], 0.0, lift)
+            Rt = np.transpose(R, (0, 2, 1))
+            grid[rows, 0:9] = Rt.reshape(m, 9)
+            grid[rows, 9:12] = -np.einsum('nij,nj->ni', Rt, t)
+            grid[rows, 12:15] = BAY_GRID_ORIGIN
+            grid[rows, 15] = BAY_GRID_H
+            grid[rows, 16:19] = BAY_GRID_N
+        so, tm = _templates(rng, m * n_obj, n_sph, side, rad)
+        oo = np.arange(m + 1, dtype=np.int64) * n_obj
+        perm = _footprint_order(oo, so, tm)
+        so, tm = _reorder_objects(perm, so, tm)
+        tmpl[c0 * n_obj * n_sph:c1 * n_obj * n_sph] = tm
+    obj_sup = (np.repeat(np.arange(n_scenes), n_obj) * n_shelves +
+               np.tile(np.arange(n_obj) % n_shelves, n_scenes)).astype(np.int32)
+    return SceneBatch(
+        obj_off=(np.arange(n_scenes + 1) * n_obj).astype(np.int32),
+        sph_off=sph_off.astype(np.int32), tmpl=tmpl, obj_sup=obj_sup,
+        obj_ncand=np.full(n_tot_obj, n_cand, np.int32), sup=sup,
+        box_off=np.zeros(n_scenes + 1, np.int32), box=np.zeros((0, 16), np.float32),
+        grid_off=(np.arange(n_scenes + 1) * n_shelves).astype(np.int32), grid=grid,
+        grid_src=np.zeros(n_scenes * n_shelves, np.int32), grid_vals=[bay_sdf_asset()],
+        name=f"shelves-{n_scenes}",
+        params=dict(n_scenes=n_scenes, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand,
+                    n_shelves=n_shelves, seed=seed))
+
+
 def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
     """The scenes `scenes` of a batch as a batch of their own, plus the
     original scene indices (which the random-number counters must keep)."""
     scenes = np.asarray(scenes, np.int64)
-    objs = np.concatenate([np.arange(b.obj_off[s], b.obj_off[s + 1]) for s in scenes])
-    boxes = np.concatenate([np.arange(b.box_off[s], b.box_off[s + 1]) for s in scenes])
+    objs = _ranges(b.obj_off[scenes], b.obj_off[scenes + 1] - b.obj_off[scenes])
+    boxes = _ranges(b.box_off[scenes], b.box_off[scenes + 1] - b.box_off[scenes])
     obj_off = np.zeros(len(scenes) + 1, np.int64)
     obj_off[1:] = np.cumsum(b.obj_off[scenes + 1] - b.obj_off[scenes])
     box_off = np.zeros(len(scenes) + 1, np.int64)
@@ -253,7 +347,7 @@ def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
     S = (b.sph_off[objs + 1] - b.sph_off[objs]).astype(np.int64)
     sph_off = np.zeros(len(objs) + 1, np.int64)
     sph_off[1:] = np.cumsum(S)
-    sidx = np.concatenate([np.arange(b.sph_off[o], b.sph_off[o + 1]) for o in objs])
+    sidx = _ranges(b.sph_off[objs], S)
     sups = np.unique(b.obj_sup[objs])
     remap = -np.ones(b.sup.shape[0], np.int64)
     remap[sups] = np.arange(len(sups))
@@ -264,7 +358,7 @@ def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
         box_off=box_off.astype(np.int32), box=b.box[boxes].copy(),
         name=b.name + "-subset", params=dict(b.params))
     if b.grid_off is not None:
-        grids = np.concatenate([np.arange(b.grid_off[s], b.grid_off[s + 1]) for s in scenes])
+        grids = _ranges(b.grid_off[scenes], b.grid_off[scenes + 1] - b.grid_off[scenes])
         goff = np.zeros(len(scenes) + 1, np.int64)
         goff[1:] = np.cumsum(b.grid_off[scenes + 1] - b.grid_off[scenes])
         out.grid_off = goff.astype(np.int32)
