@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 #   box pretest        : the sphere-box test applied to the bounding sphere = 30
 #   object pretest     : bounding sphere vs bounding sphere, like a pair = 11
 FLOP_PAIR, FLOP_BOX, FLOP_XFORM, FLOP_BOXCULL, FLOP_OBJCULL = 11, 30, 27, 30, 11
+# Distance mode (scn_check_batch with clearances): the pair is 3 sub + 5 (squared
+# distance) + 1 sqrt + 1 sub + 1 min = 11; the box adds the signed part of the
+# SDF to the flag form: 30 + 1 sqrt + 3 (max of the excess, min 0, add) + 1 sub
+# + 1 min - 1 cmp = 35.
+FLOP_PAIR_DIST, FLOP_BOX_DIST = 11, 35
 PEAK_FP32_VALU_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FP32 FLOP/clk (published MI355X figure)
 
 WORKLOADS = {
@@ -34,7 +39,7 @@ WORKLOADS = {
                               "(half extents U[0.05,0.5] m, random yaw); margin 5 mm; 10 retries",
                          make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                       fromlist=["x"]).batched_scenes(4096, seed=seed),
-                         ncand=1024, cpu_scenes=160),
+                         ncand=1024, cpu_scenes=160, learned=True, dense=True),
     "table-1": dict(desc="1 scene; 1.2x0.8 m table; 8 objects x 32 spheres; 256 candidates; "
                          "4 cuboids; margin 5 mm; 10 retries",
                     make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
@@ -67,6 +72,115 @@ def recorded_traffic(workload: str, schedule: int):
     return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def learned_leg(ctx, db, b, W, args, stream, plain_rate):
+    """The learned-proposal form on the same scenes: harvest labels from plain
+    runs on three other seeds of the workload, train the network on the device
+    (untimed), then time generation with top-64 proposals and the uniform
+    fallback exactly like the plain leg."""
+    import torch
+    from paper_2512_16896_amd import learned as L
+    from paper_2512_16896_amd import scn
+    t0 = time.perf_counter()
+    parts = []
+    for k in range(3):
+        tb = W["make"](100 + k)
+        tdb = scn.DeviceBatch(tb, "cuda:0")
+        scn.generate_scenes(ctx, tdb, scn.GenArgs(seed=500 + k, default_ncand=W["ncand"]))
+        parts.append(L.harvest(ctx, tdb, seed=900 + k, labels_per_state=64))
+        del tdb
+    data = L.merge(parts)
+    del parts
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    net = scn.Network()
+    net.init(ctx, 1)
+    t0 = time.perf_counter()
+    log = L.train(ctx, net, data, steps=6000, batch=256, lr=1e-3, log_every=3000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_labels = int(data.bins.numel())
+    del data
+    gen = lambda step: scn.generate_scenes_learned(
+        ctx, db, scn.GenArgs(seed=1000 + step, default_ncand=W["ncand"]), net, top_k=64)
+    for i in range(max(args.warmup, 1)):
+        gen(-1 - i)
+    torch.cuda.synchronize()
+    ctx.reset_counters()
+    steps = args.steps
+    t0 = time.perf_counter()
+    for k in range(steps):
+        gen(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cnt = ctx.read_counters()
+    _, rec = db.records()
+    prop = rec[:, 0] == -2
+    placed = rec[:, 1] >= 0
+    rate = cnt["valid_scenes"] / wall
+    return {"value": rate, "unit": "valid scenes/s", "ms_per_step": 1e3 * wall / steps,
+            "valid_fraction": cnt["valid_scenes"] / (b.n_scenes * steps),
+            "candidate_checks_per_s": cnt["candidates"] / wall,
+            "vs_plain": rate / plain_rate,
+            "placed_by_proposal": float(prop.sum() / max(placed.sum(), 1)),
+            "rank0_accepted": float((prop & (rec[:, 1] == 0)).sum() / max(placed.sum(), 1)),
+            "training": {"labels": n_labels, "harvest_s": t_harvest, "steps": 6000, "batch": 256,
+                         "train_s": t_train, "loss_first": log[0][1], "loss_last": log[-1][1]}}
+
+
+def dense_leg(ctx, db, b, W, stream, seed=77):
+    """scn_check_batch in distance mode over a whole generation's states: for
+    every object position j, all candidates of object j of every scene against
+    the scene's boxes and its first min(j, placed) objects (the placement of the
+    last plain run).  Times the check launches only."""
+    import torch
+    from paper_2512_16896_amd import scn
+    n, C = b.n_scenes, W["ncand"]
+    final = db.n_placed.clone()
+    fin = final.cpu().numpy().astype(np.int64)
+    obj_off = np.asarray(b.obj_off, np.int64)
+    sph_off = np.asarray(b.sph_off, np.int64)
+    nobj = obj_off[1:] - obj_off[:-1]
+    nbox = np.diff(np.asarray(b.box_off, np.int64))
+    cand_off = torch.arange(0, (n + 1) * C, C, dtype=torch.int32, device="cuda:0")
+    dnobj = torch.as_tensor(nobj, dtype=torch.int32, device="cuda:0")
+    doff = db.obj_off[:-1]
+    pairs = boxes = xf = 0
+    launches = []
+    for j in range(int(nobj.max())):
+        oi = torch.where(dnobj > j, doff + j, torch.full_like(dnobj, -1)).to(torch.int32)
+        npl = torch.minimum(final, torch.full_like(final, j))
+        poses = scn.sample_poses(ctx, db, oi, cand_off, n * C, C, seed, 0)
+        launches.append((oi, npl, poses))
+        live = nobj > j
+        o = obj_off[:-1][live] + j
+        S = sph_off[o + 1] - sph_off[o]
+        P = sph_off[obj_off[:-1][live] + np.minimum(j, fin[live])] - sph_off[obj_off[:-1][live]]
+        pairs += int(np.sum(C * S * P))
+        boxes += int(np.sum(C * S * nbox[live]))
+        xf += int(np.sum(C * S))
+    ms = []
+    for rep in range(3):
+        tot = 0.0
+        for oi, npl, poses in launches:
+            db.n_placed.copy_(npl)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            scn.check_batch(ctx, db, oi, cand_off, n * C, C, poses)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+        ms.append(tot)
+    db.n_placed.copy_(final)
+    t = min(ms) * 1e-3
+    flop = FLOP_PAIR_DIST * pairs + FLOP_BOX_DIST * boxes + FLOP_XFORM * xf
+    return {"candidate_checks_per_s": n * C * len(launches) / t, "pairs_per_s": pairs / t,
+            "ms_per_pass": 1e3 * t, "launches": len(launches),
+            "roofline": {"bound": "alu", "achieved": flop / t / 1e12,
+                         "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flop / t / 1e12 / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                         "kernel": "k_check (dense, distance mode)"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +190,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and timing the learned-proposal form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -143,6 +259,10 @@ def main():
                      "kernel": "k_place (fused place kernel)",
                      "kernel_ms": launch_ms},
     }
+    if W.get("dense"):
+        out["dense_check"] = dense_leg(ctx, db, b, W, stream)
+    if W.get("learned") and not args.no_learned:
+        out["learned"] = learned_leg(ctx, db, b, W, args, stream, valid / wall)
     if not args.no_cpu_baseline:
         import oracle
         from paper_2512_16896_amd import scenegen as sg

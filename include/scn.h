@@ -135,7 +135,10 @@ typedef struct {
     int32_t max_steps;     /* scn_generate_scenes: objects per scene (<= 0: all)    */
     int32_t schedule;      /* 0: autotuned / default; >0: explicit schedule id      */
     int32_t use_graph;     /* scn_generate_scenes: replay a captured hipGraph       */
-    int32_t reserved[4];   /* zero                                                  */
+    int32_t fallback_chunk;/* scn_generate_scenes_learned: uniform fallback entries
+                            * tried per step launch (0: one attempt of the largest
+                            * candidate count; < 0: the whole fallback at once)     */
+    int32_t reserved[3];   /* zero                                                  */
 } scn_gen_args;
 
 /* Work counters accumulated on the device since the last scn_reset_counters. */
@@ -346,7 +349,12 @@ int scn_harvest_labels(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state,
  * pose bins of its state with the network, its top_k bins (one pose drawn in
  * each) are checked in rank order before the uniform attempts, and the exact
  * check alone decides validity.  Records of proposal picks have attempt = -2
- * and idx = rank.  Synchronous with `stream` only through its own launches. */
+ * and idx = rank.  Runs as a sequence of step launches; each tries the
+ * proposals and args->fallback_chunk uniform entries of every scene's current
+ * object and resumes the rest in the next launch, which gives the same
+ * placements as one pass over the whole list.  The host waits on `stream`
+ * after each step launch to read how many scenes still have work (one int),
+ * so the call returns with the stream drained.                              */
 int scn_generate_scenes_learned(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
                                 const scn_mlp *net, int32_t top_k, scn_stream stream);
 

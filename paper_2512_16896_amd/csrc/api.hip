@@ -126,6 +126,7 @@ int scn_ctx_destroy(scn_ctx* c) {
     if (c->d_order) (void)hipFree(c->d_order);
     if (c->d_hist) (void)hipFree(c->d_hist);
     if (c->ws) (void)hipFree(c->ws);
+    if (c->h_flag) (void)hipHostFree(c->h_flag);
     delete c;
     return SCN_OK;
 }
@@ -303,14 +304,19 @@ int scn_place_step(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int32_t* cho
 
 // Plan + launch of the fused place kernel with an optional proposal list
 // (used by the learned generation pipeline; not part of the ABI).
-__attribute__((visibility("hidden"))) int scn_place_internal(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps,
-                       int32_t* chosen, bool reset, const int32_t* prop_bins, int prop_k,
-                       hipStream_t st) {
+__attribute__((visibility("hidden"))) int scn_place_internal(
+    scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps, int32_t* chosen, bool reset,
+    const int32_t* prop_bins, int prop_k, int32_t* resume, int chunk, int j_cap,
+    int32_t* n_active, hipStream_t st) {
     if (int r = check_batch(b, true)) return r;
     scn::PlacePlan plan;
     if (int r = plan_place(c, b, a, max_steps, &plan)) return r;
     plan.prop_bins = prop_bins;
     plan.prop_k = prop_bins ? prop_k : 0;
+    plan.resume = resume;
+    plan.chunk = chunk;
+    plan.j_cap = j_cap;
+    plan.n_active = n_active;
     return run_place(c, b, a, plan, chosen, reset, st);
 }
 

@@ -20,6 +20,7 @@ struct scn_ctx {
     int order_cap;
     void* ws;              // grow-only workspace arena (network activations, staging)
     size_t ws_bytes;
+    int32_t* h_flag = nullptr;   // pinned host word for small device-to-host reads
     struct Tuned { int schedule; float ms; };
     std::map<std::string, Tuned> tuned;   // autotuned schedule per batch shape bucket
 };
@@ -66,6 +67,14 @@ struct PlacePlan {
     int max_steps;    // objects to place per scene in this launch (<= 0: all)
     const int32_t* prop_bins = nullptr;  // learned proposal: [n_scenes][prop_k] bins, rank order
     int prop_k = 0;
+    // Resumable lists (learned path): a launch tries the proposals plus
+    // `chunk` uniform entries of the current object (then `chunk` per launch)
+    // and, when none is valid and entries remain, leaves the object pending
+    // with resume[s] = the next entry.  chunk <= 0: the whole list.
+    int32_t* resume = nullptr;
+    int chunk = 0;
+    int j_cap = 0;                 // objects per scene in total (<= 0: all)
+    int32_t* n_active = nullptr;   // += 1 per scene left active with work remaining
 };
 
 // learned-proposal kernels (learned.hip)
@@ -73,7 +82,8 @@ hipError_t launch_descriptor(const scn_batch& b, float* desc, hipStream_t st);
 hipError_t launch_hmap_boxes(const scn_batch& b, float* hmap, hipStream_t st);
 hipError_t launch_hmap_raise(const scn_batch& b, const int32_t* obj_idx, const int32_t* n_state,
                              float* hmap, hipStream_t st);
-hipError_t launch_next_object(const scn_batch& b, int32_t* obj_idx, hipStream_t st);
+hipError_t launch_next_object(const scn_batch& b, const int32_t* resume, int j_cap,
+                              int32_t* obj_idx, hipStream_t st);
 hipError_t launch_last_object(const scn_batch& b, const int32_t* before, int32_t* obj_idx,
                               hipStream_t st);
 hipError_t launch_features(int n, const float* hmap, const float* desc, const int32_t* obj_idx,
@@ -83,6 +93,7 @@ hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active,
 hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,
                           int round, float margin, int32_t* bins, float* accept, hipStream_t st);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);   // kernels.hip
 
 hipError_t launch_reset(const scn_batch& b, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int n, int64_t v, hipStream_t st);

@@ -246,6 +246,12 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_longest_first(const scn_batch& b, int32_t* order, int32_t* hist,
                                 hipStream_t st) {
     const int n = b.n_scenes;

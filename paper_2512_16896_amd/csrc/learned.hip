@@ -5,7 +5,8 @@
 //   k_hmap_boxes     64 x 64 height map of a scene's support from its boxes
 //   k_hmap_raise     raise the map by one placed object's spheres
 //   k_features       BF16 network input rows: [10 x height map, descriptor]
-//   k_topk           top-k pose bins per state (bitonic sort in LDS)
+//   k_topk_*         top-k pose bins per state (radix selection, or a
+//                    bitonic sort in LDS for large k)
 //   k_harvest        uniform label candidates of a state with their bins and
 //                    accept / reject from the exact checker (distance form)
 #include <climits>
@@ -235,20 +236,26 @@ hipError_t launch_hmap_raise(const scn_batch& b, const int32_t* obj_idx, const i
     return hipGetLastError();
 }
 
-// The object each scene places next (n_placed[s]) if the scene is active, else -1.
+// The object each scene starts next (n_placed[s]) if the scene is active, has
+// no pending object (resume[s] == 0) and is below the objects cap; else -1.
 __global__ void k_next_object(int n, const int32_t* __restrict__ obj_off,
                               const int32_t* __restrict__ n_placed,
-                              const int8_t* __restrict__ status, int32_t* __restrict__ obj_idx) {
+                              const int8_t* __restrict__ status,
+                              const int32_t* __restrict__ resume, int j_cap,
+                              int32_t* __restrict__ obj_idx) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int o = obj_off[s] + n_placed[s];
-    obj_idx[s] = (status[s] == SCN_SCENE_ACTIVE && o < obj_off[s + 1]) ? o : -1;
+    const bool fresh = !resume || resume[s] == 0;
+    const bool capped = j_cap > 0 && n_placed[s] >= j_cap;
+    obj_idx[s] = (status[s] == SCN_SCENE_ACTIVE && o < obj_off[s + 1] && fresh && !capped) ? o : -1;
 }
 
-hipError_t launch_next_object(const scn_batch& b, int32_t* obj_idx, hipStream_t st) {
+hipError_t launch_next_object(const scn_batch& b, const int32_t* resume, int j_cap,
+                              int32_t* obj_idx, hipStream_t st) {
     if (b.n_scenes == 0) return hipSuccess;
     hipLaunchKernelGGL(k_next_object, dim3((b.n_scenes + 255) / 256), dim3(256), 0, st, b.n_scenes,
-                       b.obj_off, b.n_placed, b.status, obj_idx);
+                       b.obj_off, b.n_placed, b.status, resume, j_cap, obj_idx);
     return hipGetLastError();
 }
 
@@ -311,31 +318,141 @@ hipError_t launch_features(int n, const float* hmap, const float* desc, const in
 }
 
 // ---------------------------------------------------------------------------
-// Top-k bins per row of logits [M][4096] (k <= 4096): bins in rank order
-// (logit descending, ties to the lower bin).  Rows with active[m] == 0 are
-// skipped (active may be nullptr).  One workgroup of 1024 threads per row; a
-// bitonic sort of 4096 64-bit keys in LDS.
+// Top-k bins per row of logits [M][4096]: bins in rank order (logit
+// descending, ties to the lower bin; NaN ranks last).  Rows with
+// active[m] < 0 are skipped (active may be nullptr).
+//
+// The rank order is the descending order of the unique 64-bit key
+// (orderable(logit) << 32) | (4095 - bin).
 __device__ __forceinline__ unsigned orderable(float f) {
     const unsigned u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
+__device__ __forceinline__ unsigned logit_key(float v) {
+    if (v != v) v = -__builtin_huge_valf();
+    if (v == 0.f) v = 0.f;   // -0 ties with +0
+    return orderable(v);
+}
 
-__global__ __launch_bounds__(1024) void k_topk(int M, const float* __restrict__ logits, int k,
-                                               const int32_t* __restrict__ active,
-                                               int32_t* __restrict__ bins) {
+// k <= kSelMax: radix selection of the k-th largest 32-bit value (four 8-bit
+// digits, histograms in LDS), then the values above it and the lowest-bin
+// ties at it are gathered and ranked by counting.  256 threads per row, 16
+// logits per thread (thread t owns bins 16t .. 16t+15).
+constexpr int kSelMax = 256;
+__global__ __launch_bounds__(256) void k_topk_select(int M, const float* __restrict__ logits, int k,
+                                                     const int32_t* __restrict__ active,
+                                                     int32_t* __restrict__ bins) {
+    __shared__ unsigned hist[256];
+    __shared__ unsigned s_prefix, s_need, s_count;
+    __shared__ unsigned s_tie_count[256];
+    __shared__ unsigned long long sel[kSelMax];
+    const int m = blockIdx.x;
+    if (m >= M) return;
+    if (active && active[m] < 0) return;
+    const int t = threadIdx.x;
+    const float4* z4 = reinterpret_cast<const float4*>(logits + (size_t)m * 4096) + 4 * t;
+    unsigned v[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 f = z4[q];
+        v[4 * q] = logit_key(f.x); v[4 * q + 1] = logit_key(f.y);
+        v[4 * q + 2] = logit_key(f.z); v[4 * q + 3] = logit_key(f.w);
+    }
+    if (t == 0) { s_prefix = 0u; s_need = (unsigned)k; s_count = 0u; }
+    // digit passes, most significant first: find the value T of rank k
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        const unsigned hi_mask = pass == 0 ? 0u : (0xFFFFFFFFu << (shift + 8));
+        hist[t] = 0u;
+        __syncthreads();
+        const unsigned prefix = s_prefix;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if ((v[i] & hi_mask) == prefix) atomicAdd(&hist[(v[i] >> shift) & 0xFFu], 1u);
+        __syncthreads();
+        if (t < 64) {
+            // wave 0 walks the digits from the top: 4 digits per lane
+            unsigned c[4], tot = 0u;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) { c[d] = hist[255 - (4 * t + d)]; tot += c[d]; }
+            // inclusive scan of lane totals (lane 0 = highest digits)
+            unsigned inc = tot;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned y = __shfl_up(inc, o, kWave);
+                if (t >= o) inc += y;
+            }
+            const unsigned need = s_need;
+            const unsigned before = inc - tot;
+            if (before < need && inc >= need) {
+                unsigned acc = before;
+                for (int d = 0; d < 4; ++d) {
+                    if (acc + c[d] >= need) {
+                        const unsigned digit = 255u - (unsigned)(4 * t + d);
+                        s_prefix = prefix | (digit << shift);
+                        s_need = need - acc;
+                        break;
+                    }
+                    acc += c[d];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const unsigned T = s_prefix;      // k-th largest value
+    const unsigned n_tie = s_need;    // ties at T that enter, lowest bins first
+    // count ties per thread, exclusive scan over threads (bin order)
+    unsigned ties = 0u;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ties += v[i] == T;
+    s_tie_count[t] = ties;
+    __syncthreads();
+    if (t < 64) {
+        unsigned c[4], tot = 0u;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) { c[d] = s_tie_count[4 * t + d]; tot += c[d]; }
+        unsigned inc = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned y = __shfl_up(inc, o, kWave);
+            if (t >= o) inc += y;
+        }
+        unsigned acc = inc - tot;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) { s_tie_count[4 * t + d] = acc; acc += c[d]; }
+    }
+    __syncthreads();
+    unsigned tie_rank = s_tie_count[t];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const unsigned bin = 16u * t + i;
+        const unsigned long long key = ((unsigned long long)v[i] << 32) | (4095u - bin);
+        bool take = v[i] > T;
+        if (v[i] == T) { take = tie_rank < n_tie; ++tie_rank; }
+        if (take) sel[atomicAdd(&s_count, 1u)] = key;
+    }
+    __syncthreads();
+    // rank by counting (keys are unique)
+    for (int i = t; i < k; i += 256) {
+        const unsigned long long a = sel[i];
+        int r = 0;
+        for (int j = 0; j < k; ++j) r += sel[j] > a;
+        bins[(size_t)m * k + r] = 4095 - (int)(a & 0xFFFFFFFFu);
+    }
+}
+
+// Any k: a bitonic sort of the 4096 keys in LDS, 1024 threads per row.
+__global__ __launch_bounds__(1024) void k_topk_sort(int M, const float* __restrict__ logits, int k,
+                                                    const int32_t* __restrict__ active,
+                                                    int32_t* __restrict__ bins) {
     __shared__ unsigned long long key[4096];
     const int m = blockIdx.x;
     if (m >= M) return;
     if (active && active[m] < 0) return;
     const float* z = logits + (size_t)m * 4096;
-    for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
-        float v = z[i];
-        if (v != v) v = -__builtin_huge_valf();   // NaN ranks last
-        // larger key = better: logit first, then the lower bin
-        key[i] = ((unsigned long long)orderable(v) << 32) | (unsigned)(4095 - i);
-    }
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x)
+        key[i] = ((unsigned long long)logit_key(z[i]) << 32) | (unsigned)(4095 - i);
     __syncthreads();
-    // bitonic sort, descending
     for (int size = 2; size <= 4096; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
@@ -356,7 +473,10 @@ __global__ __launch_bounds__(1024) void k_topk(int M, const float* __restrict__ 
 hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active, int32_t* bins,
                        hipStream_t st) {
     if (M == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_topk, dim3(M), dim3(1024), 0, st, M, logits, k, active, bins);
+    if (k <= kSelMax && ((uintptr_t)logits & 15u) == 0)
+        hipLaunchKernelGGL(k_topk_select, dim3(M), dim3(256), 0, st, M, logits, k, active, bins);
+    else
+        hipLaunchKernelGGL(k_topk_sort, dim3(M), dim3(1024), 0, st, M, logits, k, active, bins);
     return hipGetLastError();
 }
 

@@ -82,9 +82,10 @@ int scn_harvest_labels(scn_ctx* c, const scn_batch* b, const int32_t* n_state, i
 }
 
 // Defined in api.hip: plan and launch of the fused place kernel.
-__attribute__((visibility("hidden"))) int scn_place_internal(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps,
-                       int32_t* chosen, bool reset, const int32_t* prop_bins, int prop_k,
-                       hipStream_t st);
+__attribute__((visibility("hidden"))) int scn_place_internal(
+    scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps, int32_t* chosen, bool reset,
+    const int32_t* prop_bins, int prop_k, int32_t* resume, int chunk, int j_cap,
+    int32_t* n_active, hipStream_t st);
 
 int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
                                 const scn_mlp* net, int32_t top_k, scn_stream stream) {
@@ -97,6 +98,7 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
                         SCN_FEATURES, SCN_BINS);
     if (!b->placed || !b->n_placed || !b->status || !b->rec)
         return scn_fail(SCN_E_INVALID_ARG, "placed/n_placed/status/rec required");
+    if (a->retries < 0) return scn_fail(SCN_E_INVALID_ARG, "retries must be >= 0");
     const hipStream_t st = (hipStream_t)stream;
     const int n = b->n_scenes;
     if (n == 0) return SCN_OK;
@@ -107,9 +109,10 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     const size_t bytes = act + align256((size_t)n * SCN_HMAP_CELLS * 4) +
                          align256((size_t)b->n_objects * SCN_DESC * 4) +
                          align256((size_t)n * SCN_FEATURES * 2) + align256((size_t)n * SCN_BINS * 4) +
-                         align256((size_t)n * top_k * 4) + 3 * align256((size_t)n * 4);
+                         align256((size_t)n * top_k * 4) + 4 * align256((size_t)n * 4) + 256;
     void* ws;
     if (int r = scn_workspace(c, bytes, &ws)) return r;
+    if (!c->h_flag) SCN_HIP(hipHostMalloc((void**)&c->h_flag, sizeof(int32_t), hipHostMallocDefault));
     char* p = (char*)ws + act;
     auto take = [&](size_t sz) { void* q = p; p += align256(sz); return q; };
     float* hmap = (float*)take((size_t)n * SCN_HMAP_CELLS * 4);
@@ -120,21 +123,42 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     int32_t* obj_idx = (int32_t*)take((size_t)n * 4);
     int32_t* before = (int32_t*)take((size_t)n * 4);
     int32_t* placed_now = (int32_t*)take((size_t)n * 4);
+    int32_t* resume = (int32_t*)take((size_t)n * 4);
+    int32_t* n_active = (int32_t*)take(4);
+
+    const int j_cap = a->max_steps > 0 && a->max_steps < b->max_objects_per_scene ? a->max_steps : 0;
+    // uniform entries tried per launch: one attempt of the default size, so
+    // that a launch never waits on one scene's whole fallback
+    const int chunk = a->fallback_chunk < 0 ? 0
+                      : a->fallback_chunk > 0 ? a->fallback_chunk
+                      : (b->max_cand_per_object > 0 ? b->max_cand_per_object : a->default_ncand);
+    // every launch makes progress on each active scene (a placement, the
+    // invalid mark, or `chunk` more entries), which bounds the launches
+    long long c_max = b->max_cand_per_object > 0 ? b->max_cand_per_object : a->default_ncand;
+    if (c_max < 1) c_max = 1;
+    const long long per_obj = chunk > 0 ? 1 + ((long long)(a->retries + 1) * c_max + chunk - 1) / chunk : 1;
+    const long long max_launch = (long long)(j_cap > 0 ? j_cap : b->max_objects_per_scene) * per_obj + 1;
 
     SCN_HIP(scn::launch_reset(*b, st));
+    SCN_HIP(scn::launch_fill_i32(resume, n, 0, st));
     SCN_HIP(scn::launch_descriptor(*b, desc, st));
     SCN_HIP(scn::launch_hmap_boxes(*b, hmap, st));
-    const int steps = a->max_steps > 0 && a->max_steps < b->max_objects_per_scene
-                          ? a->max_steps : b->max_objects_per_scene;
-    for (int j = 0; j < steps; ++j) {
-        SCN_HIP(scn::launch_next_object(*b, obj_idx, st));
+    for (long long it = 0; it < max_launch; ++it) {
+        // scenes that start a new object get a proposal; pending ones resume
+        SCN_HIP(scn::launch_next_object(*b, resume, j_cap, obj_idx, st));
         SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, st));
         if (int r = scn_mlp_forward(c, net, x, n, logits, stream)) return r;
         SCN_HIP(scn::launch_topk(n, logits, top_k, obj_idx, bins, st));
         SCN_HIP(scn::launch_copy_i32(b->n_placed, before, n, st));
-        if (int r = scn_place_internal(c, b, a, 1, nullptr, false, bins, top_k, st)) return r;
+        SCN_HIP(scn::launch_fill_i32(n_active, 1, 0, st));
+        if (int r = scn_place_internal(c, b, a, 1, nullptr, false, bins, top_k, resume, chunk,
+                                       j_cap, n_active, st))
+            return r;
         SCN_HIP(scn::launch_last_object(*b, before, placed_now, st));
         SCN_HIP(scn::launch_hmap_raise(*b, placed_now, nullptr, hmap, st));
+        SCN_HIP(hipMemcpyAsync(c->h_flag, n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SCN_HIP(hipStreamSynchronize(st));
+        if (*c->h_flag == 0) break;
     }
     return SCN_OK;
 }

@@ -88,6 +88,7 @@ __global__ __launch_bounds__(1024) void k_place(
     unsigned long long* __restrict__ counters, const int32_t* __restrict__ order, uint64_t seed,
     float margin, int retries, int default_ncand, int max_steps, int cap_sph, int cap_obj,
     int split, int split_sph, const int32_t* __restrict__ prop_bins, int prop_k,
+    int32_t* __restrict__ resume, int chunk, int j_cap, int32_t* __restrict__ n_active,
     const int32_t* __restrict__ grid_off, const float* __restrict__ grid,
     const int32_t* __restrict__ grid_src, const int64_t* __restrict__ grid_val_off,
     const float* __restrict__ grid_val) {
@@ -127,7 +128,16 @@ __global__ __launch_bounds__(1024) void k_place(
         return;
     }
     int j = min(max(n_placed[s], 0), nobj);
-    const int j_end = max_steps > 0 ? min(nobj, j + max_steps) : nobj;
+    int j_end = max_steps > 0 ? min(nobj, j + max_steps) : nobj;
+    if (j_cap > 0) j_end = min(j_end, j_cap);
+    if (j >= j_end) {   // nothing to place in this launch (objects-per-scene cap)
+        if (chosen && threadIdx.x == 0) chosen[s] = -1;
+        return;
+    }
+    // entry of the current object's list to resume at (learned path)
+    const int resume0 = resume ? max(resume[s], 0) : 0;
+    const int j_start = j;
+    int pend = 0;
     // placed sphere k of this scene, radius grown by the margin
     auto placed_sphere = [&](int k) -> float4 {
         if constexpr (kLds) {
@@ -225,6 +235,13 @@ __global__ __launch_bounds__(1024) void k_place(
         const int pk = prop_bins ? prop_k : 0;
         const int32_t* pb = prop_bins ? prop_bins + (size_t)s * prop_k : nullptr;
         const int total = pk + (C > 0 ? (retries + 1) * C : 0);   // entries of the list
+        // entries [g_lo, g_hi) of the list are tried in this launch: with a
+        // chunk, the proposals plus `chunk` uniform entries, then `chunk` more
+        // per launch; earlier launches found none of the entries before g_lo
+        // valid, so the lowest valid entry of [g_lo, g_hi) is the first valid
+        // one of the whole list
+        const int g_lo = j == j_start ? min(resume0, total) : 0;
+        const int g_hi = chunk > 0 ? min(total, max(g_lo, pk) + chunk) : total;
         const int nob_mask = min(j, kWave * kObjWords);     // objects covered by the masks
 
         if (threadIdx.x == 0) s_best = INT_MAX;
@@ -280,13 +297,14 @@ __global__ __launch_bounds__(1024) void k_place(
 
         bool stop = false;
         for (int base = 0; !stop; base += kWave) {
-            if (wave + W * base >= total) break;
+            const int gb = g_lo + wave + W * base;
+            if (gb >= g_hi) break;
             if (uniform_int(__hip_atomic_load(&s_best, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_WORKGROUP)) < wave + W * base)
+                                              __HIP_MEMORY_SCOPE_WORKGROUP)) < gb)
                 break;
-            // ---- batch phase: lane t holds candidate entry wave + W (base + t) ----
-            const int g = wave + W * (base + lane);
-            const bool live = g < total;
+            // ---- batch phase: lane t holds entry g_lo + wave + W (base + t) ----
+            const int g = gb + W * lane;
+            const bool live = g < g_hi;
             int ga, gi;
             const Pose L = entry_pose(live ? g : 0, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
                                       ay, zc, &ga, &gi);
@@ -316,8 +334,8 @@ __global__ __launch_bounds__(1024) void k_place(
             }
             // ---- candidate phase ----
             for (int t = 0; t < kWave; ++t) {
-                const int gt = wave + W * (base + t);
-                if (gt >= total) { stop = true; break; }
+                const int gt = gb + W * t;
+                if (gt >= g_hi) { stop = true; break; }
                 if (uniform_int(__hip_atomic_load(&s_best, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP)) < gt) {
                     stop = true;
@@ -396,6 +414,11 @@ __global__ __launch_bounds__(1024) void k_place(
         }
         __syncthreads();
         const int best = s_best;
+        if (best == INT_MAX && g_hi < total) {   // entries left for a later launch
+            pend = g_hi;
+            last = -1;
+            break;
+        }
         if (wave == 0)
             n_att += (pk ? 1u : 0u) +
                      (best == INT_MAX ? (unsigned)(retries + 1)
@@ -429,9 +452,11 @@ __global__ __launch_bounds__(1024) void k_place(
     }
     if (threadIdx.x == 0) {
         n_placed[s] = j;
+        if (resume) resume[s] = pend;
         const int8_t st = fin != SCN_SCENE_ACTIVE ? fin
                                                   : (j == nobj ? SCN_SCENE_VALID : SCN_SCENE_ACTIVE);
         status[s] = st;
+        if (n_active && st == SCN_SCENE_ACTIVE && (j_cap <= 0 || j < j_cap)) atomicAdd(n_active, 1);
         if (chosen) chosen[s] = last;
         if (st == SCN_SCENE_VALID) atomicAdd(counters + kValidScenes, 1ull);
         if (st == SCN_SCENE_INVALID) atomicAdd(counters + kInvalidScenes, 1ull);
@@ -466,7 +491,8 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                        b.box_off, b.box, (float4*)b.placed, b.n_placed, b.status, b.rec, chosen,
                        ctr, plan.order, a.seed, a.margin, a.retries, a.default_ncand,
                        plan.max_steps, cap_sph, plan.cap_obj, split, plan.split_sph,
-                       plan.prop_bins, plan.prop_k, b.grid_off, b.grid, b.grid_src,
+                       plan.prop_bins, plan.prop_k, plan.resume, plan.chunk, plan.j_cap,
+                       plan.n_active, b.grid_off, b.grid, b.grid_src,
                        b.grid_val_off, b.grid_val);
     return hipGetLastError();
 }

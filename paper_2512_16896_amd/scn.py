@@ -52,7 +52,7 @@ class _GenArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("margin", C.c_float), ("retries", C.c_int32),
                 ("default_ncand", C.c_int32), ("max_steps", C.c_int32),
                 ("schedule", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("fallback_chunk", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Counters(C.Structure):
@@ -206,12 +206,14 @@ class GenArgs:
     max_steps: int = 0
     schedule: int = 0
     use_graph: int = 0
+    fallback_chunk: int = 0
 
     def c(self) -> _GenArgs:
         a = _GenArgs()
         a.seed, a.margin, a.retries = int(self.seed) & (2 ** 64 - 1), float(self.margin), int(self.retries)
         a.default_ncand, a.max_steps = int(self.default_ncand), int(self.max_steps)
         a.schedule, a.use_graph = int(self.schedule), int(self.use_graph)
+        a.fallback_chunk = int(self.fallback_chunk)
         return a
 
 

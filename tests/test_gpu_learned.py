@@ -177,9 +177,19 @@ def test_topk_matches_oracle_with_ties(dev):
     z = rng.standard_normal((40, 4096)).astype(np.float32)
     z[3, 100:200] = 5.0                       # a block of ties at the top
     z[4, :] = 0.0                             # all equal
-    got = scn.proposal_topk(ctx, torch.tensor(z, device="cuda"), 64).cpu().numpy()
-    for m in range(40):
-        assert got[m].tolist() == ol.topk(z[m].astype(np.float64), 64).tolist()
+    z[5, :] = rng.integers(-3, 4, 4096)       # many ties, threshold inside a tie block
+    z[6, 7::13] = np.nan                      # NaN ranks last
+    z[7, :] = 0.0
+    z[7, 1::2] = -0.0                         # -0 ties with +0
+    z[8, :] = -np.inf
+    z[8, 4000:] = np.float32(1e-30)
+    z[9, :60] = 2.0
+    z[9, 1000:1020] = 1.5                     # exactly 60 above, ties straddle k = 64
+    zt = torch.tensor(z, device="cuda")
+    for k in (1, 64, 65, 256, 257, 4096):     # selection path (k <= 256) and full sort
+        got = scn.proposal_topk(ctx, zt, k).cpu().numpy()
+        for m in range(40):
+            assert got[m].tolist() == ol.topk(z[m].astype(np.float64), k).tolist(), (k, m)
     act = torch.tensor([0 if m % 2 else -1 for m in range(40)], dtype=torch.int32, device="cuda")
     got2 = scn.proposal_topk(ctx, torch.tensor(z, device="cuda"), 5, active=act).cpu().numpy()
     assert np.all(got2[0::2] == -1) and got2[1].tolist() == ol.topk(z[1].astype(np.float64), 5).tolist()
@@ -278,3 +288,34 @@ def test_learned_generation_matches_oracle(dev, orc):
         if sure:
             assert status[s] == ref["status"][s]
     assert n_cmp > 0.5 * b.n_objects and n_prop > 0
+
+
+def test_learned_generation_chunking_is_invisible(dev):
+    """The step launches try the proposals plus a chunk of the uniform
+    fallback and resume the rest later; any chunk gives the placements of one
+    pass over the whole list (and max_steps caps the objects per scene)."""
+    scn, ctx, torch = dev
+    b = sg.batched_scenes(48, seed=15)
+    W, bb = _weights(22)
+    net = _net(scn, torch, W, bb)
+    out = []
+    for chunk in (-1, 0, 100, 4096):
+        db = scn.DeviceBatch(b)
+        scn.generate_scenes_learned(ctx, db, scn.GenArgs(seed=3, fallback_chunk=chunk), net, top_k=64)
+        torch.cuda.synchronize()
+        rec_f, rec_i = db.records()
+        out.append((db.status.cpu().numpy(), db.n_placed.cpu().numpy(), rec_i, rec_f,
+                    db.placed.cpu().numpy()))
+    for o in out[1:]:
+        for u, v in zip(out[0], o):
+            np.testing.assert_array_equal(u, v)
+    assert np.any(out[0][2][:, 0] >= 1)        # some objects needed the fallback
+    db = scn.DeviceBatch(b)
+    scn.generate_scenes_learned(ctx, db, scn.GenArgs(seed=3, max_steps=4), net, top_k=64)
+    torch.cuda.synchronize()
+    npl = db.n_placed.cpu().numpy()
+    assert np.all(npl <= 4) and np.all(npl == np.minimum(out[0][1], 4))
+    _, rec_i = db.records()
+    for s in range(b.n_scenes):
+        o0 = b.obj_off[s]
+        np.testing.assert_array_equal(rec_i[o0:o0 + npl[s]], out[0][2][o0:o0 + npl[s]])
