@@ -52,16 +52,24 @@ WORKLOADS = {
                          make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                       fromlist=["x"]).uneven_batch(16384, seed=seed),
                          ncand=1024, cpu_scenes=24, tune=True),
+    "shelves-65536": dict(desc="65536 scenes x 6 stacked 0.8x0.4 m shelves; 100 objects x 128 "
+                               "spheres (r~U[0.005,0.02] m, centres in a cube of side "
+                               "U[0.03,0.08] m), round-robin over the shelves; furniture as "
+                               "64^3 signed-distance grids (one shared asset, 6 instances per "
+                               "scene), trilinear; 2048 candidates per attempt; margin 5 mm; "
+                               "10 retries; autotuned launch",
+                          make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                       fromlist=["x"]).shelf_scenes(65536, seed=seed),
+                          ncand=2048, cpu_scenes=0, tune=True),
 }
 
 
-def recorded_traffic(workload: str, schedule: int):
+def recorded_traffic(key: str):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE runs kept in
-    profiles/traffic.json -- only while the place kernel's sources are the ones
-    those counters were taken on (else None)."""
+    profiles/traffic.json -- only while the kernel's sources are the ones those
+    counters were taken on (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    key = f"k_place {workload} {'default' if schedule == 0 else hex(schedule)}"
     try:
         rec = json.load(open(path))[key]
     except (OSError, KeyError, ValueError):
@@ -70,6 +78,10 @@ def recorded_traffic(workload: str, schedule: int):
     for f in rec["sources"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def learned_leg(ctx, db, b, W, args, stream, plain_rate):
@@ -177,7 +189,8 @@ def dense_leg(ctx, db, b, W, stream, seed=77):
             "ms_per_pass": 1e3 * t, "launches": len(launches),
             "roofline": {"bound": "alu", "achieved": flop / t / 1e12,
                          "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                         "frac": flop / t / 1e12 / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                         "frac": flop / t / 1e12 / PEAK_FP32_VALU_TFLOPS,
+                         "traffic": recorded_traffic(f"k_check dense {b.name}"),
                          "kernel": "k_check (dense, distance mode)"}}
 
 
@@ -203,7 +216,9 @@ def main():
     from paper_2512_16896_amd import scn
 
     W = WORKLOADS[args.workload]
+    progress(f"building {args.workload}")
     b = W["make"](args.seed)
+    progress("uploading")
     torch.cuda.set_device(0)
     ctx = scn.Context(0)
     db = scn.DeviceBatch(b, "cuda:0")
@@ -213,7 +228,9 @@ def main():
 
     tuned = None
     if W.get("tune") and args.schedule == 0:
+        progress("autotuning")
         tuned = ctx.autotune(db, scn.GenArgs(seed=999, default_ncand=W["ncand"]))
+    progress("timing")
     for i in range(args.warmup):
         gen(-1 - i)
     torch.cuda.synchronize()
@@ -255,15 +272,20 @@ def main():
         "counters_per_step": {k: v / steps for k, v in cnt.items() if k != "error_word"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": recorded_traffic(args.workload, args.schedule),
+                     "traffic": recorded_traffic(
+                         f"k_place {args.workload} "
+                         f"{'default' if args.schedule == 0 else hex(args.schedule)}"),
                      "kernel": "k_place (fused place kernel)",
                      "kernel_ms": launch_ms},
     }
     if W.get("dense"):
+        progress("dense check")
         out["dense_check"] = dense_leg(ctx, db, b, W, stream)
     if W.get("learned") and not args.no_learned:
+        progress("learned form: harvest, training, timing")
         out["learned"] = learned_leg(ctx, db, b, W, args, stream, valid / wall)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and W["cpu_scenes"] > 0:
+        progress("cpu baseline")
         import oracle
         from paper_2512_16896_amd import scenegen as sg
         k = min(W["cpu_scenes"], n)

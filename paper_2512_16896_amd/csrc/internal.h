@@ -74,7 +74,8 @@ struct PlacePlan {
     int32_t* resume = nullptr;
     int chunk = 0;
     int j_cap = 0;                 // objects per scene in total (<= 0: all)
-    int32_t* n_active = nullptr;   // += 1 per scene left active with work remaining
+    int32_t* n_active = nullptr;   // [2]: scenes left active with work remaining, and those
+                                   // of them that start a new object next
 };
 
 // learned-proposal kernels (learned.hip)

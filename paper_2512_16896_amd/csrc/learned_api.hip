@@ -112,7 +112,7 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
                          align256((size_t)n * top_k * 4) + 4 * align256((size_t)n * 4) + 256;
     void* ws;
     if (int r = scn_workspace(c, bytes, &ws)) return r;
-    if (!c->h_flag) SCN_HIP(hipHostMalloc((void**)&c->h_flag, sizeof(int32_t), hipHostMallocDefault));
+    if (!c->h_flag) SCN_HIP(hipHostMalloc((void**)&c->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
     char* p = (char*)ws + act;
     auto take = [&](size_t sz) { void* q = p; p += align256(sz); return q; };
     float* hmap = (float*)take((size_t)n * SCN_HMAP_CELLS * 4);
@@ -124,7 +124,7 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     int32_t* before = (int32_t*)take((size_t)n * 4);
     int32_t* placed_now = (int32_t*)take((size_t)n * 4);
     int32_t* resume = (int32_t*)take((size_t)n * 4);
-    int32_t* n_active = (int32_t*)take(4);
+    int32_t* n_active = (int32_t*)take(8);
 
     const int j_cap = a->max_steps > 0 && a->max_steps < b->max_objects_per_scene ? a->max_steps : 0;
     // uniform entries tried per launch: one attempt of the default size, so
@@ -143,22 +143,28 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     SCN_HIP(scn::launch_fill_i32(resume, n, 0, st));
     SCN_HIP(scn::launch_descriptor(*b, desc, st));
     SCN_HIP(scn::launch_hmap_boxes(*b, hmap, st));
+    bool fresh = true;   // some scene starts a new object (needs the network)
     for (long long it = 0; it < max_launch; ++it) {
         // scenes that start a new object get a proposal; pending ones resume
-        SCN_HIP(scn::launch_next_object(*b, resume, j_cap, obj_idx, st));
-        SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, st));
-        if (int r = scn_mlp_forward(c, net, x, n, logits, stream)) return r;
-        SCN_HIP(scn::launch_topk(n, logits, top_k, obj_idx, bins, st));
+        // their fallback and need none (a launch with only those skips the
+        // network)
+        if (fresh) {
+            SCN_HIP(scn::launch_next_object(*b, resume, j_cap, obj_idx, st));
+            SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, st));
+            if (int r = scn_mlp_forward(c, net, x, n, logits, stream)) return r;
+            SCN_HIP(scn::launch_topk(n, logits, top_k, obj_idx, bins, st));
+        }
         SCN_HIP(scn::launch_copy_i32(b->n_placed, before, n, st));
-        SCN_HIP(scn::launch_fill_i32(n_active, 1, 0, st));
+        SCN_HIP(scn::launch_fill_i32(n_active, 2, 0, st));
         if (int r = scn_place_internal(c, b, a, 1, nullptr, false, bins, top_k, resume, chunk,
                                        j_cap, n_active, st))
             return r;
         SCN_HIP(scn::launch_last_object(*b, before, placed_now, st));
         SCN_HIP(scn::launch_hmap_raise(*b, placed_now, nullptr, hmap, st));
-        SCN_HIP(hipMemcpyAsync(c->h_flag, n_active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        SCN_HIP(hipMemcpyAsync(c->h_flag, n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         SCN_HIP(hipStreamSynchronize(st));
-        if (*c->h_flag == 0) break;
+        if (c->h_flag[0] == 0) break;
+        fresh = c->h_flag[1] > 0;
     }
     return SCN_OK;
 }

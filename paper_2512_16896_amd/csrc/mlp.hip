@@ -25,69 +25,106 @@ __device__ __forceinline__ float bf2f(__bf16 v) { return (float)v; }
 __device__ __forceinline__ __bf16 f2bf(float v) { return (__bf16)v; }   // round to nearest even
 
 // ---------------------------------------------------------------------------
-// GEMM.  Workgroup tile 64 x 64, 4 waves of 32 x 32 (2 x 2 MFMA 16x16x32 tiles),
-// K in steps of 32.  Operand fragments come straight from global memory
-// (L1/L2): lane l reads row (l % 16) of a 16-row fragment, 8 BF16 at column
-// 8 (l / 16) of the 32-wide K step.  The result for lane l of a 16 x 16 tile is
-// rows 4 (l / 16) .. +3 of column l % 16.  Rows / columns past M / N are
-// clamped on load and skipped on store.  K must be a multiple of 32.
-template <bool kBias, bool kRelu>
+// GEMM.  Workgroup tile BM x BN (128 x 128 or 64 x 64), 4 waves in a 2 x 2
+// grid, each wave (BM/2) x (BN/2) of MFMA 16x16x32 tiles; K in steps of 32.
+// Both operand tiles of a step (BM x 32 and BN x 32 BF16) are staged in LDS,
+// double-buffered: the global loads of step k+1 are in flight while the waves
+// run step k's MFMAs from LDS, one barrier per step.  LDS rows are padded to
+// 40 BF16 (80 B) so the 16 rows a fragment read touches fall in distinct
+// banks.  Fragment layout (v_mfma_f32_16x16x32_bf16): lane l supplies row
+// l % 16 of a 16-row fragment, 8 BF16 at column 8 (l / 16) of the K step; the
+// result for lane l is rows 4 (l / 16) .. +3 of column l % 16.  Rows / columns
+// past M / N are clamped on load and skipped on store.  K % 32 == 0.
+constexpr int kLdsRow = 40;
+
+template <int BM, int BN, bool kBias, bool kRelu>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const __bf16* __restrict__ A,
                                              int lda, const __bf16* __restrict__ B, int ldb,
                                              const float* __restrict__ bias, float* __restrict__ C32,
                                              __bf16* __restrict__ C16, int ldc) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
-    const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+    constexpr int FM = BM / 32, FN = BN / 32;       // 16 x 16 fragments per wave
+    constexpr int LA = BM / 64, LB = BN / 64;       // 16-B global loads per thread
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][BM * kLdsRow];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN * kLdsRow];
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
+    const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
     const int r = lane & 15, kq = (lane >> 4) * 8;
-    const __bf16* pa[2];
-    const __bf16* pb[2];
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+
+    // global source and LDS destination of this thread's chunks
+    const __bf16* ga[LA];
+    const __bf16* gb[LB];
+    int la[LA], lb[LB];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        pa[t] = A + (size_t)min(m0 + 16 * t + r, M - 1) * lda + kq;
-        pb[t] = B + (size_t)min(n0 + 16 * t + r, N - 1) * ldb + kq;
+    for (int i = 0; i < LA; ++i) {
+        const int c = t + 256 * i, row = c >> 2, col = (c & 3) * 8;
+        ga[i] = A + (size_t)min(bm + row, M - 1) * lda + col;
+        la[i] = row * kLdsRow + col;
     }
-    f32x4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 fa[2], fb[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        fa[t] = *(const bf16x8*)pa[t];
-        fb[t] = *(const bf16x8*)pb[t];
+    for (int i = 0; i < LB; ++i) {
+        const int c = t + 256 * i, row = c >> 2, col = (c & 3) * 8;
+        gb[i] = B + (size_t)min(bn + row, N - 1) * ldb + col;
+        lb[i] = row * kLdsRow + col;
     }
+    bf16x8 ra[LA], rb[LB];
+#pragma unroll
+    for (int i = 0; i < LA; ++i) ra[i] = *(const bf16x8*)ga[i];
+#pragma unroll
+    for (int i = 0; i < LB; ++i) rb[i] = *(const bf16x8*)gb[i];
+#pragma unroll
+    for (int i = 0; i < LA; ++i) *(bf16x8*)&As[0][la[i]] = ra[i];
+#pragma unroll
+    for (int i = 0; i < LB; ++i) *(bf16x8*)&Bs[0][lb[i]] = rb[i];
+    __syncthreads();
+
+    f32x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    int cur = 0;
     for (int k = 32; k <= K; k += 32) {
-        bf16x8 na[2], nb[2];
-        if (k < K) {   // issue the next step's loads before this step's MFMAs
+        const bool more = k < K;
+        if (more) {   // next step's operands, in flight during this step's MFMAs
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                na[t] = *(const bf16x8*)(pa[t] + k);
-                nb[t] = *(const bf16x8*)(pb[t] + k);
-            }
+            for (int i = 0; i < LA; ++i) ra[i] = *(const bf16x8*)(ga[i] + k);
+#pragma unroll
+            for (int i = 0; i < LB; ++i) rb[i] = *(const bf16x8*)(gb[i] + k);
         }
+        bf16x8 fa[FM], fb[FN];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FM; ++i) fa[i] = *(const bf16x8*)&As[cur][(wm + 16 * i + r) * kLdsRow + kq];
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j) fb[j] = *(const bf16x8*)&Bs[cur][(wn + 16 * j + r) * kLdsRow + kq];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
-        if (k < K) {
+        if (more) {
+            // the other buffer was last read in the previous step, before the
+            // barrier that ended it
 #pragma unroll
-            for (int t = 0; t < 2; ++t) { fa[t] = na[t]; fb[t] = nb[t]; }
+            for (int i = 0; i < LA; ++i) *(bf16x8*)&As[cur ^ 1][la[i]] = ra[i];
+#pragma unroll
+            for (int i = 0; i < LB; ++i) *(bf16x8*)&Bs[cur ^ 1][lb[i]] = rb[i];
         }
+        __syncthreads();
+        cur ^= 1;
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int n = n0 + 16 * j + r;
+    for (int j = 0; j < FN; ++j) {
+        const int n = bn + wn + 16 * j + r;
         if (n >= N) continue;
         const float bv = kBias ? bias[n] : 0.f;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < FM; ++i) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int m = m0 + 16 * i + (lane >> 4) * 4 + e;
+                const int m = bm + wm + 16 * i + (lane >> 4) * 4 + e;
                 if (m >= M) continue;
                 float v = acc[i][j][e] + bv;
                 if (kRelu) v = fmaxf(v, 0.f);
@@ -98,23 +135,35 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const __bf16*
     }
 }
 
+template <int BM, int BN>
+static void launch_gemm_tile(int M, int N, int K, const __bf16* a, int lda, const __bf16* b,
+                             int ldb, const float* bias, bool relu, float* C32, __bf16* c16,
+                             int ldc, hipStream_t st) {
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM), block(256);
+    if (bias && relu)
+        hipLaunchKernelGGL((k_gemm<BM, BN, true, true>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+    else if (bias)
+        hipLaunchKernelGGL((k_gemm<BM, BN, true, false>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+    else if (relu)
+        hipLaunchKernelGGL((k_gemm<BM, BN, false, true>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+    else
+        hipLaunchKernelGGL((k_gemm<BM, BN, false, false>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+}
+
 hipError_t launch_gemm(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
                        const float* bias, bool relu, float* C32, void* C16, int ldc,
                        hipStream_t st) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (K <= 0 || K % 32 || lda % 8 || ldb % 8) return hipErrorInvalidValue;
-    dim3 grid((N + 63) / 64, (M + 63) / 64), block(256);
     auto a = (const __bf16*)A;
     auto b = (const __bf16*)B;
     auto c16 = (__bf16*)C16;
-    if (bias && relu)
-        hipLaunchKernelGGL((k_gemm<true, true>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
-    else if (bias)
-        hipLaunchKernelGGL((k_gemm<true, false>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
-    else if (relu)
-        hipLaunchKernelGGL((k_gemm<false, true>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+    // the large tile only when it still gives every compute unit a workgroup
+    const long long big = (long long)((N + 127) / 128) * ((M + 127) / 128);
+    if (big >= 256)
+        launch_gemm_tile<128, 128>(M, N, K, a, lda, b, ldb, bias, relu, C32, c16, ldc, st);
     else
-        hipLaunchKernelGGL((k_gemm<false, false>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+        launch_gemm_tile<64, 64>(M, N, K, a, lda, b, ldb, bias, relu, C32, c16, ldc, st);
     return hipGetLastError();
 }
 
@@ -208,26 +257,37 @@ hipError_t launch_relu_bwd(int n, const float* da, const void* act, void* dp, hi
     return hipGetLastError();
 }
 
-// db[n] = sum_m d[m][n] (BF16 or FP32 rows; one thread per column).
+// db[n] = sum_m d[m][n] (BF16 or FP32 rows).
 template <typename T>
-__global__ void k_colsum(int M, int N, const T* __restrict__ d, float* __restrict__ db) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+__global__ __launch_bounds__(256) void k_colsum(int M, int N, const T* __restrict__ d,
+                                                float* __restrict__ db) {
+    // 32 columns per workgroup, 8 row groups: thread (g, c) sums rows g, g+8, ...
+    // of column c, then the 8 partial sums are added in LDS (fixed order)
+    __shared__ float part[8][32];
+    const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int n = blockIdx.x * 32 + c;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += (float)d[(size_t)m * N + n];
-    db[n] = s;
+    if (n < N)
+        for (int m = g; m < M; m += 8) s += (float)d[(size_t)m * N + n];
+    part[g][c] = s;
+    __syncthreads();
+    if (g == 0 && n < N) {
+        float t = 0.f;
+        for (int q = 0; q < 8; ++q) t += part[q][c];
+        db[n] = t;
+    }
 }
 
 hipError_t launch_colsum_bf16(int M, int N, const void* d, float* db, hipStream_t st) {
     if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_colsum<__bf16>), dim3((N + 255) / 256), dim3(256), 0, st, M, N,
+    hipLaunchKernelGGL((k_colsum<__bf16>), dim3((N + 31) / 32), dim3(256), 0, st, M, N,
                        (const __bf16*)d, db);
     return hipGetLastError();
 }
 
 hipError_t launch_colsum_f32(int M, int N, const float* d, float* db, hipStream_t st) {
     if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_colsum<float>), dim3((N + 255) / 256), dim3(256), 0, st, M, N, d, db);
+    hipLaunchKernelGGL((k_colsum<float>), dim3((N + 31) / 32), dim3(256), 0, st, M, N, d, db);
     return hipGetLastError();
 }
 

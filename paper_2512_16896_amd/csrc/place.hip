@@ -130,7 +130,7 @@ __global__ __launch_bounds__(1024) void k_place(
     int j = min(max(n_placed[s], 0), nobj);
     int j_end = max_steps > 0 ? min(nobj, j + max_steps) : nobj;
     if (j_cap > 0) j_end = min(j_end, j_cap);
-    if (j >= j_end) {   // nothing to place in this launch (objects-per-scene cap)
+    if (j >= j_end && j < nobj) {   // the objects-per-scene cap stops this scene
         if (chosen && threadIdx.x == 0) chosen[s] = -1;
         return;
     }
@@ -227,6 +227,26 @@ __global__ __launch_bounds__(1024) void k_place(
         }
         rho = wave_max(rho) * (1.0f + 1e-6f) + 1e-6f;
         const float reach = rho + margin;
+        // Probe: the object's largest sphere (the lowest index among equals).
+        // A candidate whose probe already comes within the margin of a box or
+        // a grid collides, and the batch phase settles that for 64 candidates
+        // at once with the same arithmetic as the full test of that sphere.
+        float4 probe = make_float4(0.f, 0.f, 1e18f, 0.f);
+        if (S > 0) {
+            float rmax = -1.f;
+#pragma unroll
+            for (int q = 0; q < SPL; ++q)
+                if (act[q]) rmax = fmaxf(rmax, cr[q]);
+            rmax = wave_max(rmax);
+            int kp = 0;
+#pragma unroll
+            for (int q = SPL - 1; q >= 0; --q) {   // the lowest slot with a hit wins
+                const unsigned long long m = __ballot(act[q] && cr[q] == rmax);
+                if (m) kp = kWave * q + __builtin_ctzll(m);
+            }
+            probe = tmpl[sb + uniform_int(kp)];
+        }
+        const float prm2 = (probe.w + margin) * (probe.w + margin);
 
         const Support U = load_support(sup, obj_sup[o]);
         const float ax = U.hx - U.inset, ay = U.hy - U.inset, zc = U.lift + lift;
@@ -310,16 +330,32 @@ __global__ __launch_bounds__(1024) void k_place(
                                       ay, zc, &ga, &gi);
             float lx, ly, lz;   // world centre of this candidate's bounding sphere
             to_world(U, L, bc[0], bc[1], bc[2], lx, ly, lz);
+            float qx, qy, qz;   // world centre of its probe sphere
+            to_world(U, L, probe.x, probe.y, probe.z, qx, qy, qz);
+            bool sure = false;  // the probe collides: the candidate is rejected
             unsigned long long bmask = 0, gmask = 0, omask[kObjWords] = {};
             for (int bi = 0; bi < nbox_mask; ++bi) {
                 const float* B = box + 16 * (b0 + bi);
-                if (box_out2(B, lx, ly, lz) < reach * reach) bmask |= 1ull << bi;
+                const bool near = box_out2(B, lx, ly, lz) < reach * reach;
+                if (near) {
+                    bmask |= 1ull << bi;
+                    sure |= box_out2(B, qx, qy, qz) < prm2;
+                }
+                n_boxp += __popcll(__ballot(near && live));
             }
             // grids: only spheres whose centres lie inside a grid's node box
             // sample it (outside it reads +inf), so a bounding sphere that
             // misses the node box needs no sample
             if constexpr (kGrids) for (int gi = 0; gi < ngrid_mask; ++gi) {
-                if (grid_box_d2(grid + 24 * (g0 + gi), lx, ly, lz) <= rho * rho) gmask |= 1ull << gi;
+                const float* G = grid + 24 * (g0 + gi);
+                const bool near = grid_box_d2(G, lx, ly, lz) <= rho * rho;
+                if (near) {
+                    gmask |= 1ull << gi;
+                    if (!sure)
+                        sure = grid_sample(G, grid_val + grid_val_off[grid_src[g0 + gi]], qx, qy,
+                                           qz) < probe.w + margin;
+                }
+                n_grid += __popcll(__ballot(near && live));
             }
             for (int ob = 0; ob < nob_mask; ++ob) {
                 const float4 bd = lbnd[ob];
@@ -327,10 +363,12 @@ __global__ __launch_bounds__(1024) void k_place(
                 const float lim = reach + bd.w;
                 if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) omask[ob >> 6] |= 1ull << (ob & 63);
             }
+            const unsigned long long sure_mask = __ballot(sure && live);
             {
                 const unsigned long long nlive = __popcll(__ballot(live));
                 n_boxc += nlive * (unsigned long long)(nbox_mask + ngrid_mask);
                 n_objc += nlive * (unsigned long long)nob_mask;
+                n_xf += nlive;   // probe transforms
             }
             // ---- candidate phase ----
             for (int t = 0; t < kWave; ++t) {
@@ -340,6 +378,10 @@ __global__ __launch_bounds__(1024) void k_place(
                                                   __HIP_MEMORY_SCOPE_WORKGROUP)) < gt) {
                     stop = true;
                     break;
+                }
+                if ((sure_mask >> t) & 1ull) {   // rejected by its probe
+                    ++n_cand;
+                    continue;
                 }
                 Pose P;
                 P.x = bcast(L.x, t); P.y = bcast(L.y, t); P.z = zc;
@@ -456,7 +498,10 @@ __global__ __launch_bounds__(1024) void k_place(
         const int8_t st = fin != SCN_SCENE_ACTIVE ? fin
                                                   : (j == nobj ? SCN_SCENE_VALID : SCN_SCENE_ACTIVE);
         status[s] = st;
-        if (n_active && st == SCN_SCENE_ACTIVE && (j_cap <= 0 || j < j_cap)) atomicAdd(n_active, 1);
+        if (n_active && st == SCN_SCENE_ACTIVE && (j_cap <= 0 || j < j_cap)) {
+            atomicAdd(n_active, 1);                   // scenes with work left
+            if (pend == 0) atomicAdd(n_active + 1, 1);  // of them, starting a new object
+        }
         if (chosen) chosen[s] = last;
         if (st == SCN_SCENE_VALID) atomicAdd(counters + kValidScenes, 1ull);
         if (st == SCN_SCENE_INVALID) atomicAdd(counters + kInvalidScenes, 1ull);

@@ -64,6 +64,19 @@ def test_mlp_forward_matches_oracle(dev):
     np.testing.assert_allclose(z2, z[:37], rtol=0, atol=1e-6 * np.max(np.abs(z)))
 
 
+def test_mlp_forward_large_batch_matches_oracle(dev):
+    """1000 rows: the 512 -> 4096 layer runs on the 128 x 128 workgroup tile
+    (the hidden layers on 64 x 64), with a ragged last row tile."""
+    scn, ctx, torch = dev
+    W, b = _weights(11)
+    net = _net(scn, torch, W, b)
+    x = _features(12, 1000)
+    z = scn.mlp_forward(ctx, net, torch.tensor(x, dtype=torch.bfloat16, device="cuda")).cpu().numpy()
+    ref, _ = ol.forward(x, W, b)
+    assert _rel(z, ref) < 2 ** -7
+    assert np.max(np.abs(z - ref)) < 2 ** -6 * np.max(np.abs(ref))
+
+
 def test_mlp_backward_matches_oracle(dev):
     scn, ctx, torch = dev
     W, b = _weights(3)
