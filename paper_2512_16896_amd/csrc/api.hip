@@ -127,6 +127,7 @@ int scn_ctx_destroy(scn_ctx* c) {
     if (c->d_hist) (void)hipFree(c->d_hist);
     if (c->ws) (void)hipFree(c->ws);
     if (c->h_flag) (void)hipHostFree(c->h_flag);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return SCN_OK;
 }

@@ -143,29 +143,79 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     SCN_HIP(scn::launch_fill_i32(resume, n, 0, st));
     SCN_HIP(scn::launch_descriptor(*b, desc, st));
     SCN_HIP(scn::launch_hmap_boxes(*b, hmap, st));
+
+    // One step launch on stream s: for scenes that start a new object, the
+    // features, the network and the top-k (skipped when no scene does:
+    // resumed scenes need no proposal); then the place kernel, the height map
+    // update of the scenes that placed, and the read-back of the two counters.
+    auto enqueue_step = [&](hipStream_t s, bool with_net) -> int {
+        if (with_net) {
+            SCN_HIP(scn::launch_next_object(*b, resume, j_cap, obj_idx, s));
+            SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, s));
+            if (int r = scn_mlp_forward(c, net, x, n, logits, (scn_stream)s)) return r;
+            SCN_HIP(scn::launch_topk(n, logits, top_k, obj_idx, bins, s));
+        }
+        SCN_HIP(scn::launch_copy_i32(b->n_placed, before, n, s));
+        SCN_HIP(scn::launch_fill_i32(n_active, 2, 0, s));
+        if (int r = scn_place_internal(c, b, a, 1, nullptr, false, bins, top_k, resume, chunk,
+                                       j_cap, n_active, s))
+            return r;
+        SCN_HIP(scn::launch_last_object(*b, before, placed_now, s));
+        SCN_HIP(scn::launch_hmap_raise(*b, placed_now, nullptr, hmap, s));
+        SCN_HIP(hipMemcpyAsync(c->h_flag, n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        return SCN_OK;
+    };
+
+    // With use_graph the two step variants are captured once (on the
+    // context's own stream, after the first step ran eagerly and made every
+    // allocation) and replayed on `stream`: every step has the same kernel
+    // arguments, since the state lives in device memory.
+    hipGraphExec_t exec[2] = {nullptr, nullptr};   // [with network, resume only]
+    auto release = [&]() {
+        for (auto& e : exec)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+    };
+    auto capture = [&](bool with_net, hipGraphExec_t* out) -> int {
+        if (!c->cap_stream)
+            SCN_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        SCN_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        const int r = enqueue_step(c->cap_stream, with_net);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (r != SCN_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return r != SCN_OK ? r : scn_fail(SCN_E_HIP, "step capture: %s", hipGetErrorString(e));
+        }
+        const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return scn_fail(SCN_E_HIP, "step graph: %s", hipGetErrorString(ei));
+        return SCN_OK;
+    };
+
     bool fresh = true;   // some scene starts a new object (needs the network)
     for (long long it = 0; it < max_launch; ++it) {
-        // scenes that start a new object get a proposal; pending ones resume
-        // their fallback and need none (a launch with only those skips the
-        // network)
-        if (fresh) {
-            SCN_HIP(scn::launch_next_object(*b, resume, j_cap, obj_idx, st));
-            SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, st));
-            if (int r = scn_mlp_forward(c, net, x, n, logits, stream)) return r;
-            SCN_HIP(scn::launch_topk(n, logits, top_k, obj_idx, bins, st));
+        int r = SCN_OK;
+        if (a->use_graph && it > 0) {
+            hipGraphExec_t& e = exec[fresh ? 0 : 1];
+            if (!e) r = capture(fresh, &e);
+            if (r == SCN_OK && hipGraphLaunch(e, st) != hipSuccess)
+                r = scn_fail(SCN_E_HIP, "step graph launch failed");
+        } else {
+            r = enqueue_step(st, fresh);
         }
-        SCN_HIP(scn::launch_copy_i32(b->n_placed, before, n, st));
-        SCN_HIP(scn::launch_fill_i32(n_active, 2, 0, st));
-        if (int r = scn_place_internal(c, b, a, 1, nullptr, false, bins, top_k, resume, chunk,
-                                       j_cap, n_active, st))
+        if (r == SCN_OK && hipStreamSynchronize(st) != hipSuccess)
+            r = scn_fail(SCN_E_HIP, "step failed: %s", hipGetErrorString(hipGetLastError()));
+        if (r != SCN_OK) {
+            release();
             return r;
-        SCN_HIP(scn::launch_last_object(*b, before, placed_now, st));
-        SCN_HIP(scn::launch_hmap_raise(*b, placed_now, nullptr, hmap, st));
-        SCN_HIP(hipMemcpyAsync(c->h_flag, n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        SCN_HIP(hipStreamSynchronize(st));
+        }
         if (c->h_flag[0] == 0) break;
         fresh = c->h_flag[1] > 0;
     }
+    release();
     return SCN_OK;
 }
 
