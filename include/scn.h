@@ -98,11 +98,23 @@ typedef struct {
  * reported as SCN_E_CAPACITY and left untouched):
  *   max_objects_per_scene, max_spheres_per_object, max_spheres_per_scene,
  *   max_boxes_per_scene, max_grids_per_scene, max_cand_per_object
+ * Declared geometry class (`geometry`):
+ *   SCN_GEOM_GENERAL  any rotations.
+ *   SCN_GEOM_YAW      every support rotation is a turn about z, exactly
+ *                     [[a, -b, 0], [b, a, 0], [0, 0, 1]], and every box rotation
+ *                     keeps the z axis (R[2] = R[5] = R[6] = R[7] = 0, R[8] = 1).
+ *                     The place kernel then composes transforms in the plane.
+ *                     A scene that breaks the declaration is not placed: it is
+ *                     marked SCN_SCENE_INVALID and bit 1 of the counters' error
+ *                     word is set.  Grids may have any rotation either way.
  */
+#define SCN_GEOM_GENERAL 0
+#define SCN_GEOM_YAW 1
 typedef struct scn_batch {
     int32_t n_scenes, n_objects, n_spheres, n_supports, n_boxes, n_grids, n_grid_assets;
     int32_t max_objects_per_scene, max_spheres_per_object, max_spheres_per_scene;
     int32_t max_boxes_per_scene, max_grids_per_scene, max_cand_per_object;
+    int32_t geometry;      /* SCN_GEOM_GENERAL or SCN_GEOM_YAW (see above)      */
     const int32_t *obj_off;
     const int32_t *sph_off;
     const float *tmpl;
@@ -151,7 +163,8 @@ typedef struct {
     int64_t grid_samples;  /* sphere-grid trilinear samples evaluated             */
     int64_t attempts;      /* (scene, object, attempt) triples started            */
     int64_t placed;        /* objects placed                                       */
-    int64_t error_word;    /* device-detected errors (bit 0: capacity)           */
+    int64_t error_word;    /* device-detected errors (bit 0: capacity, bit 1:
+                            * a scene breaks the declared SCN_GEOM_YAW geometry) */
     int64_t transforms;    /* candidate spheres moved to the world frame          */
     int64_t box_culls;     /* bounding-sphere vs box pretests                      */
     int64_t object_culls;  /* bounding-sphere vs placed-object pretests            */
@@ -174,7 +187,9 @@ const char *scn_last_error(void);
 /* Zero the device counters (asynchronous, graph-safe fill kernel).          */
 int scn_reset_counters(scn_ctx *ctx, scn_stream stream);
 /* Synchronize `stream` and copy the counters to *out (host).  Returns
- * SCN_E_CAPACITY if the device error word is set.                          */
+ * SCN_E_CAPACITY if bit 0 of the device error word is set, SCN_E_INVALID_ARG
+ * if bit 1 is (a scene broke the declared SCN_GEOM_YAW geometry); *out is
+ * filled either way.                                                        */
 int scn_read_counters(scn_ctx *ctx, scn_counters *out, scn_stream stream);
 
 /* ---- the hot path ------------------------------------------------------ */

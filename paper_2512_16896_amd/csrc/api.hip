@@ -160,6 +160,9 @@ int scn_read_counters(scn_ctx* c, scn_counters* out, scn_stream stream) {
     out->sphere_culls = h[scn::kSphCulls];
     if (out->error_word & scn::kErrCapacity)
         return fail(SCN_E_CAPACITY, "a scene exceeded the planned capacity and was skipped");
+    if (out->error_word & scn::kErrGeometry)
+        return fail(SCN_E_INVALID_ARG,
+                    "a scene breaks the batch's declared SCN_GEOM_YAW geometry and was marked invalid");
     return SCN_OK;
 }
 

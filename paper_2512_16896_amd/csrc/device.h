@@ -80,6 +80,29 @@ __device__ __forceinline__ void to_world(const Support& S, const Pose& P, float 
     wz = fmaf(S.R[6], lx, fmaf(S.R[7], ly, fmaf(S.R[8], lz, S.t[2])));
 }
 
+// Supports that turn about z only, R = [[a, -b, 0], [b, a, 0], [0, 0, 1]]
+// (the exact pattern z-rotations have in FP32), compose with the candidate's
+// yaw into one planar rotation: world = [[C, -S], [S, C]] (cx, cy) + (Tx, Ty),
+// and world z = (cz + z) + t_z does not depend on the candidate at all.
+__device__ __forceinline__ bool yaw_support(const Support& U) {
+    return U.R[2] == 0.f && U.R[5] == 0.f && U.R[6] == 0.f && U.R[7] == 0.f && U.R[8] == 1.f &&
+           U.R[0] == U.R[4] && U.R[1] == -U.R[3];
+}
+struct Planar { float C, S, Tx, Ty; };
+__device__ __forceinline__ Planar planar(const Support& U, const Pose& P) {
+    const float a = U.R[0], b = U.R[3];
+    Planar m;
+    m.C = fmaf(a, P.c, -b * P.s);
+    m.S = fmaf(b, P.c, a * P.s);
+    m.Tx = fmaf(a, P.x, fmaf(-b, P.y, U.t[0]));
+    m.Ty = fmaf(b, P.x, fmaf(a, P.y, U.t[1]));
+    return m;
+}
+__device__ __forceinline__ void planar_xy(const Planar& m, float cx, float cy, float& wx, float& wy) {
+    wx = fmaf(m.C, cx, fmaf(-m.S, cy, m.Tx));
+    wy = fmaf(m.S, cx, fmaf(m.C, cy, m.Ty));
+}
+
 // Box row (16 floats): R[9] box->world, centre[3], half extents[3].
 // Box-local excess e = |R^T (p - c)| - h.
 __device__ __forceinline__ void box_excess(const float* B, float px, float py, float pz,
@@ -119,6 +142,25 @@ __device__ __forceinline__ float box_out2(const float* B, float px, float py, fl
     box_excess(B, px, py, pz, ex, ey, ez);
     const float ox = fmaxf(ex, 0.f), oy = fmaxf(ey, 0.f), oz = fmaxf(ez, 0.f);
     return fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+}
+
+// Boxes whose rotation keeps the z axis (R[2] = R[5] = R[6] = R[7] = 0,
+// R[8] = 1): the same value as box_out2, bit for bit, with the zero terms left
+// out (an FMA with a zero product adds exactly the other term).
+__device__ __forceinline__ bool yaw_box(const float* B) {
+    return B[2] == 0.f && B[5] == 0.f && B[6] == 0.f && B[7] == 0.f && B[8] == 1.f;
+}
+__device__ __forceinline__ float box_out2_yaw(const float* B, float px, float py, float pz) {
+    const float dx = px - B[9], dy = py - B[10], dz = pz - B[11];
+    const float ox = fmaxf(fabsf(fmaf(B[0], dx, B[3] * dy)) - B[12], 0.f);
+    const float oy = fmaxf(fabsf(fmaf(B[1], dx, B[4] * dy)) - B[13], 0.f);
+    const float oz = fmaxf(fabsf(dz) - B[14], 0.f);
+    return fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+}
+template <bool kYaw>
+__device__ __forceinline__ float box_out2_t(const float* B, float px, float py, float pz) {
+    if constexpr (kYaw) return box_out2_yaw(B, px, py, pz);
+    else return box_out2(B, px, py, pz);
 }
 
 // Grid instance row (24 floats): W[9] world->grid, tw[3], origin[3], h, nx, ny, nz, pad.

@@ -48,7 +48,7 @@ enum CounterSlot {
     kPlaced = 5, kErrorWord = 6, kTransforms = 7, kBoxCulls = 8, kObjCulls = 9,
     kValidScenes = 10, kInvalidScenes = 11, kSphCulls = 12, kNumCounters = 16
 };
-enum ErrorBits { kErrCapacity = 1 };
+enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2 };
 
 // Where the fused place kernel keeps a scene's placed spheres.
 enum PlaceMode {

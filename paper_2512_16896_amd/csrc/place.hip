@@ -77,7 +77,11 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 //               most split_sph spheres are left to the LDS launch.
 // kGrids: the batch has voxel-grid furniture (the grid code is compiled out
 // otherwise, which keeps the register count of grid-free launches low).
-template <int SPL, bool kLds, bool kGrids>
+// kYaw: the batch declares SCN_GEOM_YAW (supports and boxes turn about z
+// only); candidate transforms and box tests take their planar form (4 instead
+// of 14 instructions per sphere transform, 5 fewer per box test). A scene
+// that breaks the declaration is marked invalid with kErrGeometry.
+template <int SPL, bool kLds, bool kGrids, bool kYaw>
 __global__ __launch_bounds__(1024) void k_place(
     const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
     const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
@@ -185,6 +189,11 @@ __global__ __launch_bounds__(1024) void k_place(
     int last = -2;
     const int b0 = box_off[s], b1 = box_off[s + 1];
     const int nbox_mask = min(b1 - b0, kWave);   // boxes covered by the batch masks
+    // the scene's boxes all turn about z only (then, with a support that does
+    // too, the entry loop runs its planar form)
+    int tilted = 0;
+    for (int bi = b0 + (int)threadIdx.x; bi < b1; bi += blockDim.x) tilted |= !yaw_box(box + 16 * bi);
+    const bool boxes_yaw = !__syncthreads_or(tilted);
     const int g0 = grid_off ? grid_off[s] : 0;
     const int ngrid_mask = kGrids ? min(grid_off[s + 1] - g0, kWave) : 0;   // grids (<= 64)
 
@@ -250,6 +259,19 @@ __global__ __launch_bounds__(1024) void k_place(
 
         const Support U = load_support(sup, obj_sup[o]);
         const float ax = U.hx - U.inset, ay = U.hy - U.inset, zc = U.lift + lift;
+        // planar form: supports and boxes turn about z only; world z of each
+        // sphere, of the bounding centre and of the probe is then the same
+        // for every candidate
+        if (kYaw && !(boxes_yaw && yaw_support(U))) {   // breaks the declared geometry
+            if (threadIdx.x == 0) atomicOr(counters + kErrorWord, (unsigned long long)kErrGeometry);
+            fin = SCN_SCENE_INVALID;
+            last = -1;
+            break;
+        }
+        float wz0[SPL];
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) wz0[q] = (cz[q] + zc) + U.t[2];
+        const float bz0 = (bc[2] + zc) + U.t[2], pz0 = (probe.z + zc) + U.t[2];
         const int C = obj_ncand ? obj_ncand[o] : default_ncand;
         // proposals of this scene (only when it has them this step)
         const int pk = prop_bins ? prop_k : 0;
@@ -329,17 +351,26 @@ __global__ __launch_bounds__(1024) void k_place(
             const Pose L = entry_pose(live ? g : 0, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
                                       ay, zc, &ga, &gi);
             float lx, ly, lz;   // world centre of this candidate's bounding sphere
-            to_world(U, L, bc[0], bc[1], bc[2], lx, ly, lz);
             float qx, qy, qz;   // world centre of its probe sphere
-            to_world(U, L, probe.x, probe.y, probe.z, qx, qy, qz);
+            Planar M{};         // the candidate's planar motion (kYaw)
+            if constexpr (kYaw) {
+                M = planar(U, L);
+                planar_xy(M, bc[0], bc[1], lx, ly);
+                planar_xy(M, probe.x, probe.y, qx, qy);
+                lz = bz0;
+                qz = pz0;
+            } else {
+                to_world(U, L, bc[0], bc[1], bc[2], lx, ly, lz);
+                to_world(U, L, probe.x, probe.y, probe.z, qx, qy, qz);
+            }
             bool sure = false;  // the probe collides: the candidate is rejected
             unsigned long long bmask = 0, gmask = 0, omask[kObjWords] = {};
             for (int bi = 0; bi < nbox_mask; ++bi) {
                 const float* B = box + 16 * (b0 + bi);
-                const bool near = box_out2(B, lx, ly, lz) < reach * reach;
+                const bool near = box_out2_t<kYaw>(B, lx, ly, lz) < reach * reach;
                 if (near) {
                     bmask |= 1ull << bi;
-                    sure |= box_out2(B, qx, qy, qz) < prm2;
+                    sure |= box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
                 }
                 n_boxp += __popcll(__ballot(near && live));
             }
@@ -383,16 +414,29 @@ __global__ __launch_bounds__(1024) void k_place(
                     ++n_cand;
                     continue;
                 }
-                Pose P;
-                P.x = bcast(L.x, t); P.y = bcast(L.y, t); P.z = zc;
-                P.c = bcast(L.c, t); P.s = bcast(L.s, t);
+                Pose P{};
+                Planar Mt{};
+                if constexpr (kYaw) {
+                    Mt.C = bcast(M.C, t); Mt.S = bcast(M.S, t);
+                    Mt.Tx = bcast(M.Tx, t); Mt.Ty = bcast(M.Ty, t);
+                } else {
+                    P.x = bcast(L.x, t); P.y = bcast(L.y, t); P.z = zc;
+                    P.c = bcast(L.c, t); P.s = bcast(L.s, t);
+                }
                 Gx = bcast(lx, t); Gy = bcast(ly, t); Gz = bcast(lz, t);
                 unsigned long long bm = bcast64(bmask, t), gm = bcast64(gmask, t);
                 ++n_cand;
                 n_xf += S;
 #pragma unroll
-                for (int q = 0; q < SPL; ++q)
-                    if (q == 0 || q < nq) to_world(U, P, cx[q], cy[q], cz[q], wx[q], wy[q], wz[q]);
+                for (int q = 0; q < SPL; ++q) {
+                    if (q > 0 && q >= nq) break;
+                    if constexpr (kYaw) {
+                        planar_xy(Mt, cx[q], cy[q], wx[q], wy[q]);
+                        wz[q] = wz0[q];
+                    } else {
+                        to_world(U, P, cx[q], cy[q], cz[q], wx[q], wy[q], wz[q]);
+                    }
+                }
                 bool hit = false;
                 // boxes of the mask, then any boxes beyond the first 64
                 while (bm) {
@@ -401,17 +445,17 @@ __global__ __launch_bounds__(1024) void k_place(
                     const float* B = box + 16 * (b0 + bi);
 #pragma unroll
                     for (int q = 0; q < SPL; ++q)
-                        if (q == 0 || q < nq) hit |= box_out2(B, wx[q], wy[q], wz[q]) < rm2[q];
+                        if (q == 0 || q < nq) hit |= box_out2_t<kYaw>(B, wx[q], wy[q], wz[q]) < rm2[q];
                     n_boxp += S;
                     if (__ballot(hit)) break;
                 }
                 for (int bx = b0 + kWave; bx < b1 && !__ballot(hit); ++bx) {
                     const float* B = box + 16 * bx;
                     n_boxc += 1;
-                    if (!(box_out2(B, Gx, Gy, Gz) < reach * reach)) continue;
+                    if (!(box_out2_t<kYaw>(B, Gx, Gy, Gz) < reach * reach)) continue;
 #pragma unroll
                     for (int q = 0; q < SPL; ++q)
-                        if (q == 0 || q < nq) hit |= box_out2(B, wx[q], wy[q], wz[q]) < rm2[q];
+                        if (q == 0 || q < nq) hit |= box_out2_t<kYaw>(B, wx[q], wy[q], wz[q]) < rm2[q];
                     n_boxp += S;
                 }
                 // voxel grids of the mask: trilinear field minus radius vs margin
@@ -471,11 +515,17 @@ __global__ __launch_bounds__(1024) void k_place(
                                    &fa, &fi);
         if (wave == 0) {
             const Pose P = Pw;
+            const Planar Mc = planar(U, P);   // the planar form
 #pragma unroll
             for (int q = 0; q < SPL; ++q) {
                 if (act[q]) {
                     float px, py, pz;
-                    to_world(U, P, cx[q], cy[q], cz[q], px, py, pz);
+                    if constexpr (kYaw) {   // the arithmetic the candidate was tested with
+                        planar_xy(Mc, cx[q], cy[q], px, py);
+                        pz = wz0[q];
+                    } else {
+                        to_world(U, P, cx[q], cy[q], cz[q], px, py, pz);
+                    }
                     const int k = lane + kWave * q;
                     placed[sb + k] = make_float4(px, py, pz, cr[q]);
                     if constexpr (kLds) lsph[sb - first + k] = make_float4(px, py, pz, cr[q] + margin);
@@ -483,7 +533,12 @@ __global__ __launch_bounds__(1024) void k_place(
             }
             if (lane == 0) {
                 float gx, gy, gz;
-                to_world(U, P, bc[0], bc[1], bc[2], gx, gy, gz);
+                if constexpr (kYaw) {
+                    planar_xy(Mc, bc[0], bc[1], gx, gy);
+                    gz = bz0;
+                } else {
+                    to_world(U, P, bc[0], bc[1], bc[2], gx, gy, gz);
+                }
                 lbnd[j] = make_float4(gx, gy, gz, rho);
                 rec[o] = scn_pose_rec{P.x, P.y, P.z, P.yaw, fa, fi};
             }
@@ -524,7 +579,9 @@ template <int SPL, bool kLds>
 static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                    const PlacePlan& plan, int cap_sph, int split, int32_t* chosen,
                                    unsigned long long* ctr, hipStream_t st) {
-    auto kern = b.grid_off ? k_place<SPL, kLds, true> : k_place<SPL, kLds, false>;
+    const bool yaw = b.geometry == SCN_GEOM_YAW;
+    auto kern = b.grid_off ? (yaw ? k_place<SPL, kLds, true, true> : k_place<SPL, kLds, true, false>)
+                           : (yaw ? k_place<SPL, kLds, false, true> : k_place<SPL, kLds, false, false>);
     const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj);
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,

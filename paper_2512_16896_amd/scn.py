@@ -37,7 +37,7 @@ class _Batch(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "n_scenes", "n_objects", "n_spheres", "n_supports", "n_boxes", "n_grids", "n_grid_assets",
         "max_objects_per_scene", "max_spheres_per_object", "max_spheres_per_scene",
-        "max_boxes_per_scene", "max_grids_per_scene", "max_cand_per_object")] + \
+        "max_boxes_per_scene", "max_grids_per_scene", "max_cand_per_object", "geometry")] + \
         [(n, C.c_void_p) for n in (
             "obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
             "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
@@ -217,6 +217,22 @@ class GenArgs:
         return a
 
 
+GEOM_GENERAL, GEOM_YAW = 0, 1
+
+
+def geometry_is_yaw(b) -> bool:
+    """Whether every support rotation of the (host) batch is a turn about z,
+    [[a, -b, 0], [b, a, 0], [0, 0, 1]] exactly in FP32, and every box rotation
+    keeps the z axis: the class the library's SCN_GEOM_YAW declares."""
+    sup = np.asarray(b.sup, np.float32).reshape(-1, 16)
+    box = np.asarray(b.box, np.float32).reshape(-1, 16) if b.n_boxes else np.zeros((0, 16), np.float32)
+    zero = lambda a, cols: bool(np.all(a[:, cols] == 0))
+    sup_ok = (zero(sup, [2, 5, 6, 7]) and bool(np.all(sup[:, 8] == 1)) and
+              bool(np.all(sup[:, 0] == sup[:, 4])) and bool(np.all(sup[:, 1] == -sup[:, 3])))
+    box_ok = zero(box, [2, 5, 6, 7]) and bool(np.all(box[:, 8] == 1))
+    return sup_ok and box_ok
+
+
 class DeviceBatch:
     """Device copies of a SceneBatch plus the mutable placement state."""
 
@@ -263,6 +279,7 @@ class DeviceBatch:
         c.max_boxes_per_scene = int(b.boxes_per_scene().max()) if n else 0
         c.max_grids_per_scene = int(np.diff(b.grid_off).max()) if b.grid_off is not None and n else 0
         c.max_cand_per_object = int(b.obj_ncand.max()) if n_obj else 0
+        c.geometry = GEOM_YAW if geometry_is_yaw(b) else GEOM_GENERAL
         for name in ("obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
                      "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
                      "placed", "n_placed", "status", "rec"):

@@ -86,3 +86,26 @@ def audit_placements(b, placed, n_placed, margin=MARGIN, tol=CLR_TOL):
                 worst = min(worst, float(np.min(d - sp[:, None, 3] - prev[None, :, 3])))
     assert worst >= margin - tol, worst
     return worst
+
+
+def rot_xy(ax: float, ay: float) -> np.ndarray:
+    """Rotation about x by ax, then about y by ay (a tilt: not a turn about z)."""
+    cx, sx, cy, sy = np.cos(ax), np.sin(ax), np.cos(ay), np.sin(ay)
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    return Ry @ Rx
+
+
+def tilted(b, Q):
+    """The same scenes moved by the world rotation Q: supports and boxes turn
+    with the world, so every candidate's clearance is unchanged (up to
+    rounding) while no rotation is a turn about z any more."""
+    import dataclasses
+    sup = np.array(b.sup, np.float64).reshape(-1, 16)
+    sup[:, :9] = (Q @ sup[:, :9].reshape(-1, 3, 3)).reshape(-1, 9)
+    sup[:, 9:12] = sup[:, 9:12] @ Q.T
+    box = np.array(b.box, np.float64).reshape(-1, 16)
+    box[:, :9] = (Q @ box[:, :9].reshape(-1, 3, 3)).reshape(-1, 9)
+    box[:, 9:12] = box[:, 9:12] @ Q.T
+    return dataclasses.replace(b, sup=sup.astype(np.float32),
+                               box=box.astype(np.float32).reshape(np.shape(b.box)))

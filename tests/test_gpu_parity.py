@@ -2,7 +2,8 @@
 import numpy as np
 import pytest
 
-from gpu_util import BAND, CLR_TOL, MARGIN, audit_placements, compare_generation, objects_of
+from gpu_util import (BAND, CLR_TOL, MARGIN, audit_placements, compare_generation, first_banded,
+                      objects_of, rot_xy, tilted)
 from paper_2512_16896_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu
@@ -273,3 +274,53 @@ def test_repeated_runs_are_deterministic(dev):
     for o in outs[1:]:
         for u, v in zip(outs[0], o):
             assert np.array_equal(u, v, equal_nan=True)
+
+
+def test_general_rotations_match_oracle_and_planar_form(dev, orc):
+    """Scenes tilted by a world rotation take the general kernel form; they
+    match the oracle, and their records equal the planar form's on the
+    untilted scenes wherever neither oracle run has a banded decision."""
+    scn, ctx, torch = dev
+    b = sg.batched_scenes(32, seed=21)
+    bt = tilted(b, rot_xy(0.35, -0.2))
+    assert scn.geometry_is_yaw(b) and not scn.geometry_is_yaw(bt)
+    ref_t = orc.generate(bt, seed=77)
+    dt = scn.DeviceBatch(bt)
+    assert dt.c.geometry == scn.GEOM_GENERAL
+    scn.generate_scenes(ctx, dt, scn.GenArgs(seed=77))
+    st_t, npl_t, rec_t, recf_t, placed_t = _device_results(dt)
+    n_cmp, _ = compare_generation(bt, ref_t, st_t, rec_t, recf_t)
+    assert n_cmp > 0.8 * bt.n_objects
+    audit_placements(bt, placed_t, npl_t)
+    ref = orc.generate(b, seed=77)
+    dy = scn.DeviceBatch(b)
+    assert dy.c.geometry == scn.GEOM_YAW
+    scn.generate_scenes(ctx, dy, scn.GenArgs(seed=77))
+    st, npl, rec, _, _ = _device_results(dy)
+    same = 0
+    for s in range(b.n_scenes):
+        nobj = b.obj_off[s + 1] - b.obj_off[s]
+        if first_banded(ref, b, s) < nobj or first_banded(ref_t, bt, s) < nobj:
+            continue
+        o0 = b.obj_off[s]
+        assert st[s] == st_t[s] and npl[s] == npl_t[s], s
+        np.testing.assert_array_equal(rec[o0:o0 + nobj], rec_t[o0:o0 + nobj])
+        same += 1
+    assert same > 0.8 * b.n_scenes
+
+
+def test_false_yaw_declaration_marks_scenes_invalid(dev):
+    """A batch that declares SCN_GEOM_YAW but holds tilted supports is not
+    placed: its scenes are marked invalid and the error word says why."""
+    scn, ctx, torch = dev
+    bt = tilted(sg.batched_scenes(8, seed=3), rot_xy(0.3, 0.0))
+    db = scn.DeviceBatch(bt)
+    db.c.geometry = scn.GEOM_YAW
+    ctx.reset_counters()
+    scn.generate_scenes(ctx, db, scn.GenArgs(seed=1))
+    status, npl, _, _, _ = _device_results(db)
+    with pytest.raises(scn.ScnError) as e:
+        ctx.read_counters()
+    assert e.value.code == -1 and "SCN_GEOM_YAW" in str(e.value)
+    ctx.reset_counters()
+    assert np.all(status == 2) and np.all(npl == 0)
