@@ -202,7 +202,7 @@ def main():
     ap.add_argument("--workload", default="batched-4096", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--schedule", type=lambda v: int(v, 0), default=0)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and timing the learned-proposal form")
     args = ap.parse_args()

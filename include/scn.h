@@ -241,7 +241,7 @@ int scn_generate_scenes(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
 /* Schedule ids for scn_gen_args.schedule (0 = the context's tuned choice for
  * this batch shape, or the default):
  *   bits 0-4  waves per workgroup: candidates of one scene in flight
- *             (1, 2, 4, 8 or 16)
+ *             (1..16)
  *   bit  5    longest-first scene order (larger scenes start first)
  *   bits 8-11 LDS budget for a scene's placed spheres: 0 = sized for the
  *             largest scene (every scene LDS-resident); 1..5 = 32, 48, 64,

@@ -242,8 +242,7 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
     if (sched & ~(SCN_SCHED_WAVES_MASK | SCN_SCHED_LONGEST_FIRST | SCN_SCHED_LDS_MASK))
         return fail(SCN_E_INVALID_ARG, "unknown schedule bits 0x%x", sched);
     const int w = sched & SCN_SCHED_WAVES_MASK;
-    if (w != 1 && w != 2 && w != 4 && w != 8 && w != 16)
-        return fail(SCN_E_INVALID_ARG, "schedule waves must be 1, 2, 4, 8 or 16");
+    if (w < 1 || w > 16) return fail(SCN_E_INVALID_ARG, "schedule waves must be 1..16");
     plan->waves = w;
     plan->order = nullptr;
     if (sched & SCN_SCHED_LONGEST_FIRST) {
@@ -263,7 +262,7 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
     plan->max_steps = max_steps;
     // dynamic LDS available to the place kernel: the block limit minus the
     // kernel's own static shared variables
-    const long long lds_cap = c->lds_per_block - 1024;
+    const long long lds_cap = c->lds_per_block - 1024 - (b->grid_off ? 0 : scn::kMapBytes);
     if (16LL * plan->cap_obj + 16LL * 64 > lds_cap)
         return fail(SCN_E_UNSUPPORTED, "%d objects per scene do not fit the LDS", plan->cap_obj);
     static const int kBudgetKB[] = {0, 32, 48, 64, 80, 96};

@@ -50,6 +50,10 @@ enum CounterSlot {
 };
 enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2 };
 
+// Bytes of dynamic LDS the place kernel adds for a scene's depth map (batches
+// without grids).
+constexpr int kMapBytes = 24576;
+
 // Where the fused place kernel keeps a scene's placed spheres.
 enum PlaceMode {
     kPlaceAllLds = 0,     // every scene in LDS (LDS sized for the largest scene)

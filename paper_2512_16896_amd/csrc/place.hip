@@ -69,6 +69,105 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// ---------------------------------------------------------------------------
+// Depth map of a scene's placed spheres, in the frame of its (single) support:
+// one int8 per voxel, a lower bound of how deep the voxel centre lies inside
+// the placed spheres, max over spheres of r - |v - c| in steps of kMapQ, kept
+// where it is >= -kMapReach (kMapNone elsewhere).  A probe sphere of radius rp
+// centred at p in voxel v hits a placed sphere within the margin when
+// depth(v) > |p - v| - rp - margin (kMapSafety more is asked): for the sphere
+// that gives the depth, |p - c| <= |p - v| + |v - c| < rp + r + margin.
+// Writes race without atomics: every value written is one sphere's depth, a
+// valid lower bound, so a lost update only loses a rejection.
+constexpr float kMapQ = 5e-4f;         // depth step (m)
+constexpr float kMapReach = 0.02f;     // depths kept down to -2 cm
+constexpr float kMapSafety = 1e-4f;    // a rejection keeps this far inside the margin
+constexpr int kMapNone = -128;
+constexpr float kMapOver = 0.3f;       // mapped overhang beyond the support rectangle (m)
+constexpr float kMapTop = 0.5f;        // mapped height above the support plane (m)
+
+struct DepthMap {
+    float x0, y0, h, inv_h;
+    int nx, ny, nz;
+};
+
+// Voxel size: the smallest h >= 3 cm (in 5 % steps) whose grid over the
+// rectangle grown by kMapOver and kMapTop of height fits kMapBytes.
+__device__ __forceinline__ bool map_geometry(float ax, float ay, DepthMap& m) {
+    const float ex = 2.f * (ax + kMapOver), ey = 2.f * (ay + kMapOver);
+    if (!(ex > 0.f && ey > 0.f && ex < 1e4f && ey < 1e4f)) return false;
+    float h = fmaxf(cbrtf(ex * ey * kMapTop / (float)kMapBytes), 0.03f);
+    for (int it = 0; it < 64; ++it) {
+        m.nx = (int)ceilf(ex / h);
+        m.ny = (int)ceilf(ey / h);
+        m.nz = (int)ceilf(kMapTop / h);
+        if ((long long)m.nx * m.ny * m.nz <= kMapBytes) {
+            m.h = h;
+            m.inv_h = 1.f / h;
+            m.x0 = -ax - kMapOver;
+            m.y0 = -ay - kMapOver;
+            return true;
+        }
+        h *= 1.05f;
+    }
+    return false;
+}
+
+// Adds a sphere (support frame); the caller writes the voxels t of its cube
+// with t % parts == part.
+__device__ __forceinline__ void map_insert(int8_t* __restrict__ M, const DepthMap& m, float cx,
+                                           float cy, float cz, float r, int part, int parts) {
+    if (!(fabsf(cx) < 1e4f && fabsf(cy) < 1e4f && fabsf(cz) < 1e4f && r >= 0.f && r < 1e3f)) return;
+    const float e = r + kMapReach;
+    const int i0 = max((int)floorf((cx - e - m.x0) * m.inv_h), 0);
+    const int i1 = min((int)floorf((cx + e - m.x0) * m.inv_h), m.nx - 1);
+    const int j0 = max((int)floorf((cy - e - m.y0) * m.inv_h), 0);
+    const int j1 = min((int)floorf((cy + e - m.y0) * m.inv_h), m.ny - 1);
+    const int k0 = max((int)floorf((cz - e) * m.inv_h), 0);
+    const int k1 = min((int)floorf((cz + e) * m.inv_h), m.nz - 1);
+    const int nxr = i1 - i0 + 1, nyr = j1 - j0 + 1, nzr = k1 - k0 + 1;
+    if (nxr <= 0 || nyr <= 0 || nzr <= 0) return;
+    const int total = nxr * nyr * nzr;
+    for (int t = part; t < total; t += parts) {
+        const int i = i0 + t % nxr, j = j0 + (t / nxr) % nyr, k = k0 + t / (nxr * nyr);
+        const float dx = fmaf((float)i + 0.5f, m.h, m.x0) - cx;
+        const float dy = fmaf((float)j + 0.5f, m.h, m.y0) - cy;
+        const float dz = ((float)k + 0.5f) * m.h - cz;
+        const float depth = r - sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        if (depth >= -kMapReach) {
+            const int q = min((int)floorf(depth * (1.f / kMapQ) - 1e-3f), 127);
+            int8_t* v = M + (k * m.ny + j) * m.nx + i;
+            if (q > (int)*v) *v = (int8_t)q;
+        }
+    }
+}
+
+__device__ __forceinline__ DepthMap map_params(const DepthMap* p) {
+    const volatile DepthMap* v = p;
+    DepthMap m;
+    m.x0 = v->x0; m.y0 = v->y0; m.h = v->h; m.inv_h = v->inv_h;
+    m.nx = v->nx; m.ny = v->ny; m.nz = v->nz;
+    return m;
+}
+
+// True when a sphere of radius rp centred at (px, py, pz) (support frame)
+// certainly comes within the margin of a mapped sphere.
+__device__ __forceinline__ bool map_hit(const int8_t* __restrict__ M, const DepthMap& m, float px,
+                                        float py, float pz, float rp, float margin) {
+    const float fx = (px - m.x0) * m.inv_h, fy = (py - m.y0) * m.inv_h, fz = pz * m.inv_h;
+    if (!(fx >= 0.f && fy >= 0.f && fz >= 0.f && fx < (float)m.nx && fy < (float)m.ny &&
+          fz < (float)m.nz))
+        return false;
+    const int i = min((int)fx, m.nx - 1), j = min((int)fy, m.ny - 1), k = min((int)fz, m.nz - 1);
+    const int q = M[(k * m.ny + j) * m.nx + i];
+    if (q == kMapNone) return false;
+    const float dx = fmaf((float)i + 0.5f, m.h, m.x0) - px;
+    const float dy = fmaf((float)j + 0.5f, m.h, m.y0) - py;
+    const float dz = ((float)k + 0.5f) * m.h - pz;
+    const float dv = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    return (float)q * kMapQ > dv - rp - margin + kMapSafety;
+}
+
 // kLds = true : the scene's placed spheres live in LDS (cap_sph of them);
 //               with `split`, scenes with more spheres are left to the
 //               other launch, otherwise they are a capacity error.
@@ -102,7 +201,11 @@ __global__ __launch_bounds__(1024) void k_place(
     extern __shared__ float4 lds[];
     float4* lsph = lds;                        // placed spheres: (x, y, z, r + margin)
     float4* lbnd = lds + (kLds ? cap_sph : 0); // world bounding sphere of each placed object
+    // scenes without grids: the depth map after the bounds (kMapBytes)
+    constexpr bool kMap = !kGrids;
+    int8_t* lmap = reinterpret_cast<int8_t*>(lbnd + cap_obj);
     __shared__ int s_best;
+    __shared__ DepthMap s_dm;   // read where used (volatile), not held in registers
 
     const int s = order ? order[blockIdx.x] : (int)blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
@@ -180,6 +283,36 @@ __global__ __launch_bounds__(1024) void k_place(
         }
         rho = wave_max(rho) * (1.0f + 1e-6f) + 1e-6f;
         if (lane == 0) lbnd[ob] = make_float4(c[0], c[1], c[2], rho);
+    }
+    // Depth map: when every object of the scene rests on one support, in that
+    // support's frame; cleared, then filled with the spheres already placed
+    // (their support-frame centres from the world ones)
+    bool use_map = false;
+    if constexpr (kMap) {
+        DepthMap dm{};
+        int other = 0;
+        for (int ob = o0 + (int)threadIdx.x; ob < o1; ob += blockDim.x)
+            other |= obj_sup[ob] != obj_sup[o0];
+        use_map = nobj > 0 && !__syncthreads_or(other);
+        if (use_map) {
+            const Support U0 = load_support(sup, obj_sup[o0]);
+            use_map = map_geometry(U0.hx - U0.inset, U0.hy - U0.inset, dm);
+            if (use_map) {
+                if (threadIdx.x == 0) s_dm = dm;
+                const int words = (dm.nx * dm.ny * dm.nz + 3) >> 2;
+                int* mw = reinterpret_cast<int*>(lmap);
+                for (int i = threadIdx.x; i < words; i += blockDim.x) mw[i] = (int)0x80808080u;
+                __syncthreads();
+                const int n_old = sph_off[o0 + j] - first;
+                for (int i = threadIdx.x; i < n_old; i += blockDim.x) {
+                    const float4 q = placed[first + i];
+                    const float dx = q.x - U0.t[0], dy = q.y - U0.t[1], dz = q.z - U0.t[2];
+                    map_insert(lmap, dm, fmaf(U0.R[0], dx, fmaf(U0.R[3], dy, U0.R[6] * dz)),
+                               fmaf(U0.R[1], dx, fmaf(U0.R[4], dy, U0.R[7] * dz)),
+                               fmaf(U0.R[2], dx, fmaf(U0.R[5], dy, U0.R[8] * dz)), q.w, 0, 1);
+                }
+            }
+        }
     }
     __syncthreads();
 
@@ -394,6 +527,14 @@ __global__ __launch_bounds__(1024) void k_place(
                 const float lim = reach + bd.w;
                 if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) omask[ob >> 6] |= 1ull << (ob & 63);
             }
+            // the probe against the depth map of the placed spheres
+            if (kMap && use_map && j > 0) {
+                if (!sure)
+                    sure = map_hit(lmap, map_params(&s_dm), fmaf(L.c, probe.x, fmaf(-L.s, probe.y, L.x)),
+                                   fmaf(L.s, probe.x, fmaf(L.c, probe.y, L.y)), probe.z + zc,
+                                   probe.w, margin);
+                n_sphc += __popcll(__ballot(live));
+            }
             const unsigned long long sure_mask = __ballot(sure && live);
             {
                 const unsigned long long nlive = __popcll(__ballot(live));
@@ -544,6 +685,16 @@ __global__ __launch_bounds__(1024) void k_place(
             }
             ++n_done;
         }
+        // the new object's spheres into the depth map (voxels split over the waves)
+        if (kMap && use_map) {
+            const DepthMap dm = map_params(&s_dm);
+#pragma unroll
+            for (int q = 0; q < SPL; ++q)
+                if (act[q])
+                    map_insert(lmap, dm, fmaf(Pw.c, cx[q], fmaf(-Pw.s, cy[q], Pw.x)),
+                               fmaf(Pw.s, cx[q], fmaf(Pw.c, cy[q], Pw.y)), cz[q] + Pw.z, cr[q], wave,
+                               W);
+        }
         last = fi;
         __syncthreads();
     }
@@ -582,7 +733,7 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
     const bool yaw = b.geometry == SCN_GEOM_YAW;
     auto kern = b.grid_off ? (yaw ? k_place<SPL, kLds, true, true> : k_place<SPL, kLds, true, false>)
                            : (yaw ? k_place<SPL, kLds, false, true> : k_place<SPL, kLds, false, false>);
-    const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj);
+    const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj) + (b.grid_off ? 0 : kMapBytes);
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

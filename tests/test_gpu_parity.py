@@ -182,7 +182,7 @@ def test_place_step_sequence_equals_generate(dev, orc):
         assert npl[s] == ref["n_placed"][s] or ref["rec_banded"][b.obj_off[s]:b.obj_off[s] + 5].any()
 
 
-@pytest.mark.parametrize("waves", [1, 2, 8, 16])
+@pytest.mark.parametrize("waves", [1, 2, 5, 8, 10, 16])
 def test_schedules_give_identical_results(dev, waves):
     scn, ctx, torch = dev
     b = sg.batched_scenes(64, seed=10)
