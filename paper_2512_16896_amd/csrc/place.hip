@@ -389,6 +389,37 @@ __global__ __launch_bounds__(1024) void k_place(
             probe = tmpl[sb + uniform_int(kp)];
         }
         const float prm2 = (probe.w + margin) * (probe.w + margin);
+        // A second probe on the far side: the largest sphere (lowest index among
+        // equals) farther from the first probe than half the farthest sphere.
+        float4 probe2 = probe;
+        bool two = false;
+        if (S > 1) {
+            auto d1 = [&](int q) {
+                const float dx = cx[q] - probe.x, dy = cy[q] - probe.y, dz = cz[q] - probe.z;
+                return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+            };
+            float dfar = 0.f;
+#pragma unroll
+            for (int q = 0; q < SPL; ++q)
+                if (act[q]) dfar = fmaxf(dfar, d1(q));
+            dfar = 0.5f * wave_max(dfar);
+            float r2 = -1.f;
+#pragma unroll
+            for (int q = 0; q < SPL; ++q)
+                if (act[q] && d1(q) > dfar) r2 = fmaxf(r2, cr[q]);
+            r2 = wave_max(r2);
+            if (r2 >= 0.f) {
+                int kp = 0;
+#pragma unroll
+                for (int q = SPL - 1; q >= 0; --q) {
+                    const unsigned long long m = __ballot(act[q] && d1(q) > dfar && cr[q] == r2);
+                    if (m) kp = kWave * q + __builtin_ctzll(m);
+                }
+                probe2 = tmpl[sb + uniform_int(kp)];
+                two = true;
+            }
+        }
+        const float prm2b = (probe2.w + margin) * (probe2.w + margin);
 
         const Support U = load_support(sup, obj_sup[o]);
         const float ax = U.hx - U.inset, ay = U.hy - U.inset, zc = U.lift + lift;
@@ -405,6 +436,7 @@ __global__ __launch_bounds__(1024) void k_place(
 #pragma unroll
         for (int q = 0; q < SPL; ++q) wz0[q] = (cz[q] + zc) + U.t[2];
         const float bz0 = (bc[2] + zc) + U.t[2], pz0 = (probe.z + zc) + U.t[2];
+        const float pz02 = (probe2.z + zc) + U.t[2];
         const int C = obj_ncand ? obj_ncand[o] : default_ncand;
         // proposals of this scene (only when it has them this step)
         const int pk = prop_bins ? prop_k : 0;
@@ -418,6 +450,32 @@ __global__ __launch_bounds__(1024) void k_place(
         const int g_lo = j == j_start ? min(resume0, total) : 0;
         const int g_hi = chunk > 0 ? min(total, max(g_lo, pk) + chunk) : total;
         const int nob_mask = min(j, kWave * kObjWords);     // objects covered by the masks
+        // Boxes (of the first 64) that some candidate of this object can reach:
+        // every candidate's bounding centre lies, in the support frame, on the
+        // rectangle grown by |bc_xy| at height bc_z + zc; a box whose
+        // bounding sphere stays farther than reach from that set is skipped
+        // by the batch phase.
+        unsigned long long box_rel;
+        {
+            const float gx = ax + sqrtf(fmaf(bc[0], bc[0], bc[1] * bc[1]));
+            const float gy = ay + sqrtf(fmaf(bc[0], bc[0], bc[1] * bc[1]));
+            const float hz = bc[2] + zc;
+            bool rel = false;
+            if (lane < nbox_mask) {
+                const float* B = box + 16 * (b0 + lane);
+                const float dx = B[9] - U.t[0], dy = B[10] - U.t[1], dz = B[11] - U.t[2];
+                const float sx = fmaf(U.R[0], dx, fmaf(U.R[3], dy, U.R[6] * dz));
+                const float sy = fmaf(U.R[1], dx, fmaf(U.R[4], dy, U.R[7] * dz));
+                const float sz = fmaf(U.R[2], dx, fmaf(U.R[5], dy, U.R[8] * dz));
+                const float ox = fmaxf(fabsf(sx) - gx, 0.f), oy = fmaxf(fabsf(sy) - gy, 0.f);
+                const float oz = sz - hz;
+                const float lim = sqrtf(fmaf(B[12], B[12], fmaf(B[13], B[13], B[14] * B[14]))) +
+                                  reach;
+                // generous slack for the rounding of this test (it only prunes)
+                rel = fmaf(ox, ox, fmaf(oy, oy, oz * oz)) < lim * lim * 1.0001f + 1e-6f;
+            }
+            box_rel = __ballot(rel);
+        }
 
         if (threadIdx.x == 0) s_best = INT_MAX;
         __syncthreads();
@@ -484,28 +542,34 @@ __global__ __launch_bounds__(1024) void k_place(
             const Pose L = entry_pose(live ? g : 0, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
                                       ay, zc, &ga, &gi);
             float lx, ly, lz;   // world centre of this candidate's bounding sphere
-            float qx, qy, qz;   // world centre of its probe sphere
+            float qx, qy, qz;   // world centres of its probe spheres
+            float ux, uy, uz;
             Planar M{};         // the candidate's planar motion (kYaw)
             if constexpr (kYaw) {
                 M = planar(U, L);
                 planar_xy(M, bc[0], bc[1], lx, ly);
                 planar_xy(M, probe.x, probe.y, qx, qy);
+                planar_xy(M, probe2.x, probe2.y, ux, uy);
                 lz = bz0;
                 qz = pz0;
+                uz = pz02;
             } else {
                 to_world(U, L, bc[0], bc[1], bc[2], lx, ly, lz);
                 to_world(U, L, probe.x, probe.y, probe.z, qx, qy, qz);
+                to_world(U, L, probe2.x, probe2.y, probe2.z, ux, uy, uz);
             }
             bool sure = false;  // the probe collides: the candidate is rejected
             unsigned long long bmask = 0, gmask = 0, omask[kObjWords] = {};
-            for (int bi = 0; bi < nbox_mask; ++bi) {
+            for (unsigned long long rm = box_rel; rm; rm &= rm - 1) {
+                const int bi = __builtin_ctzll(rm);
                 const float* B = box + 16 * (b0 + bi);
                 const bool near = box_out2_t<kYaw>(B, lx, ly, lz) < reach * reach;
                 if (near) {
                     bmask |= 1ull << bi;
                     sure |= box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
+                    if (two) sure |= box_out2_t<kYaw>(B, ux, uy, uz) < prm2b;
                 }
-                n_boxp += __popcll(__ballot(near && live));
+                n_boxp += (two ? 2u : 1u) * __popcll(__ballot(near && live));
             }
             // grids: only spheres whose centres lie inside a grid's node box
             // sample it (outside it reads +inf), so a bounding sphere that
@@ -515,11 +579,11 @@ __global__ __launch_bounds__(1024) void k_place(
                 const bool near = grid_box_d2(G, lx, ly, lz) <= rho * rho;
                 if (near) {
                     gmask |= 1ull << gi;
-                    if (!sure)
-                        sure = grid_sample(G, grid_val + grid_val_off[grid_src[g0 + gi]], qx, qy,
-                                           qz) < probe.w + margin;
+                    const float* vals = grid_val + grid_val_off[grid_src[g0 + gi]];
+                    if (!sure) sure = grid_sample(G, vals, qx, qy, qz) < probe.w + margin;
+                    if (two && !sure) sure = grid_sample(G, vals, ux, uy, uz) < probe2.w + margin;
                 }
-                n_grid += __popcll(__ballot(near && live));
+                n_grid += (two ? 2u : 1u) * __popcll(__ballot(near && live));
             }
             for (int ob = 0; ob < nob_mask; ++ob) {
                 const float4 bd = lbnd[ob];
@@ -529,18 +593,23 @@ __global__ __launch_bounds__(1024) void k_place(
             }
             // the probe against the depth map of the placed spheres
             if (kMap && use_map && j > 0) {
+                const DepthMap dmq = map_params(&s_dm);
                 if (!sure)
-                    sure = map_hit(lmap, map_params(&s_dm), fmaf(L.c, probe.x, fmaf(-L.s, probe.y, L.x)),
+                    sure = map_hit(lmap, dmq, fmaf(L.c, probe.x, fmaf(-L.s, probe.y, L.x)),
                                    fmaf(L.s, probe.x, fmaf(L.c, probe.y, L.y)), probe.z + zc,
                                    probe.w, margin);
-                n_sphc += __popcll(__ballot(live));
+                if (two && !sure)
+                    sure = map_hit(lmap, dmq, fmaf(L.c, probe2.x, fmaf(-L.s, probe2.y, L.x)),
+                                   fmaf(L.s, probe2.x, fmaf(L.c, probe2.y, L.y)), probe2.z + zc,
+                                   probe2.w, margin);
+                n_sphc += (two ? 2u : 1u) * __popcll(__ballot(live));
             }
             const unsigned long long sure_mask = __ballot(sure && live);
             {
                 const unsigned long long nlive = __popcll(__ballot(live));
-                n_boxc += nlive * (unsigned long long)(nbox_mask + ngrid_mask);
+                n_boxc += nlive * (unsigned long long)(__popcll(box_rel) + ngrid_mask);
                 n_objc += nlive * (unsigned long long)nob_mask;
-                n_xf += nlive;   // probe transforms
+                n_xf += (two ? 2u : 1u) * nlive;   // probe transforms
             }
             // ---- candidate phase ----
             for (int t = 0; t < kWave; ++t) {
