@@ -51,7 +51,7 @@ WORKLOADS = {
                               "sqrt(N/20); margin 5 mm; 10 retries",
                          make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                       fromlist=["x"]).uneven_batch(16384, seed=seed),
-                         ncand=1024, cpu_scenes=24, tune=True),
+                         ncand=1024, cpu_scenes=24, tune=True, graph=True),
     "shelves-65536": dict(desc="65536 scenes x 6 stacked 0.8x0.4 m shelves; 100 objects x 128 "
                                "spheres (r~U[0.005,0.02] m, centres in a cube of side "
                                "U[0.03,0.08] m), round-robin over the shelves; furniture as "
@@ -223,8 +223,10 @@ def main():
     ctx = scn.Context(0)
     db = scn.DeviceBatch(b, "cuda:0")
     stream = torch.cuda.current_stream()
+    graph = 1 if W.get("graph") else 0
     gen = lambda step: scn.generate_scenes(
-        ctx, db, scn.GenArgs(seed=1000 + step, default_ncand=W["ncand"], schedule=args.schedule))
+        ctx, db, scn.GenArgs(seed=1000 + step, default_ncand=W["ncand"], schedule=args.schedule,
+                             use_graph=graph))
 
     tuned = None
     if W.get("tune") and args.schedule == 0:
@@ -265,6 +267,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W['desc']}", "scenes": n,
                    "objects": int(b.n_objects), "method": "plain (uniform candidates)"},
+        "launch": "hipGraph replay" if graph else "direct",
         "schedule": (f"autotuned 0x{tuned[0]:x}" if tuned else
                      (f"0x{args.schedule:x}" if args.schedule else "default")),
         "valid_fraction": valid / (n * steps),

@@ -146,9 +146,10 @@ typedef struct {
     int32_t default_ncand; /* candidates per attempt when obj_ncand is NULL        */
     int32_t max_steps;     /* scn_generate_scenes: objects per scene (<= 0: all)    */
     int32_t schedule;      /* 0: autotuned / default; >0: explicit schedule id      */
-    int32_t use_graph;     /* scn_generate_scenes_learned: capture the step launch
-                            * once per call and replay it as a hipGraph (the plain
-                            * generation is one persistent launch; ignored there) */
+    int32_t use_graph;     /* replay the launches as a hipGraph: scn_generate_scenes
+                            * keeps one executable graph per batch and plan and
+                            * refreshes its arguments each call; the learned
+                            * generation captures its step launch once per call */
     int32_t fallback_chunk;/* scn_generate_scenes_learned: uniform fallback entries
                             * tried per step launch (0: one attempt of the largest
                             * candidate count; < 0: the whole fallback at once)     */

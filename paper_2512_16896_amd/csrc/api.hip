@@ -127,6 +127,7 @@ int scn_ctx_destroy(scn_ctx* c) {
     if (c->d_hist) (void)hipFree(c->d_hist);
     if (c->ws) (void)hipFree(c->ws);
     if (c->h_flag) (void)hipHostFree(c->h_flag);
+    for (auto& kv : c->plain_graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return SCN_OK;
@@ -323,11 +324,61 @@ __attribute__((visibility("hidden"))) int scn_place_internal(
     return run_place(c, b, a, plan, chosen, reset, st);
 }
 
+// The generation's launches (reset, scene order, place kernel) as a hipGraph:
+// recorded on the context's capture stream, used to refresh the executable
+// graph kept for this batch and plan (hipGraphExecUpdate: only the kernel
+// arguments such as the seed differ between calls), then replayed on `st`.
+static int run_place_graph(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
+                           const scn::PlacePlan& plan, hipStream_t st) {
+    if (!c->cap_stream) SCN_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    SCN_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    const int r = run_place(c, b, a, plan, nullptr, true, c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (r != SCN_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return r != SCN_OK ? r : fail(SCN_E_HIP, "generation capture: %s", hipGetErrorString(e));
+    }
+    char key[512];
+    snprintf(key, sizeof key, "%p %p %p %p %p %p %p %p %p %p %p %p %d %d %d %d %d %d %d %d %d %p",
+             (const void*)b->obj_off, (const void*)b->sph_off, (const void*)b->tmpl,
+             (const void*)b->sup, (const void*)b->box, (const void*)b->grid,
+             (const void*)b->placed, (const void*)b->n_placed, (const void*)b->status,
+             (const void*)b->rec, (const void*)b->obj_ncand, (const void*)b->grid_off, b->n_scenes,
+             b->n_objects, b->geometry, plan.mode, plan.waves, plan.spl, plan.cap_sph,
+             plan.split_sph, plan.max_steps, (const void*)plan.order);
+    auto it = c->plain_graphs.find(key);
+    if (it != c->plain_graphs.end()) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(it->second, g, &bad, &res) != hipSuccess ||
+            res != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(it->second);
+            c->plain_graphs.erase(it);
+            it = c->plain_graphs.end();
+        }
+    }
+    if (it == c->plain_graphs.end()) {
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(SCN_E_HIP, "generation graph: %s", hipGetErrorString(ei));
+        }
+        it = c->plain_graphs.emplace(key, ex).first;
+    }
+    (void)hipGraphDestroy(g);
+    SCN_HIP(hipGraphLaunch(it->second, st));
+    return SCN_OK;
+}
+
 int scn_generate_scenes(scn_ctx* c, scn_batch* b, const scn_gen_args* a, scn_stream stream) {
     if (int r = check_ctx(c)) return r;
     if (int r = check_batch(b, true)) return r;
     scn::PlacePlan plan;
     if (int r = plan_place(c, b, a, a ? a->max_steps : 0, &plan)) return r;
+    if (a->use_graph) return run_place_graph(c, b, a, plan, (hipStream_t)stream);
     return run_place(c, b, a, plan, nullptr, true, (hipStream_t)stream);
 }
 

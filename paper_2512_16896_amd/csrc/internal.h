@@ -21,7 +21,8 @@ struct scn_ctx {
     void* ws;              // grow-only workspace arena (network activations, staging)
     size_t ws_bytes;
     int32_t* h_flag = nullptr;   // pinned host word for small device-to-host reads
-    hipStream_t cap_stream = nullptr;   // stream used only to capture step graphs
+    hipStream_t cap_stream = nullptr;   // stream used only to capture graphs
+    std::map<std::string, hipGraphExec_t> plain_graphs;   // generation graphs per batch + plan
     struct Tuned { int schedule; float ms; };
     std::map<std::string, Tuned> tuned;   // autotuned schedule per batch shape bucket
 };

@@ -324,3 +324,23 @@ def test_false_yaw_declaration_marks_scenes_invalid(dev):
     assert e.value.code == -1 and "SCN_GEOM_YAW" in str(e.value)
     ctx.reset_counters()
     assert np.all(status == 2) and np.all(npl == 0)
+
+
+@pytest.mark.parametrize("sched", [0, 0x24 | (2 << 8)])
+def test_generation_graph_replays_match_eager(dev, sched):
+    """use_graph: the generation's launches replay from a cached executable
+    graph whose arguments are refreshed per call; every replay, with eager
+    work and synchronizations between them, equals the eager run."""
+    scn, ctx, torch = dev
+    b = sg.uneven_batch(48, seed=2) if sched else sg.batched_scenes(64, seed=31)
+    db = scn.DeviceBatch(b)
+    other = scn.DeviceBatch(sg.table_scene(seed=3))
+    for seed in (5, 6, 5, 7):
+        scn.generate_scenes(ctx, db, scn.GenArgs(seed=seed, schedule=sched))
+        eager = _device_results(db)
+        scn.generate_scenes(ctx, other, scn.GenArgs(seed=seed, default_ncand=256))
+        torch.cuda.synchronize()
+        scn.generate_scenes(ctx, db, scn.GenArgs(seed=seed, schedule=sched, use_graph=1))
+        got = _device_results(db)
+        for u, v in zip(eager, got):
+            np.testing.assert_array_equal(u, v)
