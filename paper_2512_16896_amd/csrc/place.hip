@@ -180,21 +180,26 @@ __device__ __forceinline__ bool map_hit(const int8_t* __restrict__ M, const Dept
 // only); candidate transforms and box tests take their planar form (4 instead
 // of 14 instructions per sphere transform, 5 fewer per box test). A scene
 // that breaks the declaration is marked invalid with kErrGeometry.
+// The kernel's parameters, shared by the two entry points below.
+#define SCN_PLACE_PARAMS     const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off, \
+    const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup, \
+    const int32_t* __restrict__ obj_ncand, const float* __restrict__ sup, \
+    const int32_t* __restrict__ box_off, const float* __restrict__ box, \
+    float4* __restrict__ placed, int32_t* __restrict__ n_placed, int8_t* __restrict__ status, \
+    scn_pose_rec* __restrict__ rec, int32_t* __restrict__ chosen, \
+    unsigned long long* __restrict__ counters, const int32_t* __restrict__ order, uint64_t seed, \
+    float margin, int retries, int default_ncand, int max_steps, int cap_sph, int cap_obj, \
+    int split, int split_sph, const int32_t* __restrict__ prop_bins, int prop_k, \
+    int32_t* __restrict__ resume, int chunk, int j_cap, int32_t* __restrict__ n_active, \
+    const int32_t* __restrict__ grid_off, const float* __restrict__ grid, \
+    const int32_t* __restrict__ grid_src, const int64_t* __restrict__ grid_val_off, \
+    const float* __restrict__ grid_val
+#define SCN_PLACE_ARGS \
+    obj_off, sph_off, tmpl, obj_sup, obj_ncand, sup, box_off, box, placed, n_placed, status, rec, chosen, counters, order, seed, margin, retries, default_ncand, max_steps, cap_sph, cap_obj, split, split_sph, prop_bins, prop_k, resume, chunk, j_cap, n_active, \
+    grid_off, grid, grid_src, grid_val_off, grid_val
+
 template <int SPL, bool kLds, bool kGrids, bool kYaw>
-__global__ __launch_bounds__(1024) void k_place(
-    const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
-    const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
-    const int32_t* __restrict__ obj_ncand, const float* __restrict__ sup,
-    const int32_t* __restrict__ box_off, const float* __restrict__ box,
-    float4* __restrict__ placed, int32_t* __restrict__ n_placed, int8_t* __restrict__ status,
-    scn_pose_rec* __restrict__ rec, int32_t* __restrict__ chosen,
-    unsigned long long* __restrict__ counters, const int32_t* __restrict__ order, uint64_t seed,
-    float margin, int retries, int default_ncand, int max_steps, int cap_sph, int cap_obj,
-    int split, int split_sph, const int32_t* __restrict__ prop_bins, int prop_k,
-    int32_t* __restrict__ resume, int chunk, int j_cap, int32_t* __restrict__ n_active,
-    const int32_t* __restrict__ grid_off, const float* __restrict__ grid,
-    const int32_t* __restrict__ grid_src, const int64_t* __restrict__ grid_val_off,
-    const float* __restrict__ grid_val) {
+__device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     // placed objects covered by the batch masks: 64 per word; the dense
     // multi-shelf (grid) scenes carry 100 objects, so they get two words
     constexpr int kObjWords = kGrids ? 2 : 1;
@@ -391,9 +396,11 @@ __global__ __launch_bounds__(1024) void k_place(
         const float prm2 = (probe.w + margin) * (probe.w + margin);
         // A second probe on the far side: the largest sphere (lowest index among
         // equals) farther from the first probe than half the farthest sphere.
+        // Not in grid batches: their placements rarely collide, and the extra
+        // registers would cost occupancy.
         float4 probe2 = probe;
         bool two = false;
-        if (S > 1) {
+        if (!kGrids && S > 1) {
             auto d1 = [&](int q) {
                 const float dx = cx[q] - probe.x, dy = cy[q] - probe.y, dz = cz[q] - probe.z;
                 return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
@@ -795,13 +802,35 @@ __global__ __launch_bounds__(1024) void k_place(
     }
 }
 
+// Entry points.  k_place: every batch but the ones below.  k_place_g5: grid
+// batches with up to 128 spheres per object, asked for 5 waves per SIMD
+// (their code sits a few registers above it, and a few bytes of spills cost
+// less than a fifth of the waves; 256-sphere objects would spill far more).
+template <int SPL, bool kLds, bool kGrids, bool kYaw>
+__global__ __launch_bounds__(1024) void k_place(SCN_PLACE_PARAMS) {
+    place_scenes<SPL, kLds, kGrids, kYaw>(SCN_PLACE_ARGS);
+}
+template <int SPL, bool kLds, bool kYaw>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_place_g5(
+    SCN_PLACE_PARAMS) {
+    place_scenes<SPL, kLds, true, kYaw>(SCN_PLACE_ARGS);
+}
+
+template <int SPL, bool kLds, bool kGrids, bool kYaw>
+static auto place_kernel() {
+    if constexpr (kGrids && SPL <= 2) return k_place_g5<SPL, kLds, kYaw>;
+    else return k_place<SPL, kLds, kGrids, kYaw>;
+}
+
 template <int SPL, bool kLds>
 static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                    const PlacePlan& plan, int cap_sph, int split, int32_t* chosen,
                                    unsigned long long* ctr, hipStream_t st) {
     const bool yaw = b.geometry == SCN_GEOM_YAW;
-    auto kern = b.grid_off ? (yaw ? k_place<SPL, kLds, true, true> : k_place<SPL, kLds, true, false>)
-                           : (yaw ? k_place<SPL, kLds, false, true> : k_place<SPL, kLds, false, false>);
+    auto kern = b.grid_off ? (yaw ? place_kernel<SPL, kLds, true, true>()
+                                  : place_kernel<SPL, kLds, true, false>())
+                           : (yaw ? place_kernel<SPL, kLds, false, true>()
+                                  : place_kernel<SPL, kLds, false, false>());
     const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj) + (b.grid_off ? 0 : kMapBytes);
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
