@@ -80,6 +80,34 @@ def recorded_traffic(key: str):
     return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def dense_equivalent(b, db, ncand, retries=10):
+    """Survey definition of the generation roofline: the FLOP a dense check of
+    every candidate a first-valid scan must decide would compute (entries up
+    to and including the accepted one; all (R+1) C entries of an object that
+    fails), at 11 per sphere pair, 26 per sphere-box test, 10 per sphere
+    transform -- for the last generation in `db` (plain records)."""
+    _, rec = db.records()
+    n_placed = db.n_placed.cpu().numpy()
+    status = db.status.cpu().numpy()
+    obj_off = np.asarray(b.obj_off, np.int64)
+    sph_off = np.asarray(b.sph_off, np.int64)
+    nbox = np.diff(np.asarray(b.box_off, np.int64))
+    C = np.asarray(b.obj_ncand, np.int64) if b.obj_ncand is not None else None
+    flop = 0
+    for s in range(b.n_scenes):
+        o0 = obj_off[s]
+        last = min(int(n_placed[s]) + (1 if status[s] == 2 else 0), int(obj_off[s + 1] - o0))
+        for j in range(last):
+            o = o0 + j
+            c = int(C[o]) if C is not None else ncand
+            a, i = int(rec[o, 0]), int(rec[o, 1])
+            decided = a * c + i + 1 if i >= 0 else (retries + 1) * c
+            S = int(sph_off[o + 1] - sph_off[o])
+            P = int(sph_off[o] - sph_off[o0])
+            flop += decided * S * (11 * P + 26 * int(nbox[s]) + 10)
+    return flop
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -281,6 +309,12 @@ def main():
                      "kernel": "k_place (fused place kernel)",
                      "kernel_ms": launch_ms},
     }
+    dq = dense_equivalent(b, db, W["ncand"])
+    out["dense_equivalent"] = {
+        "flop_per_step": dq, "tflops": dq / (launch_ms * 1e-3) / 1e12,
+        "x_fp32_peak": dq / (launch_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS,
+        "note": "dense FLOP of the candidates a first-valid scan decides (last step), over the "
+                "place kernel's time; culling makes it exceed the peak"}
     if W.get("dense"):
         progress("dense check")
         out["dense_check"] = dense_leg(ctx, db, b, W, stream)
