@@ -618,18 +618,21 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 n_objc += nlive * (unsigned long long)nob_mask;
                 n_xf += (two ? 2u : 1u) * nlive;   // probe transforms
             }
-            // ---- candidate phase ----
-            for (int t = 0; t < kWave; ++t) {
+            // ---- candidate phase: the entries the batch phase left open, in
+            // entry order; entries below position t_end are decided ----
+            const unsigned long long live_mask = __ballot(live);
+            unsigned long long todo = live_mask & ~sure_mask;
+            int t_end = kWave;
+            if (live_mask != ~0ull) stop = true;   // the entry list ends in this batch
+            while (todo) {
+                const int t = __builtin_ctzll(todo);
+                todo &= todo - 1;
                 const int gt = gb + W * t;
-                if (gt >= g_hi) { stop = true; break; }
                 if (uniform_int(__hip_atomic_load(&s_best, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_WORKGROUP)) < gt) {
+                    t_end = t;
                     stop = true;
                     break;
-                }
-                if ((sure_mask >> t) & 1ull) {   // rejected by its probe
-                    ++n_cand;
-                    continue;
                 }
                 Pose P{};
                 Planar Mt{};
@@ -642,7 +645,6 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 }
                 Gx = bcast(lx, t); Gy = bcast(ly, t); Gz = bcast(lz, t);
                 unsigned long long bm = bcast64(bmask, t), gm = bcast64(gmask, t);
-                ++n_cand;
                 n_xf += S;
 #pragma unroll
                 for (int q = 0; q < SPL; ++q) {
@@ -710,10 +712,12 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 }
                 if (!__ballot(hit)) {
                     if (lane == 0) atomicMin(&s_best, gt);
+                    t_end = t + 1;
                     stop = true;
                     break;
                 }
             }
+            n_cand += __popcll(t_end == kWave ? live_mask : live_mask & ((1ull << t_end) - 1));
         }
         __syncthreads();
         const int best = s_best;
