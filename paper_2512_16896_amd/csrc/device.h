@@ -201,21 +201,35 @@ __device__ __forceinline__ float grid_box_d2(const float* G, float px, float py,
     return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
 }
 
-// Wave-wide reductions (64 lanes).
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, kWave));
-    return v;
-}
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, kWave));
-    return v;
-}
-
 __device__ __forceinline__ float bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
+
+// One DPP move of v (lanes the pattern does not write keep v).
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), kCtrl, kRowMask, 0xf, false));
+}
+
+// Wave-wide max / min over all 64 lanes (call with every lane active), on the
+// DPP network rather than LDS permutes: pairs and quads (quad_perm), half rows
+// (row_half_mirror) and rows of 16 (row_mirror), then row 0 into row 1 and
+// row 2 into row 3 (row_bcast:15), and row 1 into rows 2-3 (row_bcast:31);
+// lane 63 then holds the result, returned to every lane.
+template <bool kMax>
+__device__ __forceinline__ float wave_extreme(float v) {
+    auto op = [](float a, float b) { return kMax ? fmaxf(a, b) : fminf(a, b); };
+    v = op(v, dpp_f<0xB1>(v));        // quad_perm [1, 0, 3, 2]
+    v = op(v, dpp_f<0x4E>(v));        // quad_perm [2, 3, 0, 1]
+    v = op(v, dpp_f<0x141>(v));       // row_half_mirror
+    v = op(v, dpp_f<0x140>(v));       // row_mirror
+    v = op(v, dpp_f<0x142, 0xA>(v));  // row_bcast:15 into rows 1 and 3
+    v = op(v, dpp_f<0x143, 0xC>(v));  // row_bcast:31 into rows 2 and 3
+    return bcast(v, kWave - 1);
+}
+__device__ __forceinline__ float wave_max(float v) { return wave_extreme<true>(v); }
+__device__ __forceinline__ float wave_min(float v) { return wave_extreme<false>(v); }
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 }  // namespace scn

@@ -127,9 +127,16 @@ __device__ __forceinline__ void map_insert(int8_t* __restrict__ M, const DepthMa
     const int k1 = min((int)floorf((cz + e) * m.inv_h), m.nz - 1);
     const int nxr = i1 - i0 + 1, nyr = j1 - j0 + 1, nzr = k1 - k0 + 1;
     if (nxr <= 0 || nyr <= 0 || nzr <= 0) return;
-    const int total = nxr * nyr * nzr;
+    static_assert(kMapBytes < 32768, "voxel indices of a cube must stay below 2^15");
+    const int nxy = nxr * nyr, total = nxy * nzr;
+    // t -> (i, j, k) by float reciprocals: with t < 2^15 the quotient of
+    // (t + 1/2) / n stays at least 1/(2n) from an integer, far beyond the
+    // rounding of the product, so the truncations are exact
+    const float rx = 1.f / (float)nxr, rxy = 1.f / (float)nxy;
     for (int t = part; t < total; t += parts) {
-        const int i = i0 + t % nxr, j = j0 + (t / nxr) % nyr, k = k0 + t / (nxr * nyr);
+        const int kk = (int)(((float)t + 0.5f) * rxy), rem = t - kk * nxy;
+        const int jj = (int)(((float)rem + 0.5f) * rx);
+        const int i = i0 + (rem - jj * nxr), j = j0 + jj, k = k0 + kk;
         const float dx = fmaf((float)i + 0.5f, m.h, m.x0) - cx;
         const float dy = fmaf((float)j + 0.5f, m.h, m.y0) - cy;
         const float dz = ((float)k + 0.5f) * m.h - cz;
@@ -210,6 +217,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     constexpr bool kMap = !kGrids;
     int8_t* lmap = reinterpret_cast<int8_t*>(lbnd + cap_obj);
     __shared__ int s_best;
+    // the pose of the entry each wave found valid (a wave finds at most one
+    // per object): x, y, z, c, s, yaw, attempt, index
+    __shared__ float s_found[16][8];
     __shared__ DepthMap s_dm;   // read where used (volatile), not held in registers
 
     const int s = order ? order[blockIdx.x] : (int)blockIdx.x;
@@ -711,7 +721,18 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                     }
                 }
                 if (!__ballot(hit)) {
-                    if (lane == 0) atomicMin(&s_best, gt);
+                    if (lane == 0) atomicMin(&s_best, gt);   // first, so other waves stop early
+                    // its pose for the commit, drawn again here (once per
+                    // wave and object) rather than by every wave after the
+                    // barrier or kept live in registers
+                    int fa, fi;
+                    const Pose F = entry_pose(gt, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
+                                              ay, zc, &fa, &fi);
+                    if (lane == 0) {
+                        float* f = s_found[wave];
+                        f[0] = F.x; f[1] = F.y; f[2] = F.z; f[3] = F.c; f[4] = F.s; f[5] = F.yaw;
+                        f[6] = __int_as_float(fa); f[7] = __int_as_float(fi);
+                    }
                     t_end = t + 1;
                     stop = true;
                     break;
@@ -731,9 +752,14 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                      (best == INT_MAX ? (unsigned)(retries + 1)
                                       : (best < pk ? 0u : (unsigned)((best - pk) / C + 1)));
         if (best == INT_MAX) { fin = SCN_SCENE_INVALID; last = -1; break; }
+        // the pose the owning wave tested (entries g_lo + w + W n belong to wave w)
+        Pose Pw;
         int fa, fi;
-        const Pose Pw = entry_pose(best, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax, ay, zc,
-                                   &fa, &fi);
+        {
+            const float* f = s_found[(best - g_lo) % W];
+            Pw.x = f[0]; Pw.y = f[1]; Pw.z = f[2]; Pw.c = f[3]; Pw.s = f[4]; Pw.yaw = f[5];
+            fa = __float_as_int(f[6]); fi = __float_as_int(f[7]);
+        }
         if (wave == 0) {
             const Pose P = Pw;
             const Planar Mc = planar(U, P);   // the planar form
@@ -765,8 +791,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             }
             ++n_done;
         }
-        // the new object's spheres into the depth map (voxels split over the waves)
-        if (kMap && use_map) {
+        // the new object's spheres into the depth map (voxels split over the
+        // waves); a later launch rebuilds the map from the placed spheres
+        if (kMap && use_map && j + 1 < j_end) {
             const DepthMap dm = map_params(&s_dm);
 #pragma unroll
             for (int q = 0; q < SPL; ++q)
