@@ -264,11 +264,11 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
     // dynamic LDS available to the place kernel: the block limit minus the
     // kernel's own static shared variables
     const long long lds_cap = c->lds_per_block - 1024 - (b->grid_off ? 0 : scn::kMapBytes);
-    if (16LL * plan->cap_obj + 16LL * 64 > lds_cap)
+    if (16LL * scn::kObjLds * plan->cap_obj + 16LL * 64 > lds_cap)
         return fail(SCN_E_UNSUPPORTED, "%d objects per scene do not fit the LDS", plan->cap_obj);
     static const int kBudgetKB[] = {0, 32, 48, 64, 80, 96};
     const int code = (sched & SCN_SCHED_LDS_MASK) >> SCN_SCHED_LDS_SHIFT;
-    const long long all_bytes = 16LL * plan->cap_sph + 16LL * plan->cap_obj;
+    const long long all_bytes = 16LL * plan->cap_sph + 16LL * scn::kObjLds * plan->cap_obj;
     if (code == SCN_SCHED_LDS_NONE) {
         plan->mode = scn::kPlaceAllGlobal;
         plan->split_sph = 0;
@@ -280,7 +280,7 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
             plan->split_sph = plan->cap_sph;
         } else {
             plan->mode = scn::kPlaceSplit;
-            plan->split_sph = (int)(budget / 16) - plan->cap_obj;
+            plan->split_sph = (int)(budget / 16) - scn::kObjLds * plan->cap_obj;
             if (plan->split_sph < 1) plan->split_sph = 1;
         }
     } else {

@@ -231,5 +231,8 @@ __device__ __forceinline__ float wave_extreme(float v) {
 __device__ __forceinline__ float wave_max(float v) { return wave_extreme<true>(v); }
 __device__ __forceinline__ float wave_min(float v) { return wave_extreme<false>(v); }
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
 
 }  // namespace scn

@@ -54,6 +54,9 @@ enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2 };
 // Bytes of dynamic LDS the place kernel adds for a scene's depth map (batches
 // without grids).
 constexpr int kMapBytes = 24576;
+// float4 slots per object in the place kernel's LDS: its world bounding
+// sphere once placed, and 4 constants while it is to be placed
+constexpr int kObjLds = 5;
 
 // Where the fused place kernel keeps a scene's placed spheres.
 enum PlaceMode {

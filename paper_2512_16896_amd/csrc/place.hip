@@ -175,6 +175,130 @@ __device__ __forceinline__ bool map_hit(const int8_t* __restrict__ M, const Dept
     return (float)q * kMapQ > dv - rp - margin + kMapSafety;
 }
 
+// Constants of an object that depend on its sphere set only: the centre bc
+// of the spheres' bounding box, the radius rho of the bounding sphere about
+// bc, the lift that rests the lowest point on the support, and the probes.
+// One wave computes them (all 64 lanes active).
+struct ObjConsts {
+    float bc[3], rho, lift;
+    float4 probe, probe2;
+    bool two;
+};
+
+template <int SPL, bool kProbe2>
+__device__ __forceinline__ ObjConsts object_consts(const float4* __restrict__ tmpl, int sb, int S,
+                                                   int lane) {
+    ObjConsts K;
+    float cx[SPL], cy[SPL], cz[SPL], cr[SPL];
+    bool act[SPL];
+    float lift = -1e30f, lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        const int k = lane + kWave * q;
+        act[q] = k < S;
+        const float4 c = act[q] ? tmpl[sb + k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        cx[q] = c.x; cy[q] = c.y; cz[q] = c.z; cr[q] = c.w;
+        if (act[q]) {
+            lift = fmaxf(lift, c.w - c.z);
+            lo[0] = fminf(lo[0], c.x - c.w); hi[0] = fmaxf(hi[0], c.x + c.w);
+            lo[1] = fminf(lo[1], c.y - c.w); hi[1] = fmaxf(hi[1], c.y + c.w);
+            lo[2] = fminf(lo[2], c.z - c.w); hi[2] = fmaxf(hi[2], c.z + c.w);
+        }
+    }
+    K.lift = wave_max(lift);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) K.bc[d] = 0.5f * (wave_min(lo[d]) + wave_max(hi[d]));
+    float rho = 0.f;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        if (act[q]) {
+            const float dx = cx[q] - K.bc[0], dy = cy[q] - K.bc[1], dz = cz[q] - K.bc[2];
+            rho = fmaxf(rho, sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) + cr[q]);
+        }
+    }
+    K.rho = wave_max(rho) * (1.0f + 1e-6f) + 1e-6f;
+    // Probe: the object's largest sphere (the lowest index among equals).
+    // A candidate whose probe already comes within the margin of a box, a grid
+    // or the depth map collides, and the batch phase settles that for 64
+    // candidates at once with the same arithmetic as the full test of that
+    // sphere.
+    K.probe = make_float4(0.f, 0.f, 1e18f, 0.f);
+    if (S > 0) {
+        float rmax = -1.f;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q)
+            if (act[q]) rmax = fmaxf(rmax, cr[q]);
+        rmax = wave_max(rmax);
+        int kp = 0;
+#pragma unroll
+        for (int q = SPL - 1; q >= 0; --q) {   // the lowest slot with a hit wins
+            const unsigned long long m = __ballot(act[q] && cr[q] == rmax);
+            if (m) kp = kWave * q + __builtin_ctzll(m);
+        }
+        K.probe = tmpl[sb + uniform_int(kp)];
+    }
+    // A second probe on the far side: the largest sphere (lowest index among
+    // equals) farther from the first probe than half the farthest sphere.
+    K.probe2 = K.probe;
+    K.two = false;
+    if (kProbe2 && S > 1) {
+        const float4 p = K.probe;
+        auto d1 = [&](int q) {
+            const float dx = cx[q] - p.x, dy = cy[q] - p.y, dz = cz[q] - p.z;
+            return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        };
+        float dfar = 0.f;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q)
+            if (act[q]) dfar = fmaxf(dfar, d1(q));
+        dfar = 0.5f * wave_max(dfar);
+        float r2 = -1.f;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q)
+            if (act[q] && d1(q) > dfar) r2 = fmaxf(r2, cr[q]);
+        r2 = wave_max(r2);
+        if (r2 >= 0.f) {
+            int kp = 0;
+#pragma unroll
+            for (int q = SPL - 1; q >= 0; --q) {
+                const unsigned long long m = __ballot(act[q] && d1(q) > dfar && cr[q] == r2);
+                if (m) kp = kWave * q + __builtin_ctzll(m);
+            }
+            K.probe2 = tmpl[sb + uniform_int(kp)];
+            K.two = true;
+        }
+    }
+    return K;
+}
+
+// Boxes (of the first 64) that some candidate of an object can reach: every
+// candidate's bounding centre lies, in the support frame, on the rectangle
+// grown by |bc_xy| at height bc_z + zc; a box whose bounding sphere stays
+// farther than reach from that set is skipped by the batch phase.
+__device__ __forceinline__ unsigned long long reachable_boxes(const ObjConsts& K, const Support& U,
+                                                              float reach,
+                                                              const float* __restrict__ box,
+                                                              int b0, int nbox_mask, int lane) {
+    const float ax = U.hx - U.inset, ay = U.hy - U.inset, zc = U.lift + K.lift;
+    const float gx = ax + sqrtf(fmaf(K.bc[0], K.bc[0], K.bc[1] * K.bc[1]));
+    const float gy = ay + sqrtf(fmaf(K.bc[0], K.bc[0], K.bc[1] * K.bc[1]));
+    const float hz = K.bc[2] + zc;
+    bool rel = false;
+    if (lane < nbox_mask) {
+        const float* B = box + 16 * (b0 + lane);
+        const float dx = B[9] - U.t[0], dy = B[10] - U.t[1], dz = B[11] - U.t[2];
+        const float sx = fmaf(U.R[0], dx, fmaf(U.R[3], dy, U.R[6] * dz));
+        const float sy = fmaf(U.R[1], dx, fmaf(U.R[4], dy, U.R[7] * dz));
+        const float sz = fmaf(U.R[2], dx, fmaf(U.R[5], dy, U.R[8] * dz));
+        const float ox = fmaxf(fabsf(sx) - gx, 0.f), oy = fmaxf(fabsf(sy) - gy, 0.f);
+        const float oz = sz - hz;
+        const float lim = sqrtf(fmaf(B[12], B[12], fmaf(B[13], B[13], B[14] * B[14]))) + reach;
+        // generous slack for the rounding of this test (it only prunes)
+        rel = fmaf(ox, ox, fmaf(oy, oy, oz * oz)) < lim * lim * 1.0001f + 1e-6f;
+    }
+    return __ballot(rel);
+}
+
 // kLds = true : the scene's placed spheres live in LDS (cap_sph of them);
 //               with `split`, scenes with more spheres are left to the
 //               other launch, otherwise they are a capacity error.
@@ -213,9 +337,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     extern __shared__ float4 lds[];
     float4* lsph = lds;                        // placed spheres: (x, y, z, r + margin)
     float4* lbnd = lds + (kLds ? cap_sph : 0); // world bounding sphere of each placed object
-    // scenes without grids: the depth map after the bounds (kMapBytes)
+    // per object to place: 4 constants (bounds, probes, lift and flags)
+    float4* linfo = lbnd + cap_obj;
+    // scenes without grids: the depth map after them (kMapBytes)
     constexpr bool kMap = !kGrids;
-    int8_t* lmap = reinterpret_cast<int8_t*>(lbnd + cap_obj);
+    int8_t* lmap = reinterpret_cast<int8_t*>(linfo + 4 * cap_obj);
     __shared__ int s_best;
     // the pose of the entry each wave found valid (a wave finds at most one
     // per object): x, y, z, c, s, yaw, attempt, index
@@ -337,8 +463,28 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     int last = -2;
     const int b0 = box_off[s], b1 = box_off[s + 1];
     const int nbox_mask = min(b1 - b0, kWave);   // boxes covered by the batch masks
+    // Constants of every object this launch may place, once per scene with the
+    // objects spread over the waves; the loads and reductions of different
+    // objects overlap here instead of stalling each object's start.
+    // A second probe is not used in grid batches: their placements rarely
+    // collide, and its registers would cost occupancy.
+    for (int jj = j + wave; jj < j_end; jj += W) {
+        const int o = o0 + jj, sb = sph_off[o];
+        const ObjConsts K = object_consts<SPL, !kGrids>(tmpl, sb, sph_off[o + 1] - sb, lane);
+        const Support U = load_support(sup, obj_sup[o]);
+        const unsigned long long rel = reachable_boxes(K, U, K.rho + margin, box, b0, nbox_mask, lane);
+        if (lane == 0) {
+            float4* I = linfo + 4 * jj;
+            I[0] = make_float4(K.bc[0], K.bc[1], K.bc[2], K.rho);
+            I[1] = K.probe;
+            I[2] = K.probe2;
+            I[3] = make_float4(K.lift, __int_as_float(K.two ? 1 : 0), __int_as_float((int)(unsigned)rel),
+                               __int_as_float((int)(unsigned)(rel >> 32)));
+        }
+    }
     // the scene's boxes all turn about z only (then, with a support that does
-    // too, the entry loop runs its planar form)
+    // too, the entry loop runs its planar form); the barrier also publishes
+    // the object constants
     int tilted = 0;
     for (int bi = b0 + (int)threadIdx.x; bi < b1; bi += blockDim.x) tilted |= !yaw_box(box + 16 * bi);
     const bool boxes_yaw = !__syncthreads_or(tilted);
@@ -352,7 +498,6 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         const int nq = (S + kWave - 1) / kWave;   // sphere slots per lane this object uses
         float cx[SPL], cy[SPL], cz[SPL], cr[SPL], rm2[SPL];
         bool act[SPL];
-        float lift = -1e30f, lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
 #pragma unroll
         for (int q = 0; q < SPL; ++q) {
             const int k = lane + kWave * q;
@@ -363,79 +508,21 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             const float4 c = act[q] ? tmpl[sb + k] : make_float4(0.f, 0.f, 1e18f, 0.f);
             cx[q] = c.x; cy[q] = c.y; cz[q] = c.z; cr[q] = c.w;
             rm2[q] = act[q] ? (c.w + margin) * (c.w + margin) : 0.f;
-            if (act[q]) {
-                lift = fmaxf(lift, c.w - c.z);
-                lo[0] = fminf(lo[0], c.x - c.w); hi[0] = fmaxf(hi[0], c.x + c.w);
-                lo[1] = fminf(lo[1], c.y - c.w); hi[1] = fmaxf(hi[1], c.y + c.w);
-                lo[2] = fminf(lo[2], c.z - c.w); hi[2] = fmaxf(hi[2], c.z + c.w);
-            }
         }
-        lift = wave_max(lift);
-        float bc[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) bc[d] = 0.5f * (wave_min(lo[d]) + wave_max(hi[d]));
-        float rho = 0.f;
-#pragma unroll
-        for (int q = 0; q < SPL; ++q) {
-            if (act[q]) {
-                const float dx = cx[q] - bc[0], dy = cy[q] - bc[1], dz = cz[q] - bc[2];
-                rho = fmaxf(rho, sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) + cr[q]);
-            }
-        }
-        rho = wave_max(rho) * (1.0f + 1e-6f) + 1e-6f;
+        // the object's constants, computed in the prologue
+        const float4* I = linfo + 4 * j;
+        const float4 I0 = I[0], I1 = I[1], I2 = I[2], I3 = I[3];
+        const float bc[3] = {uniform_f(I0.x), uniform_f(I0.y), uniform_f(I0.z)};
+        const float rho = uniform_f(I0.w);
         const float reach = rho + margin;
-        // Probe: the object's largest sphere (the lowest index among equals).
-        // A candidate whose probe already comes within the margin of a box or
-        // a grid collides, and the batch phase settles that for 64 candidates
-        // at once with the same arithmetic as the full test of that sphere.
-        float4 probe = make_float4(0.f, 0.f, 1e18f, 0.f);
-        if (S > 0) {
-            float rmax = -1.f;
-#pragma unroll
-            for (int q = 0; q < SPL; ++q)
-                if (act[q]) rmax = fmaxf(rmax, cr[q]);
-            rmax = wave_max(rmax);
-            int kp = 0;
-#pragma unroll
-            for (int q = SPL - 1; q >= 0; --q) {   // the lowest slot with a hit wins
-                const unsigned long long m = __ballot(act[q] && cr[q] == rmax);
-                if (m) kp = kWave * q + __builtin_ctzll(m);
-            }
-            probe = tmpl[sb + uniform_int(kp)];
-        }
+        const float4 probe = make_float4(uniform_f(I1.x), uniform_f(I1.y), uniform_f(I1.z), uniform_f(I1.w));
+        const float4 probe2 = make_float4(uniform_f(I2.x), uniform_f(I2.y), uniform_f(I2.z), uniform_f(I2.w));
+        const float lift = uniform_f(I3.x);
+        const bool two = uniform_int(__float_as_int(I3.y)) != 0;
+        const unsigned long long box_rel =
+            ((unsigned long long)(unsigned)uniform_int(__float_as_int(I3.w)) << 32) |
+            (unsigned)uniform_int(__float_as_int(I3.z));
         const float prm2 = (probe.w + margin) * (probe.w + margin);
-        // A second probe on the far side: the largest sphere (lowest index among
-        // equals) farther from the first probe than half the farthest sphere.
-        // Not in grid batches: their placements rarely collide, and the extra
-        // registers would cost occupancy.
-        float4 probe2 = probe;
-        bool two = false;
-        if (!kGrids && S > 1) {
-            auto d1 = [&](int q) {
-                const float dx = cx[q] - probe.x, dy = cy[q] - probe.y, dz = cz[q] - probe.z;
-                return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-            };
-            float dfar = 0.f;
-#pragma unroll
-            for (int q = 0; q < SPL; ++q)
-                if (act[q]) dfar = fmaxf(dfar, d1(q));
-            dfar = 0.5f * wave_max(dfar);
-            float r2 = -1.f;
-#pragma unroll
-            for (int q = 0; q < SPL; ++q)
-                if (act[q] && d1(q) > dfar) r2 = fmaxf(r2, cr[q]);
-            r2 = wave_max(r2);
-            if (r2 >= 0.f) {
-                int kp = 0;
-#pragma unroll
-                for (int q = SPL - 1; q >= 0; --q) {
-                    const unsigned long long m = __ballot(act[q] && d1(q) > dfar && cr[q] == r2);
-                    if (m) kp = kWave * q + __builtin_ctzll(m);
-                }
-                probe2 = tmpl[sb + uniform_int(kp)];
-                two = true;
-            }
-        }
         const float prm2b = (probe2.w + margin) * (probe2.w + margin);
 
         const Support U = load_support(sup, obj_sup[o]);
@@ -467,32 +554,6 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         const int g_lo = j == j_start ? min(resume0, total) : 0;
         const int g_hi = chunk > 0 ? min(total, max(g_lo, pk) + chunk) : total;
         const int nob_mask = min(j, kWave * kObjWords);     // objects covered by the masks
-        // Boxes (of the first 64) that some candidate of this object can reach:
-        // every candidate's bounding centre lies, in the support frame, on the
-        // rectangle grown by |bc_xy| at height bc_z + zc; a box whose
-        // bounding sphere stays farther than reach from that set is skipped
-        // by the batch phase.
-        unsigned long long box_rel;
-        {
-            const float gx = ax + sqrtf(fmaf(bc[0], bc[0], bc[1] * bc[1]));
-            const float gy = ay + sqrtf(fmaf(bc[0], bc[0], bc[1] * bc[1]));
-            const float hz = bc[2] + zc;
-            bool rel = false;
-            if (lane < nbox_mask) {
-                const float* B = box + 16 * (b0 + lane);
-                const float dx = B[9] - U.t[0], dy = B[10] - U.t[1], dz = B[11] - U.t[2];
-                const float sx = fmaf(U.R[0], dx, fmaf(U.R[3], dy, U.R[6] * dz));
-                const float sy = fmaf(U.R[1], dx, fmaf(U.R[4], dy, U.R[7] * dz));
-                const float sz = fmaf(U.R[2], dx, fmaf(U.R[5], dy, U.R[8] * dz));
-                const float ox = fmaxf(fabsf(sx) - gx, 0.f), oy = fmaxf(fabsf(sy) - gy, 0.f);
-                const float oz = sz - hz;
-                const float lim = sqrtf(fmaf(B[12], B[12], fmaf(B[13], B[13], B[14] * B[14]))) +
-                                  reach;
-                // generous slack for the rounding of this test (it only prunes)
-                rel = fmaf(ox, ox, fmaf(oy, oy, oz * oz)) < lim * lim * 1.0001f + 1e-6f;
-            }
-            box_rel = __ballot(rel);
-        }
 
         if (threadIdx.x == 0) s_best = INT_MAX;
         __syncthreads();
@@ -862,7 +923,7 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                   : place_kernel<SPL, kLds, true, false>())
                            : (yaw ? place_kernel<SPL, kLds, false, true>()
                                   : place_kernel<SPL, kLds, false, false>());
-    const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj) + (b.grid_off ? 0 : kMapBytes);
+    const int bytes = 16 * ((kLds ? cap_sph : 0) + kObjLds * plan.cap_obj) + (b.grid_off ? 0 : kMapBytes);
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
