@@ -20,8 +20,10 @@ struct U4 { uint32_t a, b, c, d; };
 __device__ __forceinline__ U4 philox10(U4 x, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * x.a, hi0 = __umulhi(0xD2511F53u, x.a);
-        const uint32_t lo1 = 0xCD9E8D57u * x.c, hi1 = __umulhi(0xCD9E8D57u, x.c);
+        // one 32 x 32 -> 64 product each (v_mad_u64_u32) for both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * x.a, p1 = (uint64_t)0xCD9E8D57u * x.c;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         x = U4{hi1 ^ x.b ^ k0, lo1, hi0 ^ x.d ^ k1, lo0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
