@@ -240,7 +240,8 @@ int scn_generate_scenes(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
 /* ---- uneven batching: autotuned schedules ------------------------------ */
 
 /* Schedule ids for scn_gen_args.schedule (0 = the context's tuned choice for
- * this batch shape, or the default):
+ * this batch shape, or the default 0xF04: 4 waves, batch order, placed
+ * spheres from global memory):
  *   bits 0-4  waves per workgroup: candidates of one scene in flight
  *             (1..16)
  *   bit  5    longest-first scene order (larger scenes start first)
@@ -256,8 +257,9 @@ enum {
     SCN_SCHED_LDS_NONE = 0xF
 };
 
-/* Time every schedule of the fused place kernel on this batch (a full
- * generation per schedule, after one warm-up run) and remember the fastest
+/* Time the schedules of the fused place kernel on this batch (coordinate
+ * descent over LDS budget, waves and scene order; per schedule the best of
+ * three full generations after one warm-up run) and remember the fastest
  * for batches of the same shape bucket (largest object, largest scene,
  * objects per scene, number of scenes) in the context.  Synchronizes
  * `stream`; leaves the batch state of the last run.  *best_schedule and

@@ -253,9 +253,10 @@ def test_invalid_arguments_are_rejected_before_launch(dev):
     with pytest.raises(scn.ScnError) as e:
         scn.generate_scenes(ctx, db, scn.GenArgs(retries=-2))
     assert e.value.code == -1
-    # a batch whose scenes need more spheres than the planned capacity
+    # a batch whose scenes need more spheres than the planned capacity (which
+    # binds when the placed spheres are LDS-resident: 8 waves, LDS budget 0)
     db.c.max_spheres_per_scene = 10
-    scn.generate_scenes(ctx, db, scn.GenArgs())
+    scn.generate_scenes(ctx, db, scn.GenArgs(schedule=8))
     with pytest.raises(scn.ScnError) as e:
         ctx.read_counters()
     assert e.value.code == -3
