@@ -463,6 +463,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
 
     unsigned long long n_cand = 0, n_pairs = 0, n_boxp = 0, n_att = 0, n_done = 0, n_xf = 0;
     unsigned long long n_boxc = 0, n_objc = 0, n_sphc = 0, n_grid = 0;
+    unsigned lane_boxp = 0;   // per-lane share of n_boxp
     int8_t fin = SCN_SCENE_ACTIVE;
     int last = -2;
     const int b0 = box_off[s], b1 = box_off[s + 1];
@@ -642,16 +643,20 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             }
             bool sure = false;  // the probe collides: the candidate is rejected
             unsigned long long bmask = 0, gmask = 0, omask[kObjWords] = {};
+            // boxes near the bounding sphere (box data uniform over the wave)
             for (unsigned long long rm = box_rel; rm; rm &= rm - 1) {
                 const int bi = __builtin_ctzll(rm);
                 const float* B = box + 16 * (b0 + bi);
-                const bool near = box_out2_t<kYaw>(B, lx, ly, lz) < reach * reach;
-                if (near) {
-                    bmask |= 1ull << bi;
-                    sure |= box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
-                    if (two) sure |= box_out2_t<kYaw>(B, ux, uy, uz) < prm2b;
-                }
-                n_boxp += (two ? 2u : 1u) * __popcll(__ballot(near && live));
+                bmask |= (unsigned long long)(box_out2_t<kYaw>(B, lx, ly, lz) < reach * reach) << bi;
+            }
+            // the probes against the lane's own near boxes: a candidate is
+            // near few boxes, so this per-lane loop runs far fewer rounds
+            // than testing the probes against every box some lane is near
+            lane_boxp += live ? (two ? 2u : 1u) * (unsigned)__popcll(bmask) : 0u;
+            for (unsigned long long rm = bmask; rm; rm &= rm - 1) {
+                const float* B = box + 16 * (b0 + __builtin_ctzll(rm));
+                sure |= box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
+                if (two) sure |= box_out2_t<kYaw>(B, ux, uy, uz) < prm2b;
             }
             // grids: only spheres whose centres lie inside a grid's node box
             // sample it (outside it reads +inf), so a bounding sphere that
@@ -884,6 +889,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         if (st == SCN_SCENE_VALID) atomicAdd(counters + kValidScenes, 1ull);
         if (st == SCN_SCENE_INVALID) atomicAdd(counters + kInvalidScenes, 1ull);
     }
+    // per-lane counts summed over the wave (every lane is active here)
+    for (int m = 32; m >= 1; m >>= 1) lane_boxp += __shfl_xor(lane_boxp, m, kWave);
+    n_boxp += lane_boxp;
     if (lane == 0) {
         atomicAdd(counters + kCandidates, n_cand);
         atomicAdd(counters + kSpherePairs, n_pairs);
