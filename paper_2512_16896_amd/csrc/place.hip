@@ -63,6 +63,10 @@ __device__ __forceinline__ Pose entry_pose(int g, int prop_k, const int32_t* __r
 }
 
 
+__device__ __forceinline__ float4 bcast4(const float4& v, int lane) {
+    return make_float4(bcast(v.x, lane), bcast(v.y, lane), bcast(v.z, lane), bcast(v.w, lane));
+}
+
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int lane) {
     const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
     const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
@@ -116,8 +120,10 @@ __device__ __forceinline__ bool map_geometry(float ax, float ay, DepthMap& m) {
     return false;
 }
 
-// Adds a sphere (support frame); the caller writes the voxels t of its cube
-// with t % parts == part.
+// Adds a sphere (support frame): the voxels whose centres lie within
+// r + kMapReach of its centre.  The caller writes the (i, j) columns c of the
+// covering cube with c % parts == part; each column visits only the z range
+// of that ball.
 __device__ __forceinline__ void map_insert(int8_t* __restrict__ M, const DepthMap& m, float cx,
                                            float cy, float cz, float r, int part, int parts) {
     if (!(fabsf(cx) < 1e4f && fabsf(cy) < 1e4f && fabsf(cz) < 1e4f && r >= 0.f && r < 1e3f)) return;
@@ -128,27 +134,37 @@ __device__ __forceinline__ void map_insert(int8_t* __restrict__ M, const DepthMa
     const int j1 = min((int)floorf((cy + e - m.y0) * m.inv_h), m.ny - 1);
     const int k0 = max((int)floorf((cz - e) * m.inv_h), 0);
     const int k1 = min((int)floorf((cz + e) * m.inv_h), m.nz - 1);
-    const int nxr = i1 - i0 + 1, nyr = j1 - j0 + 1, nzr = k1 - k0 + 1;
-    if (nxr <= 0 || nyr <= 0 || nzr <= 0) return;
+    const int nxr = i1 - i0 + 1, nyr = j1 - j0 + 1;
+    if (nxr <= 0 || nyr <= 0 || k1 < k0) return;
     static_assert(kMapBytes < 32768, "voxel indices of a cube must stay below 2^15");
-    const int nxy = nxr * nyr, total = nxy * nzr;
-    // t -> (i, j, k) by float reciprocals: with t < 2^15 the quotient of
-    // (t + 1/2) / n stays at least 1/(2n) from an integer, far beyond the
-    // rounding of the product, so the truncations are exact
-    // (indices stay below 2^15, so 24-bit multiplies are exact)
-    const float rx = 1.f / (float)nxr, rxy = 1.f / (float)nxy;
-    for (int t = part; t < total; t += parts) {
-        const int kk = (int)(((float)t + 0.5f) * rxy), rem = t - __mul24(kk, nxy);
-        const int jj = (int)(((float)rem + 0.5f) * rx);
-        const int i = i0 + (rem - __mul24(jj, nxr)), j = j0 + jj, k = k0 + kk;
+    // c -> (i, j) by a float reciprocal: with c < 2^15 the quotient of
+    // (c + 1/2) / nxr stays at least 1/(2 nxr) from an integer, far beyond
+    // the rounding of the product, so the truncation is exact (and indices
+    // below 2^15 make 24-bit multiplies exact)
+    const int ncol = nxr * nyr;
+    const float rx = 1.f / (float)nxr;
+    const float e2 = e * e;
+    for (int c = part; c < ncol; c += parts) {
+        const int jj = (int)(((float)c + 0.5f) * rx);
+        const int i = i0 + (c - __mul24(jj, nxr)), j = j0 + jj;
         const float dx = fmaf((float)i + 0.5f, m.h, m.x0) - cx;
         const float dy = fmaf((float)j + 0.5f, m.h, m.y0) - cy;
-        const float dz = ((float)k + 0.5f) * m.h - cz;
-        const float depth = r - __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        if (depth >= -kMapReach) {
-            const int q = min((int)floorf(depth * (1.f / kMapQ) - 1e-3f), 127);
-            int8_t* v = M + __mul24(__mul24(k, m.ny) + j, m.nx) + i;
-            if (q > (int)*v) *v = (int8_t)q;
+        const float dxy2 = fmaf(dx, dx, dy * dy);
+        if (dxy2 > e2) continue;
+        // voxel centres (k + 1/2) h within sqrt(e^2 - dxy2) of cz, widened by
+        // one voxel each way (the depth test below decides)
+        const float hz = __builtin_amdgcn_sqrtf(e2 - dxy2);
+        const int ka = max((int)floorf((cz - hz) * m.inv_h - 0.5f), k0);
+        const int kb = min((int)floorf((cz + hz) * m.inv_h - 0.5f) + 1, k1);
+        int8_t* col = M + __mul24(j, m.nx) + i;
+        for (int k = ka; k <= kb; ++k) {
+            const float dz = ((float)k + 0.5f) * m.h - cz;
+            const float depth = r - __builtin_amdgcn_sqrtf(fmaf(dz, dz, dxy2));
+            if (depth >= -kMapReach) {
+                const int q = min((int)floorf(depth * (1.f / kMapQ) - 1e-3f), 127);
+                int8_t* v = col + __mul24(k, __mul24(m.ny, m.nx));
+                if (q > (int)*v) *v = (int8_t)q;
+            }
         }
     }
 }
@@ -570,10 +586,12 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         auto test_object = [&](int ob, bool& hit) {
             const int a0 = sph_off[o0 + ob] - first, a1 = sph_off[o0 + ob + 1] - first;
             for (int c0 = a0; c0 < a1; c0 += kWave) {
-                // lane-parallel pretest of up to 64 placed spheres
+                // lane-parallel pretest of up to 64 placed spheres; the pair
+                // loop then takes each sphere from the lane that loaded it
                 bool rel = false;
+                float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (c0 + lane < a1) {
-                    const float4 q = placed_sphere(c0 + lane);
+                    q = placed_sphere(c0 + lane);
                     const float dx = q.x - Gx, dy = q.y - Gy, dz = q.z - Gz;
                     const float lim = rho + q.w;
                     rel = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim;
@@ -581,14 +599,15 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 unsigned long long rm = __ballot(rel);
                 n_sphc += (unsigned long long)min(kWave, a1 - c0);
                 while (rm) {
-                    const int k0 = c0 + __builtin_ctzll(rm);
+                    const int l0 = __builtin_ctzll(rm);
                     rm &= rm - 1;
-                    int k1 = k0;
+                    int l1 = l0;
                     if (rm) {
-                        k1 = c0 + __builtin_ctzll(rm);
+                        l1 = __builtin_ctzll(rm);
                         rm &= rm - 1;
                     }
-                    const float4 qa = placed_sphere(k0), qb = placed_sphere(k1);
+                    const int k0 = c0 + l0, k1 = c0 + l1;
+                    const float4 qa = bcast4(q, l0), qb = bcast4(q, l1);
                     float m = __builtin_huge_valf();
 #pragma unroll
                     for (int q = 0; q < SPL; ++q) {
