@@ -39,7 +39,7 @@ WORKLOADS = {
                               "(half extents U[0.05,0.5] m, random yaw); margin 5 mm; 10 retries",
                          make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                       fromlist=["x"]).batched_scenes(4096, seed=seed),
-                         ncand=1024, cpu_scenes=160, learned=True, dense=True, tune=True),
+                         ncand=1024, cpu_scenes=160, learned=True, dense=True),
     "table-1": dict(desc="1 scene; 1.2x0.8 m table; 8 objects x 32 spheres; 256 candidates; "
                          "4 cuboids; margin 5 mm; 10 retries",
                     make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
@@ -260,6 +260,8 @@ def main():
     if W.get("tune") and args.schedule == 0:
         progress("autotuning")
         tuned = ctx.autotune(db, scn.GenArgs(seed=999, default_ncand=W["ncand"]))
+    # the schedule the timed launches run
+    sched_run = tuned[0] if tuned else (args.schedule or scn.DEFAULT_SCHEDULE)
     progress("timing")
     for i in range(args.warmup):
         gen(-1 - i)
@@ -297,15 +299,14 @@ def main():
                    "objects": int(b.n_objects), "method": "plain (uniform candidates)"},
         "launch": "hipGraph replay" if graph else "direct",
         "schedule": (f"autotuned 0x{tuned[0]:x}" if tuned else
-                     (f"0x{args.schedule:x}" if args.schedule else "default")),
+                     (f"0x{args.schedule:x}" if args.schedule
+                      else f"default 0x{scn.DEFAULT_SCHEDULE:x}")),
         "valid_fraction": valid / (n * steps),
         "candidate_checks_per_s": cnt["candidates"] / wall,
         "counters_per_step": {k: v / steps for k, v in cnt.items() if k != "error_word"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": recorded_traffic(
-                         f"k_place {args.workload} "
-                         f"{'default' if args.schedule == 0 else hex(args.schedule)}"),
+                     "traffic": recorded_traffic(f"k_place {args.workload} 0x{sched_run:x}"),
                      "kernel": "k_place (fused place kernel)",
                      "kernel_ms": launch_ms},
     }

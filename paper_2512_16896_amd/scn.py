@@ -134,6 +134,9 @@ EXPORTS = ("scn_ctx_create", "scn_ctx_destroy", "scn_status_string", "scn_last_e
            "scn_generate_scenes_learned")
 
 SCHED_LONGEST_FIRST = 0x20
+# the library's schedule when none is given and none is tuned (scn.h):
+# 4 waves, batch order, placed spheres from global memory
+DEFAULT_SCHEDULE = 0xF04
 
 
 def lib():
