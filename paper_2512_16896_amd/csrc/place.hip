@@ -87,9 +87,10 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 // quantisation slack of an insert (1e-3 of a step) for distances under 4 m,
 // and far inside kMapSafety at any scale the map covers.
 constexpr float kMapQ = 5e-4f;         // depth step (m)
-constexpr float kMapReach = 0.02f;     // depths kept down to -2 cm
+constexpr float kMapReach = 0.04f;     // depths kept down to -4 cm (-80 steps)
 constexpr float kMapSafety = 1e-4f;    // a rejection keeps this far inside the margin
 constexpr int kMapNone = -128;
+static_assert(kMapReach / kMapQ + 2.f < 128.f, "quantised depths must stay above kMapNone");
 constexpr float kMapOver = 0.3f;       // mapped overhang beyond the support rectangle (m)
 constexpr float kMapTop = 0.5f;        // mapped height above the support plane (m)
 
