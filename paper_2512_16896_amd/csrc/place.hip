@@ -789,6 +789,34 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                             hit |= grid_sample(G, vals, wx[q], wy[q], wz[q]) < cr[q] + margin;
                     n_grid += S;
                 }
+                // Every sphere against the depth map: a hit there is a proven
+                // collision, found without the placed spheres' pair tests
+                // (support-frame coordinates R_u^T (w - t_u) of the world
+                // spheres; their rounding is far inside the map's safety).
+                // Objects of up to 64 spheres only: for 4 spheres per lane the
+                // lookups and the registers they hold cost more than the pair
+                // tests they save.
+                if (kMap && SPL == 1 && use_map && j > 0 && !__ballot(hit)) {
+                    const DepthMap dmq = map_params(&s_dm);
+#pragma unroll
+                    for (int q = 0; q < SPL; ++q) {
+                        if (!(q == 0 || q < nq) || !act[q]) continue;
+                        const float dx = wx[q] - U.t[0], dy = wy[q] - U.t[1];
+                        float sx, sy, sz;
+                        if constexpr (kYaw) {
+                            sx = fmaf(U.R[0], dx, U.R[3] * dy);
+                            sy = fmaf(U.R[1], dx, U.R[4] * dy);
+                            sz = cz[q] + zc;
+                        } else {
+                            const float dz = wz[q] - U.t[2];
+                            sx = fmaf(U.R[0], dx, fmaf(U.R[3], dy, U.R[6] * dz));
+                            sy = fmaf(U.R[1], dx, fmaf(U.R[4], dy, U.R[7] * dz));
+                            sz = fmaf(U.R[2], dx, fmaf(U.R[5], dy, U.R[8] * dz));
+                        }
+                        hit |= map_hit(lmap, dmq, sx, sy, sz, cr[q], margin);
+                    }
+                    n_sphc += S;
+                }
                 // placed objects of the masks, then any beyond them
                 if (!__ballot(hit)) {
 #pragma unroll
