@@ -663,59 +663,67 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             }
             bool sure = false;  // the probe collides: the candidate is rejected
             unsigned long long bmask = 0, gmask = 0, omask[kObjWords] = {};
-            // boxes near the bounding sphere (box data uniform over the wave)
-            for (unsigned long long rm = box_rel; rm; rm &= rm - 1) {
-                const int bi = __builtin_ctzll(rm);
-                const float* B = box + 16 * (b0 + bi);
-                bmask |= (unsigned long long)(box_out2_t<kYaw>(B, lx, ly, lz) < reach * reach) << bi;
-            }
-            // the probes against the lane's own near boxes: a candidate is
-            // near few boxes, so this per-lane loop runs far fewer rounds
-            // than testing the probes against every box some lane is near
-            lane_boxp += live ? (two ? 2u : 1u) * (unsigned)__popcll(bmask) : 0u;
-            for (unsigned long long rm = bmask; rm; rm &= rm - 1) {
-                const float* B = box + 16 * (b0 + __builtin_ctzll(rm));
-                sure |= box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
-                if (two) sure |= box_out2_t<kYaw>(B, ux, uy, uz) < prm2b;
-            }
-            // grids: only spheres whose centres lie inside a grid's node box
-            // sample it (outside it reads +inf), so a bounding sphere that
-            // misses the node box needs no sample
-            if constexpr (kGrids) for (int gi = 0; gi < ngrid_mask; ++gi) {
-                const float* G = grid + 24 * (g0 + gi);
-                const bool near = grid_box_d2(G, lx, ly, lz) <= rho * rho;
-                if (near) {
-                    gmask |= 1ull << gi;
-                    const float* vals = grid_val + grid_val_off[grid_src[g0 + gi]];
-                    if (!sure) sure = grid_sample(G, vals, qx, qy, qz) < probe.w + margin;
-                    if (two && !sure) sure = grid_sample(G, vals, ux, uy, uz) < probe2.w + margin;
-                }
-                n_grid += (two ? 2u : 1u) * __popcll(__ballot(near && live));
-            }
-            for (int ob = 0; ob < nob_mask; ++ob) {
-                const float4 bd = lbnd[ob];
-                const float dx = lx - bd.x, dy = ly - bd.y, dz = lz - bd.z;
-                const float lim = reach + bd.w;
-                if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) omask[ob >> 6] |= 1ull << (ob & 63);
-            }
-            // the probe against the depth map of the placed spheres
+            // the probes against the depth map of the placed spheres first:
+            // the cheapest rejection
             if (kMap && use_map && j > 0) {
                 const DepthMap dmq = map_params(&s_dm);
-                if (!sure)
-                    sure = map_hit(lmap, dmq, fmaf(L.c, probe.x, fmaf(-L.s, probe.y, L.x)),
-                                   fmaf(L.s, probe.x, fmaf(L.c, probe.y, L.y)), probe.z + zc,
-                                   probe.w, margin);
+                sure = map_hit(lmap, dmq, fmaf(L.c, probe.x, fmaf(-L.s, probe.y, L.x)),
+                               fmaf(L.s, probe.x, fmaf(L.c, probe.y, L.y)), probe.z + zc,
+                               probe.w, margin);
                 if (two && !sure)
                     sure = map_hit(lmap, dmq, fmaf(L.c, probe2.x, fmaf(-L.s, probe2.y, L.x)),
                                    fmaf(L.s, probe2.x, fmaf(L.c, probe2.y, L.y)), probe2.z + zc,
                                    probe2.w, margin);
                 n_sphc += (two ? 2u : 1u) * __popcll(__ballot(live));
             }
+            // The box, grid and object masks serve only candidates still
+            // open: a batch the map rejected entirely skips them.
+            const bool need = __ballot(live && !sure) != 0;
+            if (need) {
+                // boxes near the bounding sphere (box data uniform over the wave)
+                for (unsigned long long rm = box_rel; rm; rm &= rm - 1) {
+                    const int bi = __builtin_ctzll(rm);
+                    const float* B = box + 16 * (b0 + bi);
+                    bmask |= (unsigned long long)(box_out2_t<kYaw>(B, lx, ly, lz) < reach * reach) << bi;
+                }
+                // the probes against the lane's own near boxes: a candidate is
+                // near few boxes, so this per-lane loop runs far fewer rounds
+                // than testing the probes against every box some lane is near
+                const unsigned long long pm = sure ? 0ull : bmask;
+                lane_boxp += live ? (two ? 2u : 1u) * (unsigned)__popcll(pm) : 0u;
+                for (unsigned long long rm = pm; rm; rm &= rm - 1) {
+                    const float* B = box + 16 * (b0 + __builtin_ctzll(rm));
+                    sure |= box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
+                    if (two) sure |= box_out2_t<kYaw>(B, ux, uy, uz) < prm2b;
+                }
+                // grids: only spheres whose centres lie inside a grid's node box
+                // sample it (outside it reads +inf), so a bounding sphere that
+                // misses the node box needs no sample
+                if constexpr (kGrids) for (int gi = 0; gi < ngrid_mask; ++gi) {
+                    const float* G = grid + 24 * (g0 + gi);
+                    const bool near = grid_box_d2(G, lx, ly, lz) <= rho * rho;
+                    if (near) {
+                        gmask |= 1ull << gi;
+                        const float* vals = grid_val + grid_val_off[grid_src[g0 + gi]];
+                        if (!sure) sure = grid_sample(G, vals, qx, qy, qz) < probe.w + margin;
+                        if (two && !sure) sure = grid_sample(G, vals, ux, uy, uz) < probe2.w + margin;
+                    }
+                    n_grid += (two ? 2u : 1u) * __popcll(__ballot(near && live));
+                }
+                for (int ob = 0; ob < nob_mask; ++ob) {
+                    const float4 bd = lbnd[ob];
+                    const float dx = lx - bd.x, dy = ly - bd.y, dz = lz - bd.z;
+                    const float lim = reach + bd.w;
+                    if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) omask[ob >> 6] |= 1ull << (ob & 63);
+                }
+            }
             const unsigned long long sure_mask = __ballot(sure && live);
             {
                 const unsigned long long nlive = __popcll(__ballot(live));
-                n_boxc += nlive * (unsigned long long)(__popcll(box_rel) + ngrid_mask);
-                n_objc += nlive * (unsigned long long)nob_mask;
+                if (need) {
+                    n_boxc += nlive * (unsigned long long)(__popcll(box_rel) + ngrid_mask);
+                    n_objc += nlive * (unsigned long long)nob_mask;
+                }
                 n_xf += (two ? 2u : 1u) * nlive;   // probe transforms
             }
             // ---- candidate phase: the entries the batch phase left open, in
