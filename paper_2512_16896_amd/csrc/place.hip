@@ -662,7 +662,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 to_world(U, L, probe2.x, probe2.y, probe2.z, ux, uy, uz);
             }
             bool sure = false;  // the probe collides: the candidate is rejected
-            unsigned long long bmask = 0, gmask = 0, omask[kObjWords] = {};
+            unsigned long long bmask = 0, gmask = 0;
             // the probes against the depth map of the placed spheres first:
             // the cheapest rejection
             if (kMap && use_map && j > 0) {
@@ -710,20 +710,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                     }
                     n_grid += (two ? 2u : 1u) * __popcll(__ballot(near && live));
                 }
-                for (int ob = 0; ob < nob_mask; ++ob) {
-                    const float4 bd = lbnd[ob];
-                    const float dx = lx - bd.x, dy = ly - bd.y, dz = lz - bd.z;
-                    const float lim = reach + bd.w;
-                    if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim) omask[ob >> 6] |= 1ull << (ob & 63);
-                }
             }
             const unsigned long long sure_mask = __ballot(sure && live);
             {
                 const unsigned long long nlive = __popcll(__ballot(live));
-                if (need) {
-                    n_boxc += nlive * (unsigned long long)(__popcll(box_rel) + ngrid_mask);
-                    n_objc += nlive * (unsigned long long)nob_mask;
-                }
+                if (need) n_boxc += nlive * (unsigned long long)(__popcll(box_rel) + ngrid_mask);
                 n_xf += (two ? 2u : 1u) * nlive;   // probe transforms
             }
             // ---- candidate phase: the entries the batch phase left open, in
@@ -753,6 +744,23 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 }
                 Gx = bcast(lx, t); Gy = bcast(ly, t); Gz = bcast(lz, t);
                 unsigned long long bm = bcast64(bmask, t), gm = bcast64(gmask, t);
+                // placed objects whose bounding spheres come within reach of
+                // the candidate's bounding centre (lane = object), built only
+                // for candidates still open
+                unsigned long long omask[kObjWords];
+#pragma unroll
+                for (int w = 0; w < kObjWords; ++w) {
+                    const int ob = 64 * w + lane;
+                    bool onear = false;
+                    if (ob < nob_mask) {
+                        const float4 bd = lbnd[ob];
+                        const float dx = Gx - bd.x, dy = Gy - bd.y, dz = Gz - bd.z;
+                        const float lim = reach + bd.w;
+                        onear = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < lim * lim;
+                    }
+                    omask[w] = __ballot(onear);
+                }
+                n_objc += (unsigned)nob_mask;
                 n_xf += S;
 #pragma unroll
                 for (int q = 0; q < SPL; ++q) {
@@ -829,7 +837,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 if (!__ballot(hit)) {
 #pragma unroll
                     for (int w = 0; w < kObjWords; ++w) {
-                        unsigned long long om = bcast64(omask[w], t);
+                        unsigned long long om = omask[w];
                         while (om) {
                             const int ob = 64 * w + __builtin_ctzll(om);
                             om &= om - 1;
