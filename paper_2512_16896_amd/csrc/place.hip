@@ -9,16 +9,17 @@
 // the entries w, w+W, w+2W, ... in batches of 64:
 //
 //   batch phase (lane t <-> candidate t of the batch): the pose (Philox), the
-//     world centre of the object's bounding sphere, and two bit masks: the
-//     boxes and the placed objects whose bounding volumes come within the
-//     margin of that bounding sphere (1-Lipschitz distance bounds: every other
-//     box / object is farther than the margin from every sphere, exactly);
-//   candidate phase (one candidate at a time, the object's spheres across the
-//     lanes, SPL per lane): sphere tests against the boxes of its mask, then
-//     for each object of its mask a lane-parallel pretest of that object's
-//     placed spheres against the bounding sphere followed by exact tests of
-//     the spheres that pass.  The candidate is rejected at the first hit any
-//     lane reports (ballot).
+//     world centre of the object's bounding sphere, two probe spheres tested
+//     against a depth map of the placed spheres and against the boxes near
+//     the bounding sphere (a probe that collides rejects its candidate), and
+//     the bit mask of those near boxes (1-Lipschitz distance bounds: every
+//     other box is farther than the margin from every sphere, exactly);
+//   candidate phase (each candidate the batch phase left open, the object's
+//     spheres across the lanes, SPL per lane): sphere tests against the boxes
+//     of its mask, the depth map, and for each placed object whose bounding
+//     sphere comes within reach a lane-parallel pretest of its placed
+//     spheres followed by exact tests of the spheres that pass.  The
+//     candidate is rejected at the first hit any lane reports (ballot).
 //
 // A collision-free candidate lowers the scene's best entry (LDS atomicMin);
 // a wave stops once the best entry is below its next one, so every entry
@@ -352,8 +353,8 @@ __device__ __forceinline__ unsigned long long reachable_boxes(const ObjConsts& K
 
 template <int SPL, bool kLds, bool kGrids, bool kYaw>
 __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
-    // placed objects covered by the batch masks: 64 per word; the dense
-    // multi-shelf (grid) scenes carry 100 objects, so they get two words
+    // placed objects covered by a candidate's object mask: 64 per word; the
+    // dense multi-shelf (grid) scenes carry 100 objects, so they get two words
     constexpr int kObjWords = kGrids ? 2 : 1;
     extern __shared__ float4 lds[];
     float4* lsph = lds;                        // placed spheres: (x, y, z, r + margin)
@@ -676,8 +677,8 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                                    probe2.w, margin);
                 n_sphc += (two ? 2u : 1u) * __popcll(__ballot(live));
             }
-            // The box, grid and object masks serve only candidates still
-            // open: a batch the map rejected entirely skips them.
+            // The box and grid masks serve only candidates still open: a
+            // batch the map rejected entirely skips them.
             const bool need = __ballot(live && !sure) != 0;
             if (need) {
                 // boxes near the bounding sphere (box data uniform over the wave)
