@@ -310,6 +310,28 @@ def test_general_rotations_match_oracle_and_planar_form(dev, orc):
     assert same > 0.8 * b.n_scenes
 
 
+def test_packed_scenes_near_the_margin_match_oracle(dev, orc):
+    """Small supports packed with small objects: many chosen placements sit
+    within half a millimetre of the collision margin, and every entry before
+    each of them was rejected, most by the depth map (probes in the batch
+    phase, every sphere for open candidates).  The map only proves hits with
+    0.1 mm to spare; a false rejection near the margin would change the
+    chosen entry against the oracle.  Planar and general (tilted) forms."""
+    scn, ctx, torch = dev
+    b = sg.uniform_batch(64, 24, 16, 256, 2, 0.2, 0.15, seed=31, side=(0.03, 0.06),
+                         rad=(0.006, 0.02), box_half=(0.02, 0.1))
+    for batch in (b, tilted(b, rot_xy(0.35, -0.25))):
+        ref = orc.generate(batch, seed=77, default_ncand=256)
+        clear = np.asarray(ref["rec_clear"])[np.asarray(ref["rec_idx"]) >= 0]
+        assert np.sum(clear < MARGIN + 5e-4) >= 50       # the test reaches the margin
+        db = scn.DeviceBatch(batch)
+        scn.generate_scenes(ctx, db, scn.GenArgs(seed=77, default_ncand=256))
+        status, npl, rec_i, rec_f, placed = _device_results(db)
+        n_cmp, n_band = compare_generation(batch, ref, status, rec_i, rec_f)
+        assert n_cmp > 0.7 * batch.n_objects
+        audit_placements(batch, placed, npl)
+
+
 def test_false_yaw_declaration_marks_scenes_invalid(dev):
     """A batch that declares SCN_GEOM_YAW but holds tilted supports is not
     placed: its scenes are marked invalid and the error word says why."""
