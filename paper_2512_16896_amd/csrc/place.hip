@@ -159,14 +159,21 @@ __device__ __forceinline__ void map_insert(int8_t* __restrict__ M, const DepthMa
         const int ka = max((int)floorf((cz - hz) * m.inv_h - 0.5f), k0);
         const int kb = min((int)floorf((cz + hz) * m.inv_h - 0.5f) + 1, k1);
         int8_t* col = M + __mul24(j, m.nx) + i;
-        for (int k = ka; k <= kb; ++k) {
-            const float dz = ((float)k + 0.5f) * m.h - cz;
-            const float depth = r - __builtin_amdgcn_sqrtf(fmaf(dz, dz, dxy2));
-            if (depth >= -kMapReach) {
-                const int q = min((int)floorf(depth * (1.f / kMapQ) - 1e-3f), 127);
-                int8_t* v = col + __mul24(k, __mul24(m.ny, m.nx));
-                if (q > (int)*v) *v = (int8_t)q;
-            }
+        const int plane = __mul24(m.ny, m.nx);
+        // two z neighbours per step: both reads issue before either write
+        // (different planes, so they never alias)
+        for (int k = ka; k <= kb; k += 2) {
+            const bool has1 = k + 1 <= kb;
+            const float dz0 = ((float)k + 0.5f) * m.h - cz, dz1 = dz0 + m.h;
+            const float d0 = r - __builtin_amdgcn_sqrtf(fmaf(dz0, dz0, dxy2));
+            const float d1 = r - __builtin_amdgcn_sqrtf(fmaf(dz1, dz1, dxy2));
+            int8_t* v0 = col + __mul24(k, plane);
+            int8_t* v1 = has1 ? v0 + plane : v0;
+            const int o0 = *v0, o1 = *v1;
+            const int q0 = min((int)floorf(d0 * (1.f / kMapQ) - 1e-3f), 127);
+            const int q1 = min((int)floorf(d1 * (1.f / kMapQ) - 1e-3f), 127);
+            if (d0 >= -kMapReach && q0 > o0) *v0 = (int8_t)q0;
+            if (has1 && d1 >= -kMapReach && q1 > o1) *v1 = (int8_t)q1;
         }
     }
 }
