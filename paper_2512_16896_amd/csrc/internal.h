@@ -57,6 +57,8 @@ constexpr int kMapBytes = 24576;
 // float4 slots per object in the place kernel's LDS: its world bounding
 // sphere once placed, and 4 constants while it is to be placed
 constexpr int kObjLds = 5;
+// the place kernel's LDS copy of a scene's first 64 box rows (16 floats each)
+constexpr int kBoxLdsBytes = 64 * 16 * 4;
 
 // Where the fused place kernel keeps a scene's placed spheres.
 enum PlaceMode {

@@ -368,9 +368,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     float4* lbnd = lds + (kLds ? cap_sph : 0); // world bounding sphere of each placed object
     // per object to place: 4 constants (bounds, probes, lift and flags)
     float4* linfo = lbnd + cap_obj;
+    // the rows of the scene's first 64 boxes (kBoxLdsBytes)
+    float* lbox = reinterpret_cast<float*>(linfo + 4 * cap_obj);
     // scenes without grids: the depth map after them (kMapBytes)
     constexpr bool kMap = !kGrids;
-    int8_t* lmap = reinterpret_cast<int8_t*>(linfo + 4 * cap_obj);
+    int8_t* lmap = reinterpret_cast<int8_t*>(lbox) + kBoxLdsBytes;
     __shared__ int s_best;
     // the pose of the entry each wave found valid (a wave finds at most one
     // per object): x, y, z, c, s, yaw, attempt, index
@@ -493,6 +495,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     int last = -2;
     const int b0 = box_off[s], b1 = box_off[s + 1];
     const int nbox_mask = min(b1 - b0, kWave);   // boxes covered by the batch masks
+    // the first 64 box rows into LDS: the batch and candidate phases read
+    // them there (the barrier below publishes them)
+    for (int i = threadIdx.x; i < 16 * nbox_mask; i += blockDim.x) lbox[i] = box[16 * b0 + i];
     // Constants of every object this launch may place, once per scene with the
     // objects spread over the waves; the loads and reductions of different
     // objects overlap here instead of stalling each object's start.
@@ -691,7 +696,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 // boxes near the bounding sphere (box data uniform over the wave)
                 for (unsigned long long rm = box_rel; rm; rm &= rm - 1) {
                     const int bi = __builtin_ctzll(rm);
-                    const float* B = box + 16 * (b0 + bi);
+                    const float* B = lbox + 16 * bi;
                     bmask |= (unsigned long long)(box_out2_t<kYaw>(B, lx, ly, lz) < reach * reach) << bi;
                 }
                 // the probes against the lane's own near boxes: a candidate is
@@ -700,7 +705,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 const unsigned long long pm = sure ? 0ull : bmask;
                 lane_boxp += live ? (two ? 2u : 1u) * (unsigned)__popcll(pm) : 0u;
                 for (unsigned long long rm = pm; rm; rm &= rm - 1) {
-                    const float* B = box + 16 * (b0 + __builtin_ctzll(rm));
+                    const float* B = lbox + 16 * __builtin_ctzll(rm);
                     sure |= box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
                     if (two) sure |= box_out2_t<kYaw>(B, ux, uy, uz) < prm2b;
                 }
@@ -785,7 +790,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 while (bm) {
                     const int bi = __builtin_ctzll(bm);
                     bm &= bm - 1;
-                    const float* B = box + 16 * (b0 + bi);
+                    const float* B = lbox + 16 * bi;
 #pragma unroll
                     for (int q = 0; q < SPL; ++q)
                         if (q == 0 || q < nq) hit |= box_out2_t<kYaw>(B, wx[q], wy[q], wz[q]) < rm2[q];
@@ -1007,7 +1012,8 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                   : place_kernel<SPL, kLds, true, false>())
                            : (yaw ? place_kernel<SPL, kLds, false, true>()
                                   : place_kernel<SPL, kLds, false, false>());
-    const int bytes = 16 * ((kLds ? cap_sph : 0) + kObjLds * plan.cap_obj) + (b.grid_off ? 0 : kMapBytes);
+    const int bytes = 16 * ((kLds ? cap_sph : 0) + kObjLds * plan.cap_obj) + kBoxLdsBytes +
+                      (b.grid_off ? 0 : kMapBytes);
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
