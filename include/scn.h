@@ -374,7 +374,10 @@ int scn_harvest_labels(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state,
  * object and resumes the rest in the next launch, which gives the same
  * placements as one pass over the whole list.  The host waits on `stream`
  * after each step launch to read how many scenes still have work (one int),
- * so the call returns with the stream drained.                              */
+ * so the call returns with the stream drained.  args->schedule 0 selects
+ * 0xF02 here (2 waves, placed spheres from global memory), not the context's
+ * tuned or default plain schedule: step launches last as long as their
+ * slowest scene, and fewer waves per scene measured faster.                 */
 int scn_generate_scenes_learned(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
                                 const scn_mlp *net, int32_t top_k, scn_stream stream);
 

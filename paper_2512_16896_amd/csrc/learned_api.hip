@@ -99,6 +99,13 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     if (!b->placed || !b->n_placed || !b->status || !b->rec)
         return scn_fail(SCN_E_INVALID_ARG, "placed/n_placed/status/rec required");
     if (a->retries < 0) return scn_fail(SCN_E_INVALID_ARG, "retries must be >= 0");
+    // Schedule 0: 2 waves, batch order, placed spheres from global memory.
+    // Each step launch is as long as its slowest scene's proposals and
+    // fallback chunk; measured on batched-4096 this beat the plain default
+    // of 4 waves (34.2 vs 37.3 ms per generation) and 1, 3 or 8 waves.
+    scn_gen_args args = *a;
+    if (args.schedule == 0) args.schedule = 2 | (SCN_SCHED_LDS_NONE << SCN_SCHED_LDS_SHIFT);
+    a = &args;
     const hipStream_t st = (hipStream_t)stream;
     const int n = b->n_scenes;
     if (n == 0) return SCN_OK;
