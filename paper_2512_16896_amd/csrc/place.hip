@@ -704,10 +704,10 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 // than testing the probes against every box some lane is near
                 const unsigned long long pm = sure ? 0ull : bmask;
                 lane_boxp += live ? (two ? 2u : 1u) * (unsigned)__popcll(pm) : 0u;
-                for (unsigned long long rm = pm; rm; rm &= rm - 1) {
+                for (unsigned long long rm = pm; rm && !sure; rm &= rm - 1) {
                     const float* B = lbox + 16 * __builtin_ctzll(rm);
-                    sure |= box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
-                    if (two) sure |= box_out2_t<kYaw>(B, ux, uy, uz) < prm2b;
+                    sure = box_out2_t<kYaw>(B, qx, qy, qz) < prm2;
+                    if (two && !sure) sure = box_out2_t<kYaw>(B, ux, uy, uz) < prm2b;
                 }
                 // grids: only spheres whose centres lie inside a grid's node box
                 // sample it (outside it reads +inf), so a bounding sphere that
