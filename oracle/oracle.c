@@ -161,7 +161,8 @@ double orc_box_sdf(const double R[9], const double c[3], const double h[3], cons
 
 /* Trilinear interpolation of a node-centred voxel grid (value v[i,j,k] at
  * origin + h*(i,j,k)), queried at a point already in the grid frame.  Outside
- * the node box the grid returns +inf (nothing there).                        */
+ * the node box the grid returns +inf (nothing there).  Inside it, a sample
+ * that reads a non-finite node value is NaN (see clearance() below).        */
 double orc_grid_sample(const float *val, const int dims[3], const double origin[3], double h,
                        const double pg[3])
 {
@@ -182,18 +183,39 @@ double orc_grid_sample(const float *val, const int dims[3], const double origin[
                 double w = (dx ? f[0] : 1 - f[0]) * (dy ? f[1] : 1 - f[1]) * (dz ? f[2] : 1 - f[2]);
                 size_t idx = ((size_t)(i0[2] + dz) * dims[1] + (size_t)(i0[1] + dy)) * dims[0]
                              + (size_t)(i0[0] + dx);
+                if (!isfinite((double)val[idx])) return NAN;
                 acc += w * (double)val[idx];
             }
     return acc;
 }
 
+static int finite_n(const double *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
 /* Clearance of one placed sphere set against the obstacles of scene s:
  * min over its spheres of (signed distance to every box, grid and already
- * placed sphere) minus the sphere radius.  +inf with no obstacles.          */
+ * placed sphere) minus the sphere radius.  +inf with no obstacles.
+ *
+ * Non-finite input (the paper is silent; the project's reading): a candidate
+ * whose world spheres, or any box row, grid instance row, placed sphere or
+ * sampled grid node it is tested against, hold a NaN or an infinity has no
+ * clearance: the result is NaN, which no margin test accepts, so the
+ * candidate collides.                                                        */
 static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
                         const double *placed, int n_placed_sph)
 {
     double best = INFINITY;
+    if (!finite_n(sph, 4 * n_sph)) return NAN;
+    for (int bx = b->box_off[s]; bx < b->box_off[s + 1]; ++bx)
+        if (!finite_n(b->box + 16 * bx, 15)) return NAN;
+    if (b->grid_off)
+        for (int g = b->grid_off[s]; g < b->grid_off[s + 1]; ++g)
+            if (!finite_n(b->grid + 24 * g, 19)) return NAN;
+    if (!finite_n(placed, 4 * n_placed_sph)) return NAN;
     for (int k = 0; k < n_sph; ++k) {
         const double *p = sph + 4 * k;
         for (int bx = b->box_off[s]; bx < b->box_off[s + 1]; ++bx) {
@@ -210,6 +232,7 @@ static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
                     pg[r] = G[3 * r] * p[0] + G[3 * r + 1] * p[1] + G[3 * r + 2] * p[2] + G[9 + r];
                 int dims[3] = {(int)G[16], (int)G[17], (int)G[18]};
                 double v = orc_grid_sample(b->grid_val[b->grid_src[g]], dims, G + 12, G[15], pg) - p[3];
+                if (isnan(v)) return NAN;
                 if (v < best) best = v;
             }
         }
