@@ -23,9 +23,20 @@
  *     NULL = the null stream) unless the description says they synchronize.
  *   - Argument and shape errors are found on the host before any launch
  *     (SCN_E_INVALID_ARG).  Errors only the device can see (a scene larger than
- *     the capacity the call was planned for) are recorded in a device error word
- *     and returned by the next synchronizing call (scn_read_counters) as
- *     SCN_E_CAPACITY.
+ *     the capacity the call was planned for, non-finite input) are recorded in
+ *     a device error word and returned by the next synchronizing call
+ *     (scn_read_counters) as SCN_E_CAPACITY / SCN_E_NONFINITE.
+ *   - Non-finite input (NaN or an infinity; the paper is silent on it): a
+ *     candidate whose own spheres or pose, or any box row, grid instance row,
+ *     placed sphere or sampled grid node it is tested against, is not finite
+ *     collides; its clearance is NaN.  In the place calls every candidate of
+ *     the object then collides, so the object fails and its scene becomes
+ *     INVALID.  Each such decision is counted (scn_counters.nonfinite).
+ *   - Device scratch memory comes from a caller-owned workspace attached to
+ *     the context (scn_set_workspace; size from scn_workspace_bytes).  The
+ *     library allocates device memory only in scn_ctx_create (counters).
+ *     A call whose workspace is too small fails with SCN_E_INVALID_ARG
+ *     before any launch.
  *   - A context is used by one host thread at a time.
  *   - FP32 data; metres and radians.  All arrays are row-major.
  */
@@ -45,7 +56,8 @@ enum {
     SCN_E_HIP = -2,         /* a HIP runtime call failed; see scn_last_error()  */
     SCN_E_CAPACITY = -3,    /* a scene exceeded the planned on-chip capacity    */
     SCN_E_NO_DEVICE = -4,   /* no usable gfx950 device                          */
-    SCN_E_UNSUPPORTED = -5  /* a size outside what the kernels support          */
+    SCN_E_UNSUPPORTED = -5, /* a size or batch kind the call does not support   */
+    SCN_E_NONFINITE = -6    /* non-finite input was met (and treated as a collision) */
 };
 
 /* Scene status values (scn_batch.status). */
@@ -172,7 +184,9 @@ typedef struct {
     int64_t valid_scenes;  /* scenes that became VALID                             */
     int64_t invalid_scenes;/* scenes that became INVALID                           */
     int64_t sphere_culls;  /* bounding-sphere vs placed-sphere pretests            */
-    int64_t reserved[3];
+    int64_t nonfinite;     /* decisions forced by non-finite input: objects failed
+                            * by the place kernel, candidates by the dense check */
+    int64_t reserved[2];
 } scn_counters;
 
 /* ---- context ---------------------------------------------------------- */
@@ -184,6 +198,39 @@ int scn_ctx_create(scn_ctx **out, int device);
 int scn_ctx_destroy(scn_ctx *ctx);
 const char *scn_status_string(int status);
 const char *scn_last_error(void);
+
+/* ---- workspace --------------------------------------------------------- */
+
+/* What a workspace is sized for (scn_workspace_bytes `kind`):
+ *   SCN_WS_GENERATE          scn_generate_scenes / scn_place_step / scn_autotune:
+ *                            the longest-first scene order of batch b (0 bytes
+ *                            for schedules without SCN_SCHED_LONGEST_FIRST;
+ *                            the value returned covers them all)
+ *   SCN_WS_MLP_FORWARD       scn_mlp_forward of `rows` feature rows through net
+ *   SCN_WS_MLP_BACKWARD      scn_mlp_backward of `rows` rows
+ *   SCN_WS_MLP_TRAIN         scn_mlp_train_step of `rows` rows (backward plus the
+ *                            gradient buffers)
+ *   SCN_WS_GENERATE_LEARNED  scn_generate_scenes_learned of batch b with net and
+ *                            top_k proposals                                  */
+enum {
+    SCN_WS_GENERATE = 0,
+    SCN_WS_MLP_FORWARD = 1,
+    SCN_WS_MLP_BACKWARD = 2,
+    SCN_WS_MLP_TRAIN = 3,
+    SCN_WS_GENERATE_LEARNED = 4
+};
+typedef struct scn_mlp scn_mlp;
+
+/* *bytes (host) = device workspace bytes the call of `kind` needs; b, net,
+ * rows and top_k are read as the kind needs them (others may be NULL / 0).  */
+int scn_workspace_bytes(int kind, const struct scn_batch *b, const scn_mlp *net, int32_t rows,
+                        int32_t top_k, size_t *bytes);
+
+/* Attach a caller-owned device buffer of `bytes` bytes (256-byte aligned) as
+ * the context's workspace; NULL detaches.  The buffer must stay allocated
+ * while calls that use it are in flight; calls on one context share it, so
+ * they must not overlap.                                                   */
+int scn_set_workspace(scn_ctx *ctx, void *ptr, size_t bytes);
 
 /* Zero the device counters (asynchronous, graph-safe fill kernel).          */
 int scn_reset_counters(scn_ctx *ctx, scn_stream stream);
@@ -286,13 +333,13 @@ int scn_autotune_load(scn_ctx *ctx, const char *path);
  *   m_w, v_w, m_b, v_b  AdamW moments like w / b (only needed for training).
  * dims[0..3] must be multiples of 32 (K of the matrix-core GEMMs).          */
 #define SCN_MLP_LAYERS 4
-typedef struct {
+struct scn_mlp {
     int32_t dims[SCN_MLP_LAYERS + 1];
     float *w[SCN_MLP_LAYERS], *b[SCN_MLP_LAYERS];
     uint16_t *wb[SCN_MLP_LAYERS], *wt[SCN_MLP_LAYERS];
     float *m_w[SCN_MLP_LAYERS], *v_w[SCN_MLP_LAYERS], *m_b[SCN_MLP_LAYERS], *v_b[SCN_MLP_LAYERS];
     int64_t step; /* AdamW steps taken; advanced by scn_mlp_train_step (host field) */
-} scn_mlp;
+};
 
 typedef struct {
     float lr, beta1, beta2, eps, weight_decay;
@@ -302,12 +349,14 @@ typedef struct {
  * biases and moments, step = 0.                                              */
 int scn_mlp_init(scn_ctx *ctx, scn_mlp *net, uint64_t seed, scn_stream stream);
 
-/* logits[M][dims[4]] (FP32) of the BF16 feature rows x[M][dims[0]].  Uses a
- * context workspace for the activations (grown on first use of a larger M). */
+/* logits[M][dims[4]] (FP32) of the BF16 feature rows x[M][dims[0]].  The
+ * hidden activations live in the context's workspace
+ * (SCN_WS_MLP_FORWARD).                                                      */
 int scn_mlp_forward(scn_ctx *ctx, const scn_mlp *net, const uint16_t *x, int32_t M,
                     float *logits, scn_stream stream);
 
-/* Gradients of the mean binary cross-entropy over the labelled bins:
+/* Gradients of the mean binary cross-entropy over the labelled bins
+ * (workspace SCN_WS_MLP_BACKWARD):
  * label_bins[M][L] (int32, -1 = no label), label_tgt[M][L] (1 accepted, 0
  * rejected); loss = mean over labels of softplus(z) - t z with z the logit of
  * the labelled bin.  gw[l] [dims[l+1]][dims[l]], gb[l] [dims[l+1]] (FP32,
@@ -317,7 +366,9 @@ int scn_mlp_backward(scn_ctx *ctx, const scn_mlp *net, const uint16_t *x, int32_
                      float *const *gw, float *const *gb, float *loss, scn_stream stream);
 
 /* One AdamW step (decoupled weight decay, bias-corrected moments) on the
- * gradients of scn_mlp_backward; refreshes the BF16 copies; ++net->step.    */
+ * gradients of scn_mlp_backward; refreshes the BF16 copies; ++net->step.
+ * Weight decay applies to the weight matrices only, not to the biases.
+ * Workspace SCN_WS_MLP_TRAIN.                                               */
 int scn_mlp_train_step(scn_ctx *ctx, scn_mlp *net, const uint16_t *x, int32_t M,
                        const int32_t *label_bins, const float *label_tgt, int32_t L,
                        const scn_adamw *opt, float *loss, scn_stream stream);

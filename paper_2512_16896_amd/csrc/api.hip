@@ -30,15 +30,17 @@ int scn_check_ctx(scn_ctx* c) {
 }
 
 int scn_workspace(scn_ctx* c, size_t bytes, void** out) {
-    if (bytes > c->ws_bytes) {
-        if (c->ws) (void)hipFree(c->ws);
-        c->ws = nullptr;
-        c->ws_bytes = 0;
-        SCN_HIP(hipMalloc(&c->ws, bytes));
-        c->ws_bytes = bytes;
-    }
+    if (bytes > 0 && (!c->ws || bytes > c->ws_bytes))
+        return scn_fail(SCN_E_INVALID_ARG,
+                        "workspace of %zu bytes needed, %zu attached (scn_workspace_bytes, "
+                        "scn_set_workspace)", bytes, c->ws ? c->ws_bytes : (size_t)0);
     *out = c->ws;
     return SCN_OK;
+}
+
+size_t scn::ws_order_bytes(int n_scenes) {
+    return align256(sizeof(int32_t) * (size_t)(n_scenes > 0 ? n_scenes : 0)) +
+           align256(sizeof(int32_t) * (kOrderBuckets + 1));
 }
 
 namespace {
@@ -81,6 +83,7 @@ const char* scn_status_string(int status) {
         case SCN_E_CAPACITY: return "scene exceeds the planned capacity";
         case SCN_E_NO_DEVICE: return "no usable gfx950 device";
         case SCN_E_UNSUPPORTED: return "unsupported size";
+        case SCN_E_NONFINITE: return "non-finite input (treated as a collision)";
         default: return "unknown status";
     }
 }
@@ -98,6 +101,10 @@ int scn_ctx_create(scn_ctx** out, int device) {
     SCN_HIP(hipSetDevice(device));
     auto* c = new scn_ctx();
     c->device = device;
+    if (hipHostMalloc((void**)&c->h_flag, 4 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(SCN_E_HIP, "hipHostMalloc(flags) failed");
+    }
     c->n_cu = p.multiProcessorCount;
     c->lds_per_block = (int)p.sharedMemPerBlock;
     int optin = 0;
@@ -105,12 +112,14 @@ int scn_ctx_create(scn_ctx** out, int device) {
         optin > c->lds_per_block)
         c->lds_per_block = optin;
     if (hipMalloc((void**)&c->d_counters, sizeof(int64_t) * scn::kNumCounters) != hipSuccess) {
+        (void)hipHostFree(c->h_flag);
         delete c;
         return fail(SCN_E_HIP, "hipMalloc(counters) failed");
     }
     if (hipMemset(c->d_counters, 0, sizeof(int64_t) * scn::kNumCounters) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(c->d_counters);
+        (void)hipHostFree(c->h_flag);
         delete c;
         return fail(SCN_E_HIP, "counter init failed");
     }
@@ -123,13 +132,55 @@ int scn_ctx_destroy(scn_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(c->d_counters);
-    if (c->d_order) (void)hipFree(c->d_order);
-    if (c->d_hist) (void)hipFree(c->d_hist);
-    if (c->ws) (void)hipFree(c->ws);
     if (c->h_flag) (void)hipHostFree(c->h_flag);
     for (auto& kv : c->plain_graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
+    return SCN_OK;
+}
+
+int scn_workspace_bytes(int kind, const scn_batch* b, const scn_mlp* net, int32_t rows,
+                        int32_t top_k, size_t* bytes) {
+    if (!bytes) return fail(SCN_E_INVALID_ARG, "null output pointer");
+    *bytes = 0;
+    auto need_net = [&]() -> int {
+        if (!net) return fail(SCN_E_INVALID_ARG, "network required for this workspace kind");
+        for (int l = 0; l <= SCN_MLP_LAYERS; ++l)
+            if (net->dims[l] <= 0) return fail(SCN_E_INVALID_ARG, "dims[%d] must be > 0", l);
+        return SCN_OK;
+    };
+    switch (kind) {
+        case SCN_WS_GENERATE:
+            if (!b || b->n_scenes < 0) return fail(SCN_E_INVALID_ARG, "batch required");
+            *bytes = scn::ws_order_bytes(b->n_scenes);
+            return SCN_OK;
+        case SCN_WS_MLP_FORWARD:
+        case SCN_WS_MLP_BACKWARD:
+        case SCN_WS_MLP_TRAIN:
+            if (int r = need_net()) return r;
+            if (rows < 0) return fail(SCN_E_INVALID_ARG, "rows must be >= 0");
+            *bytes = kind == SCN_WS_MLP_FORWARD    ? scn::ws_mlp_forward_bytes(net, rows)
+                     : kind == SCN_WS_MLP_BACKWARD ? scn::ws_mlp_backward_bytes(net, rows)
+                                                   : scn::ws_mlp_train_bytes(net, rows);
+            return SCN_OK;
+        case SCN_WS_GENERATE_LEARNED:
+            if (int r = need_net()) return r;
+            if (!b || b->n_scenes < 0 || b->n_objects < 0)
+                return fail(SCN_E_INVALID_ARG, "batch required");
+            if (top_k < 1 || top_k > SCN_BINS) return fail(SCN_E_INVALID_ARG, "top_k out of range");
+            *bytes = scn::ws_learned_bytes(b, net, top_k);
+            return SCN_OK;
+        default:
+            return fail(SCN_E_INVALID_ARG, "unknown workspace kind %d", kind);
+    }
+}
+
+int scn_set_workspace(scn_ctx* c, void* ptr, size_t bytes) {
+    if (!c) return fail(SCN_E_INVALID_ARG, "null context");
+    if (ptr && ((uintptr_t)ptr & 255u))
+        return fail(SCN_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    c->ws = ptr;
+    c->ws_bytes = ptr ? bytes : 0;
     return SCN_OK;
 }
 
@@ -159,11 +210,16 @@ int scn_read_counters(scn_ctx* c, scn_counters* out, scn_stream stream) {
     out->valid_scenes = h[scn::kValidScenes];
     out->invalid_scenes = h[scn::kInvalidScenes];
     out->sphere_culls = h[scn::kSphCulls];
+    out->nonfinite = h[scn::kNonFinite];
     if (out->error_word & scn::kErrCapacity)
         return fail(SCN_E_CAPACITY, "a scene exceeded the planned capacity and was skipped");
     if (out->error_word & scn::kErrGeometry)
         return fail(SCN_E_INVALID_ARG,
                     "a scene breaks the batch's declared SCN_GEOM_YAW geometry and was marked invalid");
+    if (out->error_word & scn::kErrNonFinite)
+        return fail(SCN_E_NONFINITE,
+                    "non-finite input: the candidates tested against it collided (%lld counted)",
+                    (long long)out->nonfinite);
     return SCN_OK;
 }
 
@@ -195,7 +251,7 @@ int scn_check_batch(scn_ctx* c, const scn_batch* b, const int32_t* obj_idx,
     if (!(margin >= 0.f)) return fail(SCN_E_INVALID_ARG, "margin must be >= 0");
     if ((int64_t)max_cand > 65535LL * 256) return fail(SCN_E_UNSUPPORTED, "max_cand too large");
     SCN_HIP(scn::launch_check(*b, obj_idx, cand_off, max_cand, poses, margin, clearance, collide,
-                              (hipStream_t)stream));
+                              c->d_counters, (hipStream_t)stream));
     return SCN_OK;
 }
 
@@ -230,7 +286,7 @@ static std::string shape_key(const scn_batch* b) {
 static const int kDefaultSchedule = 4 | (SCN_SCHED_LDS_NONE << SCN_SCHED_LDS_SHIFT);
 
 static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int max_steps,
-                      scn::PlacePlan* plan) {
+                      scn::PlacePlan* plan, void* order_ws = nullptr) {
     if (!a) return fail(SCN_E_INVALID_ARG, "null args");
     if (!(a->margin >= 0.f)) return fail(SCN_E_INVALID_ARG, "margin must be >= 0");
     if (a->retries < 0) return fail(SCN_E_INVALID_ARG, "retries must be >= 0");
@@ -250,17 +306,15 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
     if (w < 1 || w > 16) return fail(SCN_E_INVALID_ARG, "schedule waves must be 1..16");
     plan->waves = w;
     plan->order = nullptr;
+    plan->hist = nullptr;
     if (sched & SCN_SCHED_LONGEST_FIRST) {
-        if (c->order_cap < b->n_scenes) {
-            if (c->d_order) (void)hipFree(c->d_order);
-            c->d_order = nullptr;
-            c->order_cap = 0;
-            SCN_HIP(hipMalloc((void**)&c->d_order, sizeof(int32_t) * (size_t)b->n_scenes));
-            c->order_cap = b->n_scenes;
-        }
-        if (!c->d_hist)
-            SCN_HIP(hipMalloc((void**)&c->d_hist, sizeof(int32_t) * (scn::kOrderBuckets + 1)));
-        plan->order = c->d_order;
+        // the order and its histogram in the caller's workspace (order_ws:
+        // the learned generation passes its own region)
+        void* ws = order_ws;
+        if (!ws)
+            if (int r = scn_workspace(c, scn::ws_order_bytes(b->n_scenes), &ws)) return r;
+        plan->order = (int32_t*)ws;
+        plan->hist = (int32_t*)((char*)ws + scn::align256(sizeof(int32_t) * (size_t)b->n_scenes));
     }
     plan->cap_sph = b->max_spheres_per_scene > 0 ? b->max_spheres_per_scene : 1;
     plan->cap_obj = b->max_objects_per_scene > 0 ? b->max_objects_per_scene : 1;
@@ -297,7 +351,8 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
 static int run_place(scn_ctx* c, scn_batch* b, const scn_gen_args* a, const scn::PlacePlan& plan,
                      int32_t* chosen, bool reset, hipStream_t st) {
     if (reset) SCN_HIP(scn::launch_reset(*b, st));
-    if (plan.order) SCN_HIP(scn::launch_longest_first(*b, c->d_order, c->d_hist, st));
+    if (plan.order) SCN_HIP(scn::launch_longest_first(*b, plan.order, plan.hist, st));
+    SCN_HIP(scn::launch_scan_grid_values(*b, c->d_counters, st));
     SCN_HIP(scn::launch_place(*b, *a, plan, chosen, c->d_counters, st));
     return SCN_OK;
 }
@@ -316,10 +371,10 @@ int scn_place_step(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int32_t* cho
 __attribute__((visibility("hidden"))) int scn_place_internal(
     scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps, int32_t* chosen, bool reset,
     const int32_t* prop_bins, int prop_k, int32_t* resume, int chunk, int j_cap,
-    int32_t* n_active, hipStream_t st) {
+    int32_t* n_active, void* order_ws, hipStream_t st) {
     if (int r = check_batch(b, true)) return r;
     scn::PlacePlan plan;
-    if (int r = plan_place(c, b, a, max_steps, &plan)) return r;
+    if (int r = plan_place(c, b, a, max_steps, &plan, order_ws)) return r;
     plan.prop_bins = prop_bins;
     plan.prop_k = prop_bins ? prop_k : 0;
     plan.resume = resume;

@@ -166,7 +166,8 @@ __device__ __forceinline__ float box_out2_t(const float* B, float px, float py, 
 }
 
 // Grid instance row (24 floats): W[9] world->grid, tw[3], origin[3], h, nx, ny, nz, pad.
-// Trilinear sample of node values at a world point; +inf outside the nodes.
+// Trilinear sample of node values at a world point; +inf outside the nodes,
+// NaN inside when a node it reads is not finite (non-finite input collides).
 __device__ __forceinline__ float grid_sample(const float* G, const float* __restrict__ vals,
                                              float px, float py, float pz) {
     const float gx = fmaf(G[0], px, fmaf(G[1], py, fmaf(G[2], pz, G[9])));
@@ -188,7 +189,21 @@ __device__ __forceinline__ float grid_sample(const float* G, const float* __rest
     const float c11 = fmaf(tx, v[sz + sy + 1] - v[sz + sy], v[sz + sy]);
     const float c0 = fmaf(ty, c10 - c00, c00);
     const float c1 = fmaf(ty, c11 - c01, c01);
-    return fmaf(tz, c1 - c0, c0);
+    // a non-finite node makes the interpolant non-finite (no finite weight
+    // cancels an infinity or a NaN)
+    const float r = fmaf(tz, c1 - c0, c0);
+    return __builtin_isfinite(r) ? r : __builtin_nanf("");
+}
+
+// Every one of n floats is finite (not NaN, not an infinity).
+__device__ __forceinline__ bool all_finite(const float* p, int n) {
+    bool ok = true;
+    for (int i = 0; i < n; ++i) ok &= __builtin_isfinite(p[i]);
+    return ok;
+}
+__device__ __forceinline__ bool finite4(const float4& v) {
+    return __builtin_isfinite(v.x) & __builtin_isfinite(v.y) & __builtin_isfinite(v.z) &
+           __builtin_isfinite(v.w);
 }
 
 // Squared distance from a world point to a grid instance's node box (0 inside).

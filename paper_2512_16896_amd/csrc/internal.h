@@ -15,12 +15,9 @@ struct scn_ctx {
     int lds_per_block;
     int n_cu;
     int64_t* d_counters;   // scn::kNumCounters int64
-    int32_t* d_order;      // longest-first scene order workspace
-    int32_t* d_hist;       // its bucket counters
-    int order_cap;
-    void* ws;              // grow-only workspace arena (network activations, staging)
-    size_t ws_bytes;
-    int32_t* h_flag = nullptr;   // pinned host word for small device-to-host reads
+    void* ws = nullptr;    // caller-owned workspace (scn_set_workspace), never freed here
+    size_t ws_bytes = 0;
+    int32_t* h_flag = nullptr;   // pinned host words for small device-to-host reads
     hipStream_t cap_stream = nullptr;   // stream used only to capture graphs
     std::map<std::string, hipGraphExec_t> plain_graphs;   // generation graphs per batch + plan
     struct Tuned { int schedule; float ms; };
@@ -31,8 +28,25 @@ struct scn_ctx {
 // scn_last_error() and returns `code`.
 int scn_fail(int code, const char* fmt, ...);
 int scn_check_ctx(scn_ctx* c);
-// Context workspace of at least `bytes` (grown with hipMalloc when needed).
+// The caller-owned workspace when it holds at least `bytes`, else an
+// SCN_E_INVALID_ARG failure naming the sizes (nothing is allocated here).
 int scn_workspace(scn_ctx* c, size_t bytes, void** out);
+
+namespace scn {
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+// Workspace bytes of each kind of call (scn_workspace_bytes); the calls take
+// their buffers in the order these sizes are summed.
+size_t ws_order_bytes(int n_scenes);                       // longest-first order + histogram
+size_t ws_mlp_forward_bytes(const scn_mlp* n, int rows);   // hidden activations
+size_t ws_mlp_backward_bytes(const scn_mlp* n, int rows);
+size_t ws_mlp_train_bytes(const scn_mlp* n, int rows);     // backward + gradients
+size_t ws_learned_bytes(const scn_batch* b, const scn_mlp* n, int top_k);
+}  // namespace scn
+
+// Network forward with the hidden activations in `act_ws`
+// (ws_mlp_forward_bytes of it); used by the learned generation.
+int scn_mlp_forward_ws(const scn_mlp* n, const uint16_t* x, int M, float* logits, void* act_ws,
+                       hipStream_t st);
 
 #define SCN_HIP(call)                                                                      \
     do {                                                                                   \
@@ -47,9 +61,9 @@ namespace scn {
 enum CounterSlot {
     kCandidates = 0, kSpherePairs = 1, kBoxPairs = 2, kGridSamples = 3, kAttempts = 4,
     kPlaced = 5, kErrorWord = 6, kTransforms = 7, kBoxCulls = 8, kObjCulls = 9,
-    kValidScenes = 10, kInvalidScenes = 11, kSphCulls = 12, kNumCounters = 16
+    kValidScenes = 10, kInvalidScenes = 11, kSphCulls = 12, kNonFinite = 13, kNumCounters = 16
 };
-enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2 };
+enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2, kErrNonFinite = 4 };
 
 // Bytes of dynamic LDS the place kernel adds for a scene's depth map (batches
 // without grids).
@@ -68,7 +82,8 @@ enum PlaceMode {
 };
 
 struct PlacePlan {
-    const int32_t* order;  // scene launch order (nullptr: batch order)
+    int32_t* order;   // scene launch order (nullptr: batch order), in the workspace
+    int32_t* hist;    // its bucket counters (kOrderBuckets + 1), in the workspace
     int waves;        // waves per workgroup (candidates in flight per scene)
     int spl;          // template spheres per lane (1, 2 or 4)
     int mode;         // PlaceMode
@@ -103,7 +118,8 @@ hipError_t launch_features(int n, const float* hmap, const float* desc, const in
 hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active, int32_t* bins,
                        hipStream_t st);
 hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,
-                          int round, float margin, int32_t* bins, float* accept, hipStream_t st);
+                          int round, float margin, int32_t* bins, float* accept,
+                          int64_t* counters, hipStream_t st);
 hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);   // kernels.hip
 
@@ -113,7 +129,9 @@ hipError_t launch_sample(const scn_batch& b, const int32_t* obj_idx, const int32
                          int max_cand, uint64_t seed, int attempt, scn_poses out, hipStream_t st);
 hipError_t launch_check(const scn_batch& b, const int32_t* obj_idx, const int32_t* cand_off,
                         int max_cand, scn_poses poses, float margin, float* clr, uint8_t* col,
-                        hipStream_t st);
+                        int64_t* counters, hipStream_t st);
+// Sets the non-finite error bit when any grid asset node value is not finite.
+hipError_t launch_scan_grid_values(const scn_batch& b, int64_t* counters, hipStream_t st);
 hipError_t launch_place(const scn_batch& b, const scn_gen_args& a, const PlacePlan& plan,
                         int32_t* chosen, int64_t* counters, hipStream_t st);
 // Longest-first scene order: a counting sort of the scenes by an estimate of

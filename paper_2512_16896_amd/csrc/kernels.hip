@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_check(
     const int32_t* __restrict__ obj_idx, const int32_t* __restrict__ cand_off,
     const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
     const float* __restrict__ pyaw, float margin, float* __restrict__ clr_out,
-    uint8_t* __restrict__ col_out) {
+    uint8_t* __restrict__ col_out, unsigned long long* __restrict__ counters) {
     const int s = blockIdx.x;
     const int o = obj_idx[s];
     if (o < obj_off[s] || o >= obj_off[s + 1]) return;   // -1 or not an object of scene s
@@ -119,10 +119,30 @@ __global__ __launch_bounds__(256) void k_check(
     const bool live = t < c1;
     const int tt = live ? t : c1 - 1;
 
+    const int oo = obj_off[s];
+    const int first = sph_off[oo];
+    const int pl_end = sph_off[oo + min(max(n_placed[s], 0), obj_off[s + 1] - oo)];
+    const int b0 = box_off[s], b1 = box_off[s + 1];
+    int g0 = 0, g1 = 0;
+    if (kGrids) { g0 = grid_off[s]; g1 = grid_off[s + 1]; }
+    // Non-finite input makes a candidate collide with a NaN clearance: the
+    // object's support row and spheres, the scene's box and grid rows and
+    // placed spheres (shared by the workgroup), the candidate's own pose, and
+    // any grid sample that reads a non-finite node.
+    int bad_in = threadIdx.x < 16 ? !__builtin_isfinite(sup[16 * obj_sup[o] + threadIdx.x]) : 0;
+    for (int k = sph_off[o] + threadIdx.x; k < sph_off[o + 1]; k += blockDim.x)
+        bad_in |= !finite4(tmpl[k]);
+    for (int bx = b0 + threadIdx.x; bx < b1; bx += blockDim.x) bad_in |= !all_finite(box + 16 * bx, 15);
+    for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) bad_in |= !all_finite(grid + 24 * g, 19);
+    for (int q = first + threadIdx.x; q < pl_end; q += blockDim.x) bad_in |= !finite4(placed[q]);
+    bool bad = __syncthreads_or(bad_in) != 0;
+
     const Support U = load_support(sup, obj_sup[o]);
     float sn, cs;
-    sincosf(pyaw[tt], &sn, &cs);
-    const float x = px[tt], y = py[tt], z = pz[tt];
+    const float x = px[tt], y = py[tt], z = pz[tt], yw = pyaw[tt];
+    bad |= !(__builtin_isfinite(x) & __builtin_isfinite(y) & __builtin_isfinite(z) &
+             __builtin_isfinite(yw));
+    sincosf(yw, &sn, &cs);
     // candidate -> world: Rw = R_u Rz(yaw), tw = R_u (x,y,z) + t_u
     float Rw[9], tw[3];
 #pragma unroll
@@ -132,13 +152,6 @@ __global__ __launch_bounds__(256) void k_check(
         Rw[3 * r + 2] = U.R[3 * r + 2];
         tw[r] = fmaf(U.R[3 * r + 0], x, fmaf(U.R[3 * r + 1], y, fmaf(U.R[3 * r + 2], z, U.t[r])));
     }
-    const int oo = obj_off[s];
-    const int first = sph_off[oo];
-    const int pl_end = sph_off[oo + min(max(n_placed[s], 0), obj_off[s + 1] - oo)];
-    const int b0 = box_off[s], b1 = box_off[s + 1];
-    int g0 = 0, g1 = 0;
-    if (kGrids) { g0 = grid_off[s]; g1 = grid_off[s + 1]; }
-
     float clr = __builtin_huge_valf();
     for (int k = sph_off[o]; k < sph_off[o + 1]; ++k) {
         const float4 c = tmpl[k];
@@ -150,7 +163,9 @@ __global__ __launch_bounds__(256) void k_check(
         if (kGrids) {
             for (int g = g0; g < g1; ++g) {
                 const float* G = grid + 24 * g;
-                best = fminf(best, grid_sample(G, grid_val + grid_val_off[grid_src[g]], wx, wy, wz));
+                const float v = grid_sample(G, grid_val + grid_val_off[grid_src[g]], wx, wy, wz);
+                bad |= v != v;
+                best = fminf(best, v);
             }
         }
         int j = first;
@@ -171,28 +186,60 @@ __global__ __launch_bounds__(256) void k_check(
         }
         clr = fminf(clr, best - c.w);
     }
+    if (bad) clr = __builtin_nanf("");
     if (live) {
         if (clr_out) clr_out[t] = clr;
-        if (col_out) col_out[t] = clr < margin ? 1 : 0;
+        if (col_out) col_out[t] = clr >= margin ? 0 : 1;
     }
+    const unsigned long long nbad = __ballot(bad && live);
+    if (nbad && (threadIdx.x & (kWave - 1)) == 0) {
+        atomicOr(counters + kErrorWord, (unsigned long long)kErrNonFinite);
+        atomicAdd(counters + kNonFinite, (unsigned long long)__popcll(nbad));
+    }
+}
+
+// Any non-finite node value in the grid assets sets the non-finite error bit
+// (the samples that read it collide).
+__global__ __launch_bounds__(256) void k_scan_grid_values(const int64_t* __restrict__ off,
+                                                          int n_assets,
+                                                          const float* __restrict__ vals,
+                                                          unsigned long long* __restrict__ counters) {
+    const int64_t n = off[n_assets];
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !__builtin_isfinite(vals[i]);
+    if (__ballot(bad) && (threadIdx.x & (kWave - 1)) == 0)
+        atomicOr(counters + kErrorWord, (unsigned long long)kErrNonFinite);
+}
+
+hipError_t launch_scan_grid_values(const scn_batch& b, int64_t* counters, hipStream_t st) {
+    if (!b.grid_off || b.n_grid_assets <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_grid_values, dim3(256), dim3(256), 0, st, b.grid_val_off,
+                       b.n_grid_assets, b.grid_val, (unsigned long long*)counters);
+    return hipGetLastError();
 }
 
 hipError_t launch_check(const scn_batch& b, const int32_t* obj_idx, const int32_t* cand_off,
                         int max_cand, scn_poses P, float margin, float* clr, uint8_t* col,
-                        hipStream_t st) {
+                        int64_t* counters, hipStream_t st) {
     if (b.n_scenes == 0 || max_cand == 0) return hipSuccess;
     dim3 grid(b.n_scenes, (max_cand + 255) / 256);
+    auto* ctr = (unsigned long long*)counters;
     if (b.grid_off) {
+        hipError_t e = launch_scan_grid_values(b, counters, st);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_check<true>, grid, dim3(256), 0, st, b.obj_off, b.sph_off,
                            (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box, b.grid_off,
                            b.grid, b.grid_src, b.grid_val_off, b.grid_val,
                            (const float4*)b.placed, b.n_placed, obj_idx, cand_off, P.x, P.y, P.z,
-                           P.yaw, margin, clr, col);
+                           P.yaw, margin, clr, col, ctr);
     } else {
         hipLaunchKernelGGL(k_check<false>, grid, dim3(256), 0, st, b.obj_off, b.sph_off,
                            (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box, nullptr,
                            nullptr, nullptr, nullptr, nullptr, (const float4*)b.placed,
-                           b.n_placed, obj_idx, cand_off, P.x, P.y, P.z, P.yaw, margin, clr, col);
+                           b.n_placed, obj_idx, cand_off, P.x, P.y, P.z, P.yaw, margin, clr, col,
+                           ctr);
     }
     return hipGetLastError();
 }

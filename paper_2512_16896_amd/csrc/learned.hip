@@ -486,14 +486,17 @@ hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active,
 // (i, 0x20000 | round, step, s)) are checked exactly against the scene's boxes
 // and its first n_placed[s] objects; bins[s][i] receives the pose bin and
 // accept[s][i] 1 (collision-free) or 0.  Lane per candidate, wave-uniform
-// obstacles (like the dense checker).
+// obstacles (like the dense checker).  Non-finite input (the object's spheres
+// or support row, a box row or placed sphere of the state) makes every label
+// of the state a rejection and sets the non-finite error bit.
 __global__ __launch_bounds__(64) void k_harvest(
     const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
     const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
     const float* __restrict__ sup, const int32_t* __restrict__ box_off,
     const float* __restrict__ box, const float4* __restrict__ placed,
     const int32_t* __restrict__ n_state, int L, uint64_t seed, int round, float margin,
-    int32_t* __restrict__ bins_out, float* __restrict__ accept_out) {
+    int32_t* __restrict__ bins_out, float* __restrict__ accept_out,
+    unsigned long long* __restrict__ counters) {
     const int s = blockIdx.x;
     const int i = blockIdx.y * 64 + threadIdx.x;
     const int o = obj_off[s] + max(n_state[s], 0);   // the next object of the state
@@ -519,6 +522,12 @@ __global__ __launch_bounds__(64) void k_harvest(
                     min((int)(u2 * 8.f), 7);
     const int first = sph_off[obj_off[s]];
     const int pl_end = sph_off[o];   // the state's placed objects precede o
+    bool bad = threadIdx.x < 16 ? !__builtin_isfinite(sup[16 * obj_sup[o] + threadIdx.x]) : false;
+    for (int k = sph_off[o] + threadIdx.x; k < sph_off[o + 1]; k += kWave) bad |= !finite4(tmpl[k]);
+    for (int bx = box_off[s] + threadIdx.x; bx < box_off[s + 1]; bx += kWave)
+        bad |= !all_finite(box + 16 * bx, 15);
+    for (int q = first + threadIdx.x; q < pl_end; q += kWave) bad |= !finite4(placed[q]);
+    bad = __ballot(bad) != 0;
     float clr = __builtin_huge_valf();
     for (int k = sph_off[o]; k < sph_off[o + 1]; ++k) {
         const float4 c = tmpl[k];
@@ -536,16 +545,19 @@ __global__ __launch_bounds__(64) void k_harvest(
     }
     if (i < L) {
         bins_out[(size_t)s * L + i] = bin;
-        accept_out[(size_t)s * L + i] = clr >= margin ? 1.f : 0.f;
+        accept_out[(size_t)s * L + i] = !bad && clr >= margin ? 1.f : 0.f;
     }
+    if (bad && threadIdx.x == 0) atomicOr(counters + kErrorWord, (unsigned long long)kErrNonFinite);
 }
 
 hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,
-                          int round, float margin, int32_t* bins, float* accept, hipStream_t st) {
+                          int round, float margin, int32_t* bins, float* accept,
+                          int64_t* counters, hipStream_t st) {
     if (b.n_scenes == 0 || L <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_harvest, dim3(b.n_scenes, (L + 63) / 64), dim3(64), 0, st, b.obj_off,
                        b.sph_off, (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box,
-                       (const float4*)b.placed, n_state, L, seed, round, margin, bins, accept);
+                       (const float4*)b.placed, n_state, L, seed, round, margin, bins, accept,
+                       (unsigned long long*)counters);
     return hipGetLastError();
 }
 

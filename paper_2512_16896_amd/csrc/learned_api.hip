@@ -5,9 +5,23 @@
 #include "internal.h"
 #include "scn.h"
 
+using scn::align256;
+
 namespace {
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+// The learned proposal's state features hold one height map over the support
+// of each scene's first object, and its label harvest tests boxes and placed
+// spheres only: batches with voxel grids, or more supports than scenes (some
+// scene's objects on several supports), are outside what it computes.
+int check_single_support(const scn_batch* b) {
+    if (b->grid_off)
+        return scn_fail(SCN_E_UNSUPPORTED, "the learned proposal does not support voxel-grid batches");
+    if (b->n_supports > b->n_scenes)
+        return scn_fail(SCN_E_UNSUPPORTED,
+                        "the learned proposal needs one support per scene (%d supports, %d scenes)",
+                        b->n_supports, b->n_scenes);
+    return SCN_OK;
+}
 
 int check_scenes(const scn_batch* b) {
     if (!b) return scn_fail(SCN_E_INVALID_ARG, "null batch");
@@ -70,6 +84,7 @@ int scn_harvest_labels(scn_ctx* c, const scn_batch* b, const int32_t* n_state, i
                        scn_stream stream) {
     if (int r = scn_check_ctx(c)) return r;
     if (int r = check_scenes(b)) return r;
+    if (int r = check_single_support(b)) return r;
     if (L <= 0 || round < 0 || round > 0xFFFF || !(margin >= 0.f))
         return scn_fail(SCN_E_INVALID_ARG, "bad L, round or margin");
     if (b->n_scenes == 0) return SCN_OK;
@@ -77,7 +92,8 @@ int scn_harvest_labels(scn_ctx* c, const scn_batch* b, const int32_t* n_state, i
     if (!ns || !b->placed || !bins || !accept)
         return scn_fail(SCN_E_INVALID_ARG, "n_state (or n_placed), placed, bins and accept required");
     if (L > 65535 * 64) return scn_fail(SCN_E_UNSUPPORTED, "L too large");
-    SCN_HIP(scn::launch_harvest(*b, ns, L, seed, round, margin, bins, accept, (hipStream_t)stream));
+    SCN_HIP(scn::launch_harvest(*b, ns, L, seed, round, margin, bins, accept, c->d_counters,
+                                (hipStream_t)stream));
     return SCN_OK;
 }
 
@@ -85,7 +101,55 @@ int scn_harvest_labels(scn_ctx* c, const scn_batch* b, const int32_t* n_state, i
 __attribute__((visibility("hidden"))) int scn_place_internal(
     scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps, int32_t* chosen, bool reset,
     const int32_t* prop_bins, int prop_k, int32_t* resume, int chunk, int j_cap,
-    int32_t* n_active, hipStream_t st);
+    int32_t* n_active, void* order_ws, hipStream_t st);
+
+}  // extern "C"
+
+// Layout of the learned generation's workspace: the scene order region, the
+// network's hidden activations, then the pipeline buffers below.
+namespace {
+struct LearnedWs {
+    void* order;
+    void* act;
+    float* hmap;
+    float* desc;
+    uint16_t* x;
+    float* logits;
+    int32_t* bins;
+    int32_t *obj_idx, *before, *placed_now, *resume, *n_active;
+};
+size_t learned_layout(const scn_batch* b, const scn_mlp* net, int top_k, char* base,
+                      LearnedWs* w) {
+    const size_t n = (size_t)b->n_scenes;
+    size_t off = 0;
+    auto take = [&](size_t sz) -> char* {
+        char* q = base ? base + off : nullptr;
+        off += align256(sz);
+        return q;
+    };
+    LearnedWs t;
+    t.order = take(scn::ws_order_bytes(b->n_scenes));
+    t.act = take(scn::ws_mlp_forward_bytes(net, b->n_scenes));
+    t.hmap = (float*)take(n * SCN_HMAP_CELLS * 4);
+    t.desc = (float*)take((size_t)b->n_objects * SCN_DESC * 4);
+    t.x = (uint16_t*)take(n * SCN_FEATURES * 2);
+    t.logits = (float*)take(n * SCN_BINS * 4);
+    t.bins = (int32_t*)take(n * (size_t)top_k * 4);
+    t.obj_idx = (int32_t*)take(n * 4);
+    t.before = (int32_t*)take(n * 4);
+    t.placed_now = (int32_t*)take(n * 4);
+    t.resume = (int32_t*)take(n * 4);
+    t.n_active = (int32_t*)take(8);
+    if (w) *w = t;
+    return off;
+}
+}  // namespace
+
+size_t scn::ws_learned_bytes(const scn_batch* b, const scn_mlp* net, int top_k) {
+    return learned_layout(b, net, top_k, nullptr, nullptr);
+}
+
+extern "C" {
 
 int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
                                 const scn_mlp* net, int32_t top_k, scn_stream stream) {
@@ -96,9 +160,16 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     if (net->dims[0] != SCN_FEATURES || net->dims[SCN_MLP_LAYERS] != SCN_BINS)
         return scn_fail(SCN_E_INVALID_ARG, "network must map %d features to %d bins",
                         SCN_FEATURES, SCN_BINS);
+    for (int l = 0; l < SCN_MLP_LAYERS; ++l) {
+        if (net->dims[l + 1] <= 0 || net->dims[l] % 32)
+            return scn_fail(SCN_E_INVALID_ARG, "layer %d: dims must be positive multiples of 32", l);
+        if (!net->b[l] || !net->wb[l])
+            return scn_fail(SCN_E_INVALID_ARG, "layer %d tensors missing", l);
+    }
     if (!b->placed || !b->n_placed || !b->status || !b->rec)
         return scn_fail(SCN_E_INVALID_ARG, "placed/n_placed/status/rec required");
     if (a->retries < 0) return scn_fail(SCN_E_INVALID_ARG, "retries must be >= 0");
+    if (int r = check_single_support(b)) return r;
     // Schedule 0: 2 waves, batch order, placed spheres from global memory.
     // Each step launch is as long as its slowest scene's proposals and
     // fallback chunk; measured on batched-4096 this beat the plain default
@@ -109,29 +180,20 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     const hipStream_t st = (hipStream_t)stream;
     const int n = b->n_scenes;
     if (n == 0) return SCN_OK;
-    int hidden = 0;
-    for (int l = 1; l < SCN_MLP_LAYERS; ++l) hidden = net->dims[l] > hidden ? net->dims[l] : hidden;
-    // pipeline buffers, after the network's own activation space
-    const size_t act = 3 * align256((size_t)n * hidden * 2) + 256;
-    const size_t bytes = act + align256((size_t)n * SCN_HMAP_CELLS * 4) +
-                         align256((size_t)b->n_objects * SCN_DESC * 4) +
-                         align256((size_t)n * SCN_FEATURES * 2) + align256((size_t)n * SCN_BINS * 4) +
-                         align256((size_t)n * top_k * 4) + 4 * align256((size_t)n * 4) + 256;
     void* ws;
-    if (int r = scn_workspace(c, bytes, &ws)) return r;
-    if (!c->h_flag) SCN_HIP(hipHostMalloc((void**)&c->h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
-    char* p = (char*)ws + act;
-    auto take = [&](size_t sz) { void* q = p; p += align256(sz); return q; };
-    float* hmap = (float*)take((size_t)n * SCN_HMAP_CELLS * 4);
-    float* desc = (float*)take((size_t)b->n_objects * SCN_DESC * 4);
-    uint16_t* x = (uint16_t*)take((size_t)n * SCN_FEATURES * 2);
-    float* logits = (float*)take((size_t)n * SCN_BINS * 4);
-    int32_t* bins = (int32_t*)take((size_t)n * top_k * 4);
-    int32_t* obj_idx = (int32_t*)take((size_t)n * 4);
-    int32_t* before = (int32_t*)take((size_t)n * 4);
-    int32_t* placed_now = (int32_t*)take((size_t)n * 4);
-    int32_t* resume = (int32_t*)take((size_t)n * 4);
-    int32_t* n_active = (int32_t*)take(8);
+    if (int r = scn_workspace(c, learned_layout(b, net, top_k, nullptr, nullptr), &ws)) return r;
+    LearnedWs W;
+    learned_layout(b, net, top_k, (char*)ws, &W);
+    float* hmap = W.hmap;
+    float* desc = W.desc;
+    uint16_t* x = W.x;
+    float* logits = W.logits;
+    int32_t* bins = W.bins;
+    int32_t* obj_idx = W.obj_idx;
+    int32_t* before = W.before;
+    int32_t* placed_now = W.placed_now;
+    int32_t* resume = W.resume;
+    int32_t* n_active = W.n_active;
 
     const int j_cap = a->max_steps > 0 && a->max_steps < b->max_objects_per_scene ? a->max_steps : 0;
     // uniform entries tried per launch: one attempt of the default size, so
@@ -159,13 +221,13 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
         if (with_net) {
             SCN_HIP(scn::launch_next_object(*b, resume, j_cap, obj_idx, s));
             SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, s));
-            if (int r = scn_mlp_forward(c, net, x, n, logits, (scn_stream)s)) return r;
+            if (int r = scn_mlp_forward_ws(net, x, n, logits, W.act, s)) return r;
             SCN_HIP(scn::launch_topk(n, logits, top_k, obj_idx, bins, s));
         }
         SCN_HIP(scn::launch_copy_i32(b->n_placed, before, n, s));
         SCN_HIP(scn::launch_fill_i32(n_active, 2, 0, s));
         if (int r = scn_place_internal(c, b, a, 1, nullptr, false, bins, top_k, resume, chunk,
-                                       j_cap, n_active, s))
+                                       j_cap, n_active, W.order, s))
             return r;
         SCN_HIP(scn::launch_last_object(*b, before, placed_now, s));
         SCN_HIP(scn::launch_hmap_raise(*b, placed_now, nullptr, hmap, s));

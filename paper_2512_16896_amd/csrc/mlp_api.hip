@@ -29,9 +29,9 @@ int max_hidden(const scn_mlp* n) {
     return h;
 }
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+using scn::align256;
 
-// Bump allocator over the context workspace.
+// Bump allocator over the caller's workspace.
 struct Arena {
     char* base;
     size_t off;
@@ -58,18 +58,13 @@ int forward(const scn_mlp* n, const uint16_t* x, int M, uint16_t* const* act, fl
     return SCN_OK;
 }
 
-// Backward pass into gw / gb (FP32, caller layout) and *loss.
-int backward(scn_ctx* c, const scn_mlp* n, const uint16_t* x, int M, const int32_t* bins,
-             const float* tgt, int L, float* const* gw, float* const* gb, float* loss,
-             hipStream_t st) {
+// Backward pass into gw / gb (FP32, caller layout) and *loss, with its
+// buffers in `ws` (ws_mlp_backward_bytes).
+int backward(const scn_mlp* n, const uint16_t* x, int M, const int32_t* bins, const float* tgt,
+             int L, float* const* gw, float* const* gb, float* loss, void* ws, hipStream_t st) {
     const int H = max_hidden(n), NO = n->dims[SCN_MLP_LAYERS];
     int maxdim = NO;
     for (int l = 0; l <= SCN_MLP_LAYERS; ++l) maxdim = n->dims[l] > maxdim ? n->dims[l] : maxdim;
-    const size_t need = 3 * align256((size_t)M * H * 2) + 2 * align256((size_t)M * NO * 4) +
-                        align256((size_t)M * NO * 2) + 2 * align256((size_t)maxdim * M * 2) +
-                        align256((size_t)M * H * 4) + align256((size_t)M * H * 2) + 256;
-    void* ws;
-    if (int r = scn_workspace(c, need, &ws)) return r;
     Arena a{(char*)ws, 0};
     uint16_t* act[SCN_MLP_LAYERS] = {nullptr};
     for (int l = 1; l < SCN_MLP_LAYERS; ++l) act[l] = a.take<uint16_t>((size_t)M * H);
@@ -111,7 +106,45 @@ int backward(scn_ctx* c, const scn_mlp* n, const uint16_t* x, int M, const int32
     return SCN_OK;
 }
 
+int max_dim(const scn_mlp* n) {
+    int m = 0;
+    for (int l = 0; l <= SCN_MLP_LAYERS; ++l) m = n->dims[l] > m ? n->dims[l] : m;
+    return m;
+}
+
+size_t grad_bytes(const scn_mlp* n) {
+    size_t b = 0;
+    for (int l = 0; l < SCN_MLP_LAYERS; ++l)
+        b += align256((size_t)n->dims[l + 1] * n->dims[l] * 4) + align256((size_t)n->dims[l + 1] * 4);
+    return b;
+}
+
 }  // namespace
+
+size_t scn::ws_mlp_forward_bytes(const scn_mlp* n, int rows) {
+    return rows > 0 ? 3 * align256((size_t)rows * max_hidden(n) * 2) : 0;
+}
+
+size_t scn::ws_mlp_backward_bytes(const scn_mlp* n, int rows) {
+    if (rows <= 0) return 0;
+    const size_t M = (size_t)rows, H = (size_t)max_hidden(n), NO = (size_t)n->dims[SCN_MLP_LAYERS];
+    const size_t D = (size_t)max_dim(n);
+    return 3 * align256(M * H * 2) + 2 * align256(M * NO * 4) + align256(M * NO * 2) +
+           2 * align256(D * M * 2) + align256(M * H * 4) + align256(M * H * 2);
+}
+
+size_t scn::ws_mlp_train_bytes(const scn_mlp* n, int rows) {
+    return rows > 0 ? ws_mlp_backward_bytes(n, rows) + grad_bytes(n) : 0;
+}
+
+int scn_mlp_forward_ws(const scn_mlp* n, const uint16_t* x, int M, float* logits, void* act_ws,
+                       hipStream_t st) {
+    if (M <= 0) return SCN_OK;
+    Arena a{(char*)act_ws, 0};
+    uint16_t* act[SCN_MLP_LAYERS] = {nullptr};
+    for (int l = 1; l < SCN_MLP_LAYERS; ++l) act[l] = a.take<uint16_t>((size_t)M * max_hidden(n));
+    return forward(n, x, M, act, logits, st);
+}
 
 extern "C" {
 
@@ -139,13 +172,9 @@ int scn_mlp_forward(scn_ctx* c, const scn_mlp* n, const uint16_t* x, int32_t M, 
     if (M < 0) return scn_fail(SCN_E_INVALID_ARG, "M must be >= 0");
     if (M == 0) return SCN_OK;
     if (!x || !logits) return scn_fail(SCN_E_INVALID_ARG, "x and logits required");
-    const int H = max_hidden(n);
     void* ws;
-    if (int r = scn_workspace(c, 3 * align256((size_t)M * H * 2) + 256, &ws)) return r;
-    Arena a{(char*)ws, 0};
-    uint16_t* act[SCN_MLP_LAYERS] = {nullptr};
-    for (int l = 1; l < SCN_MLP_LAYERS; ++l) act[l] = a.take<uint16_t>((size_t)M * H);
-    return forward(n, x, M, act, logits, (hipStream_t)stream);
+    if (int r = scn_workspace(c, scn::ws_mlp_forward_bytes(n, M), &ws)) return r;
+    return scn_mlp_forward_ws(n, x, M, logits, ws, (hipStream_t)stream);
 }
 
 int scn_mlp_backward(scn_ctx* c, const scn_mlp* n, const uint16_t* x, int32_t M,
@@ -159,7 +188,9 @@ int scn_mlp_backward(scn_ctx* c, const scn_mlp* n, const uint16_t* x, int32_t M,
         return scn_fail(SCN_E_INVALID_ARG, "x, labels, gradients and loss required");
     for (int l = 0; l < SCN_MLP_LAYERS; ++l)
         if (!gw[l] || !gb[l]) return scn_fail(SCN_E_INVALID_ARG, "gradient buffer %d missing", l);
-    return backward(c, n, x, M, bins, tgt, L, gw, gb, loss, (hipStream_t)stream);
+    void* ws;
+    if (int r = scn_workspace(c, scn::ws_mlp_backward_bytes(n, M), &ws)) return r;
+    return backward(n, x, M, bins, tgt, L, gw, gb, loss, ws, (hipStream_t)stream);
 }
 
 int scn_mlp_train_step(scn_ctx* c, scn_mlp* n, const uint16_t* x, int32_t M, const int32_t* bins,
@@ -174,22 +205,11 @@ int scn_mlp_train_step(scn_ctx* c, scn_mlp* n, const uint16_t* x, int32_t M, con
     if (L <= 0 || !x || !bins || !tgt || !loss)
         return scn_fail(SCN_E_INVALID_ARG, "x, labels and loss required");
     const hipStream_t st = (hipStream_t)stream;
-    // gradient buffers live in a second region after the backward workspace:
-    // grow the workspace to hold both, backward's part first.
-    size_t grad_floats = 0;
-    for (int l = 0; l < SCN_MLP_LAYERS; ++l)
-        grad_floats += (size_t)n->dims[l + 1] * n->dims[l] + n->dims[l + 1];
-    // The backward pass takes the front of the workspace; keep the gradients
-    // in a separately sized block at its end.
-    const int H = max_hidden(n), NO = n->dims[SCN_MLP_LAYERS];
-    int maxdim = NO;
-    for (int l = 0; l <= SCN_MLP_LAYERS; ++l) maxdim = n->dims[l] > maxdim ? n->dims[l] : maxdim;
-    const size_t bw = 3 * align256((size_t)M * H * 2) + 2 * align256((size_t)M * NO * 4) +
-                      align256((size_t)M * NO * 2) + 2 * align256((size_t)maxdim * M * 2) +
-                      align256((size_t)M * H * 4) + align256((size_t)M * H * 2) + 256;
-    const size_t gbytes = align256(grad_floats * 4) + SCN_MLP_LAYERS * 256;
+    // the backward pass takes the front of the workspace, the gradients the
+    // block after it
+    const size_t bw = scn::ws_mlp_backward_bytes(n, M);
     void* ws;
-    if (int r = scn_workspace(c, bw + gbytes, &ws)) return r;
+    if (int r = scn_workspace(c, scn::ws_mlp_train_bytes(n, M), &ws)) return r;
     Arena g{(char*)ws + bw, 0};
     float* gw[SCN_MLP_LAYERS];
     float* gb[SCN_MLP_LAYERS];
@@ -197,7 +217,7 @@ int scn_mlp_train_step(scn_ctx* c, scn_mlp* n, const uint16_t* x, int32_t M, con
         gw[l] = g.take<float>((size_t)n->dims[l + 1] * n->dims[l]);
         gb[l] = g.take<float>((size_t)n->dims[l + 1]);
     }
-    if (int r = backward(c, n, x, M, bins, tgt, L, gw, gb, loss, st)) return r;
+    if (int r = backward(n, x, M, bins, tgt, L, gw, gb, loss, ws, st)) return r;
     const double t = (double)(n->step + 1);
     const float c1 = (float)(1.0 - std::pow((double)opt->beta1, t));
     const float c2 = (float)(1.0 - std::pow((double)opt->beta2, t));

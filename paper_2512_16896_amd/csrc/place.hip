@@ -507,24 +507,43 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         const int o = o0 + jj, sb = sph_off[o];
         const ObjConsts K = object_consts<SPL, !kGrids>(tmpl, sb, sph_off[o + 1] - sb, lane);
         const Support U = load_support(sup, obj_sup[o]);
+        // a non-finite template sphere or support entry: every candidate of
+        // the object collides
+        bool fin_ok = lane < 16 ? __builtin_isfinite(sup[16 * obj_sup[o] + lane]) : true;
+        for (int k = sb + lane; k < sph_off[o + 1]; k += kWave) fin_ok &= finite4(tmpl[k]);
+        const bool obj_bad = __ballot(!fin_ok) != 0;
         const unsigned long long rel = reachable_boxes(K, U, K.rho + margin, box, b0, nbox_mask, lane);
         if (lane == 0) {
             float4* I = linfo + 4 * jj;
             I[0] = make_float4(K.bc[0], K.bc[1], K.bc[2], K.rho);
             I[1] = K.probe;
             I[2] = K.probe2;
-            I[3] = make_float4(K.lift, __int_as_float(K.two ? 1 : 0), __int_as_float((int)(unsigned)rel),
+            I[3] = make_float4(K.lift, __int_as_float((K.two ? 1 : 0) | (obj_bad ? 2 : 0)),
+                               __int_as_float((int)(unsigned)rel),
                                __int_as_float((int)(unsigned)(rel >> 32)));
         }
     }
     // the scene's boxes all turn about z only (then, with a support that does
     // too, the entry loop runs its planar form); the barrier also publishes
     // the object constants
-    int tilted = 0;
-    for (int bi = b0 + (int)threadIdx.x; bi < b1; bi += blockDim.x) tilted |= !yaw_box(box + 16 * bi);
-    const bool boxes_yaw = !__syncthreads_or(tilted);
     const int g0 = grid_off ? grid_off[s] : 0;
-    const int ngrid_mask = kGrids ? min(grid_off[s + 1] - g0, kWave) : 0;   // grids (<= 64)
+    const int g1 = grid_off ? grid_off[s + 1] : 0;
+    const int ngrid_mask = kGrids ? min(g1 - g0, kWave) : 0;   // grids covered by the masks
+    int tilted = 0, bad_in = 0;
+    for (int bi = b0 + (int)threadIdx.x; bi < b1; bi += blockDim.x) {
+        tilted |= !yaw_box(box + 16 * bi);
+        bad_in |= !all_finite(box + 16 * bi, 15);
+    }
+    // non-finite input the whole scene is tested against (box rows, grid
+    // instance rows, spheres placed before this launch): every candidate of
+    // every remaining object collides
+    if constexpr (kGrids)
+        for (int gi = g0 + (int)threadIdx.x; gi < g1; gi += blockDim.x)
+            bad_in |= !all_finite(grid + 24 * gi, 19);
+    for (int i = threadIdx.x; i < sph_off[o0 + j] - first; i += blockDim.x)
+        bad_in |= !finite4(placed[first + i]);
+    const bool boxes_yaw = !__syncthreads_or(tilted);
+    const bool scene_bad = __syncthreads_or(bad_in) != 0;
 
     for (; j < j_end; ++j) {
         const int o = o0 + j;
@@ -553,7 +572,8 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         const float4 probe = make_float4(uniform_f(I1.x), uniform_f(I1.y), uniform_f(I1.z), uniform_f(I1.w));
         const float4 probe2 = make_float4(uniform_f(I2.x), uniform_f(I2.y), uniform_f(I2.z), uniform_f(I2.w));
         const float lift = uniform_f(I3.x);
-        const bool two = uniform_int(__float_as_int(I3.y)) != 0;
+        const int oflags = uniform_int(__float_as_int(I3.y));
+        const bool two = (oflags & 1) != 0;
         const unsigned long long box_rel =
             ((unsigned long long)(unsigned)uniform_int(__float_as_int(I3.w)) << 32) |
             (unsigned)uniform_int(__float_as_int(I3.z));
@@ -565,6 +585,15 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         // planar form: supports and boxes turn about z only; world z of each
         // sphere, of the bounding centre and of the probe is then the same
         // for every candidate
+        if (scene_bad || (oflags & 2)) {   // non-finite input: every candidate collides
+            if (threadIdx.x == 0) {
+                atomicOr(counters + kErrorWord, (unsigned long long)kErrNonFinite);
+                atomicAdd(counters + kNonFinite, 1ull);
+            }
+            fin = SCN_SCENE_INVALID;
+            last = -1;
+            break;
+        }
         if (kYaw && !(boxes_yaw && yaw_support(U))) {   // breaks the declared geometry
             if (threadIdx.x == 0) atomicOr(counters + kErrorWord, (unsigned long long)kErrGeometry);
             fin = SCN_SCENE_INVALID;
@@ -806,7 +835,8 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                         if (q == 0 || q < nq) hit |= box_out2_t<kYaw>(B, wx[q], wy[q], wz[q]) < rm2[q];
                     n_boxp += S;
                 }
-                // voxel grids of the mask: trilinear field minus radius vs margin
+                // voxel grids of the mask: trilinear field minus radius vs
+                // margin (a NaN sample, from a non-finite node, collides)
                 if constexpr (kGrids) while (gm && !__ballot(hit)) {
                     const int gi = __builtin_ctzll(gm);
                     gm &= gm - 1;
@@ -815,7 +845,20 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
 #pragma unroll
                     for (int q = 0; q < SPL; ++q)
                         if (q == 0 || q < nq)
-                            hit |= grid_sample(G, vals, wx[q], wy[q], wz[q]) < cr[q] + margin;
+                            hit |= !(grid_sample(G, vals, wx[q], wy[q], wz[q]) >= cr[q] + margin);
+                    n_grid += S;
+                }
+                // grids beyond the first 64: the same node-box pretest on the
+                // candidate's bounding sphere, then the samples
+                if constexpr (kGrids) for (int gx = g0 + kWave; gx < g1 && !__ballot(hit); ++gx) {
+                    const float* G = grid + 24 * gx;
+                    n_boxc += 1;
+                    if (!(grid_box_d2(G, Gx, Gy, Gz) <= rho * rho)) continue;
+                    const float* vals = grid_val + grid_val_off[grid_src[gx]];
+#pragma unroll
+                    for (int q = 0; q < SPL; ++q)
+                        if (q == 0 || q < nq)
+                            hit |= !(grid_sample(G, vals, wx[q], wy[q], wz[q]) >= cr[q] + margin);
                     n_grid += S;
                 }
                 // Every sphere against the depth map: a hit there is a proven

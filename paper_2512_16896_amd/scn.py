@@ -19,7 +19,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscn.so")
 
 SCN_OK = 0
+SCN_E_INVALID_ARG, SCN_E_HIP, SCN_E_CAPACITY, SCN_E_NO_DEVICE, SCN_E_UNSUPPORTED, \
+    SCN_E_NONFINITE = -1, -2, -3, -4, -5, -6
 ACTIVE, VALID, INVALID = 0, 1, 2
+# workspace kinds (scn_workspace_bytes)
+WS_GENERATE, WS_MLP_FORWARD, WS_MLP_BACKWARD, WS_MLP_TRAIN, WS_GENERATE_LEARNED = 0, 1, 2, 3, 4
 
 
 class ScnError(RuntimeError):
@@ -59,7 +63,7 @@ class Counters(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "candidates", "sphere_pairs", "box_pairs", "grid_samples", "attempts", "placed",
         "error_word", "transforms", "box_culls", "object_culls", "valid_scenes",
-        "invalid_scenes", "sphere_culls")] + [("reserved", C.c_int64 * 3)]
+        "invalid_scenes", "sphere_culls", "nonfinite")] + [("reserved", C.c_int64 * 2)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}
@@ -89,6 +93,8 @@ def _load():
     sigs = {
         "scn_ctx_create": [C.POINTER(vp), C.c_int],
         "scn_ctx_destroy": [vp],
+        "scn_workspace_bytes": [C.c_int, vp, vp, i32, i32, C.POINTER(C.c_size_t)],
+        "scn_set_workspace": [vp, vp, C.c_size_t],
         "scn_reset_counters": [vp, vp],
         "scn_read_counters": [vp, C.POINTER(Counters), vp],
         "scn_sample_poses": [vp, C.POINTER(_Batch), vp, vp, i32, i32, u64, i32, _Poses, vp],
@@ -126,7 +132,8 @@ _lib = _load()
 
 # names of the C ABI entry points (what include/scn.h declares)
 EXPORTS = ("scn_ctx_create", "scn_ctx_destroy", "scn_status_string", "scn_last_error",
-           "scn_reset_counters", "scn_read_counters", "scn_sample_poses", "scn_check_batch",
+           "scn_workspace_bytes", "scn_set_workspace", "scn_reset_counters",
+           "scn_read_counters", "scn_sample_poses", "scn_check_batch",
            "scn_reset_scenes", "scn_place_step", "scn_generate_scenes", "scn_autotune",
            "scn_autotune_save", "scn_autotune_load", "scn_mlp_init", "scn_mlp_forward",
            "scn_mlp_backward", "scn_mlp_train_step", "scn_descriptors", "scn_heightmaps",
@@ -157,19 +164,47 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def workspace_bytes(kind: int, db=None, net=None, rows: int = 0, top_k: int = 0) -> int:
+    n = C.c_size_t()
+    _ok(_lib.scn_workspace_bytes(int(kind), None if db is None else C.byref(db.c),
+                                 None if net is None else C.byref(net.c), int(rows), int(top_k),
+                                 C.byref(n)))
+    return int(n.value)
+
+
 class Context:
-    """An scn_ctx on one device."""
+    """An scn_ctx on one device, with the caller-owned workspace (a torch
+    uint8 tensor) the library's calls take their scratch memory from."""
 
     def __init__(self, device: int = 0):
         self.device = device
         h = C.c_void_p()
         _ok(_lib.scn_ctx_create(C.byref(h), int(device)))
         self.h = h
+        self.ws = None
+
+    def ensure_workspace(self, nbytes: int):
+        """Attach a workspace of at least nbytes (grown, never shrunk)."""
+        if nbytes <= 0 or (self.ws is not None and self.ws.numel() >= nbytes):
+            return
+        size = max(int(nbytes), 2 * (0 if self.ws is None else self.ws.numel()))
+        ws = torch.empty(size, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        _ok(_lib.scn_set_workspace(self.h, C.c_void_p(ws.data_ptr()), size))
+        self.ws = ws
+
+    def set_workspace(self, ws: Optional[torch.Tensor]):
+        """Attach exactly this uint8 tensor (None detaches)."""
+        if ws is None:
+            _ok(_lib.scn_set_workspace(self.h, None, 0))
+        else:
+            _ok(_lib.scn_set_workspace(self.h, C.c_void_p(ws.data_ptr()), int(ws.numel())))
+        self.ws = ws
 
     def close(self):
         if self.h:
             _lib.scn_ctx_destroy(self.h)
             self.h = None
+        self.ws = None
 
     def __del__(self):
         try:
@@ -188,6 +223,7 @@ class Context:
     def autotune(self, db: "DeviceBatch", args: "GenArgs", stream=None):
         """Time every schedule on this batch; returns (schedule, ms)."""
         sched, ms = C.c_int32(), C.c_float()
+        self.ensure_workspace(workspace_bytes(WS_GENERATE, db))
         a = args.c()
         _ok(_lib.scn_autotune(self.h, C.byref(db.c), C.byref(a), C.byref(sched), C.byref(ms),
                               _stream(stream)))
@@ -330,12 +366,14 @@ def reset_scenes(ctx: Context, db: DeviceBatch, stream=None):
 
 def place_step(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None) -> torch.Tensor:
     chosen = torch.empty(max(db.c.n_scenes, 1), dtype=torch.int32, device=db.n_placed.device)
+    ctx.ensure_workspace(workspace_bytes(WS_GENERATE, db))
     a = args.c()
     _ok(_lib.scn_place_step(ctx.h, C.byref(db.c), C.byref(a), _ptr(chosen), _stream(stream)))
     return chosen[:db.c.n_scenes]
 
 
 def generate_scenes(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None):
+    ctx.ensure_workspace(workspace_bytes(WS_GENERATE, db))
     a = args.c()
     _ok(_lib.scn_generate_scenes(ctx.h, C.byref(db.c), C.byref(a), _stream(stream)))
 
@@ -396,6 +434,7 @@ class Network:
 def mlp_forward(ctx: Context, net: Network, x: torch.Tensor, stream=None) -> torch.Tensor:
     M = int(x.shape[0])
     out = torch.empty((max(M, 1), net.dims[-1]), dtype=torch.float32, device=x.device)
+    ctx.ensure_workspace(workspace_bytes(WS_MLP_FORWARD, net=net, rows=M))
     _ok(_lib.scn_mlp_forward(ctx.h, C.byref(net.c), _ptr(x), M, _ptr(out), _stream(stream)))
     return out[:M]
 
@@ -407,6 +446,7 @@ def mlp_backward(ctx: Context, net: Network, x, bins, tgt, stream=None):
     loss = torch.zeros(1, dtype=torch.float32, device=x.device)
     pw = (C.c_void_p * N_LAYERS)(*[g.data_ptr() for g in gw])
     pb = (C.c_void_p * N_LAYERS)(*[g.data_ptr() for g in gb])
+    ctx.ensure_workspace(workspace_bytes(WS_MLP_BACKWARD, net=net, rows=M))
     _ok(_lib.scn_mlp_backward(ctx.h, C.byref(net.c), _ptr(x), M, _ptr(bins), _ptr(tgt), L,
                               C.cast(pw, C.c_void_p), C.cast(pb, C.c_void_p), _ptr(loss),
                               _stream(stream)))
@@ -419,6 +459,7 @@ def mlp_train_step(ctx: Context, net: Network, x, bins, tgt, lr=1e-3, betas=(0.9
     if loss is None:
         loss = torch.zeros(1, dtype=torch.float32, device=x.device)
     opt = AdamW(float(lr), float(betas[0]), float(betas[1]), float(eps), float(weight_decay))
+    ctx.ensure_workspace(workspace_bytes(WS_MLP_TRAIN, net=net, rows=M))
     _ok(_lib.scn_mlp_train_step(ctx.h, C.byref(net.c), _ptr(x), M, _ptr(bins), _ptr(tgt), L,
                                 C.byref(opt), _ptr(loss), _stream(stream)))
     return loss
@@ -467,6 +508,7 @@ def harvest_labels(ctx: Context, db: DeviceBatch, n_state, L: int, seed: int, ro
 
 def generate_scenes_learned(ctx: Context, db: DeviceBatch, args: GenArgs, net: Network,
                             top_k: int = 64, stream=None):
+    ctx.ensure_workspace(workspace_bytes(WS_GENERATE_LEARNED, db, net, top_k=top_k))
     a = args.c()
     _ok(_lib.scn_generate_scenes_learned(ctx.h, C.byref(db.c), C.byref(a), C.byref(net.c),
                                          int(top_k), _stream(stream)))

@@ -50,3 +50,42 @@ def test_status_strings_without_device():
     import torch
     if not torch.cuda.is_available():
         assert lib.scn_ctx_create(ctypes.byref(h), 0) == -4
+
+
+def test_nonfinite_status_string():
+    lib = ctypes.CDLL(LIB)
+    lib.scn_status_string.restype = ctypes.c_char_p
+    assert b"non-finite" in lib.scn_status_string(-6)
+
+
+def test_workspace_bytes_on_the_host():
+    """scn_workspace_bytes is host arithmetic on the sizes (no device): the
+    longest-first order of n scenes, the network's hidden activations, and
+    the learned generation's buffers (at least its logits and features)."""
+    from paper_2512_16896_amd import scn
+    al = lambda v: (v + 255) // 256 * 256
+    b = scn._Batch()
+    b.n_scenes, b.n_objects = 1000, 20000
+    n = ctypes.c_size_t()
+    assert scn.lib().scn_workspace_bytes(scn.WS_GENERATE, ctypes.byref(b), None, 0, 0,
+                                         ctypes.byref(n)) == 0
+    assert n.value == al(4 * 1000) + al(4 * 257)
+    net = scn.Mlp()
+    for l, d in enumerate((4128, 512, 512, 512, 4096)):
+        net.dims[l] = d
+    assert scn.lib().scn_workspace_bytes(scn.WS_MLP_FORWARD, None, ctypes.byref(net), 96, 0,
+                                         ctypes.byref(n)) == 0
+    assert n.value == 3 * al(96 * 512 * 2)
+    assert scn.lib().scn_workspace_bytes(scn.WS_MLP_TRAIN, None, ctypes.byref(net), 256, 0,
+                                         ctypes.byref(n)) == 0
+    grads = sum(al(4 * o * i) + al(4 * o) for i, o in ((4128, 512), (512, 512), (512, 512),
+                                                        (512, 4096)))
+    assert n.value > grads
+    assert scn.lib().scn_workspace_bytes(scn.WS_GENERATE_LEARNED, ctypes.byref(b),
+                                         ctypes.byref(net), 0, 64, ctypes.byref(n)) == 0
+    assert n.value >= 1000 * (4096 * 4 + 4128 * 2 + 4096 * 4 + 64 * 4) + 20000 * 32 * 4
+    # bad arguments are refused without a device
+    assert scn.lib().scn_workspace_bytes(99, ctypes.byref(b), None, 0, 0, ctypes.byref(n)) == -1
+    assert scn.lib().scn_workspace_bytes(scn.WS_GENERATE_LEARNED, ctypes.byref(b),
+                                         ctypes.byref(net), 0, 0, ctypes.byref(n)) == -1
+    assert scn.lib().scn_set_workspace(None, None, 0) == -1
