@@ -26,8 +26,10 @@ the paper does not give are the readings recorded in the design notes.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
 from typing import Optional
 
 import numpy as np
@@ -298,7 +300,9 @@ def shelf_scenes(n_scenes: int = 65536, seed: int = 0, n_obj: int = 100, n_sph: 
     sph_off = (np.arange(n_tot_obj + 1, dtype=np.int64) * n_sph)
     sup = np.zeros((n_scenes * n_shelves, 16), np.float32)
     grid = np.zeros((n_scenes * n_shelves, 24), np.float32)
-    for c0 in range(0, n_scenes, chunk):
+    def fill(c0):
+        # chunks draw from their own seeded streams and write disjoint rows,
+        # so they run on a thread pool with the same result in any order
         c1 = min(n_scenes, c0 + chunk)
         m = c1 - c0
         rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5E1F, c0 // chunk]))
@@ -320,6 +324,15 @@ def shelf_scenes(n_scenes: int = 65536, seed: int = 0, n_obj: int = 100, n_sph: 
         perm = _footprint_order(oo, so, tm)
         so, tm = _reorder_objects(perm, so, tm)
         tmpl[c0 * n_obj * n_sph:c1 * n_obj * n_sph] = tm
+
+    starts = range(0, n_scenes, chunk)
+    workers = max(1, min(len(starts), 8, os.cpu_count() or 1))
+    if workers == 1:
+        for c0 in starts:
+            fill(c0)
+    else:
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(fill, starts))
     obj_sup = (np.repeat(np.arange(n_scenes), n_obj) * n_shelves +
                np.tile(np.arange(n_obj) % n_shelves, n_scenes)).astype(np.int32)
     return SceneBatch(
