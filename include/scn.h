@@ -284,6 +284,28 @@ int scn_place_step(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args, int32_t
 int scn_generate_scenes(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
                         scn_stream stream);
 
+/* ---- allocation-free generation ---------------------------------------- */
+
+/* For callers that cannot allocate device memory or attach a workspace (code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): scn_generate_scenes with its scratch memory (the longest-first
+ * scene order of schedules with SCN_SCHED_LONGEST_FIRST) taken from a fixed
+ * array inside the library instead of the context's workspace.
+ *   - Limit: SCN_NOALLOC_MAX_SCENES scenes (the array is 4 MiB + 1.25 KiB per
+ *     device, held until the process ends; scn_ctx_create looks up its address
+ *     on the context's device).  A larger batch fails with SCN_E_INVALID_ARG
+ *     before any launch.
+ *   - Calls no hipMalloc / hipFree and no allocating runtime routine; launches
+ *     eagerly on `stream` (args->use_graph must be 0, else SCN_E_UNSUPPORTED).
+ *   - Every call on one device shares that device's array and leaves its
+ *     contents behind (the order is rebuilt and its histogram cleared by a fill
+ *     kernel in each call): calls that overlap on one device, from any stream,
+ *     context or thread, race; the caller serializes them.
+ *   - Results are identical to scn_generate_scenes with the same arguments. */
+#define SCN_NOALLOC_MAX_SCENES (1 << 20)
+int scn_generate_scenes_noalloc(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
+                                scn_stream stream);
+
 /* ---- uneven batching: autotuned schedules ------------------------------ */
 
 /* Schedule ids for scn_gen_args.schedule (0 = the context's tuned choice for

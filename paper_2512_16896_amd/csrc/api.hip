@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
@@ -41,6 +42,42 @@ int scn_workspace(scn_ctx* c, size_t bytes, void** out) {
 size_t scn::ws_order_bytes(int n_scenes) {
     return align256(sizeof(int32_t) * (size_t)(n_scenes > 0 ? n_scenes : 0)) +
            align256(sizeof(int32_t) * (kOrderBuckets + 1));
+}
+
+// Fixed device scratch of scn_generate_scenes_noalloc: the longest-first scene
+// order and its histogram for up to SCN_NOALLOC_MAX_SCENES scenes (4 MiB + 1.25
+// KiB).  Every device the library runs on holds its own copy until the process
+// ends.  In host code `scratch` only names the symbol: kernels are handed the
+// per-device address that hipGetSymbolAddress returned for it (g_scratch_ptr).
+static constexpr size_t kScratchBytes =
+    scn::align256(sizeof(int32_t) * (size_t)SCN_NOALLOC_MAX_SCENES) +
+    scn::align256(sizeof(int32_t) * (scn::kOrderBuckets + 1));
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kScratchMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchMaxDevices] = {};
+
+// Looks up this device's address of `scratch` once (the device must be
+// current); called by scn_ctx_create.
+static int scratch_setup(int device) {
+    if (device < 0 || device >= kScratchMaxDevices)
+        return scn_fail(SCN_E_NO_DEVICE, "device %d beyond the %d the library tracks", device,
+                        kScratchMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return SCN_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return scn_fail(SCN_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+    return SCN_OK;
+}
+
+static void* scratch_ptr(int device) {
+    if (device < 0 || device >= kScratchMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 namespace {
@@ -99,6 +136,7 @@ int scn_ctx_create(scn_ctx** out, int device) {
     if (strncmp(p.gcnArchName, "gfx950", 6) != 0)
         return fail(SCN_E_NO_DEVICE, "device %d is %s, not gfx950", device, p.gcnArchName);
     SCN_HIP(hipSetDevice(device));
+    if (int r = scratch_setup(device)) return r;
     auto* c = new scn_ctx();
     c->device = device;
     if (hipHostMalloc((void**)&c->h_flag, 4 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
@@ -439,6 +477,24 @@ int scn_generate_scenes(scn_ctx* c, scn_batch* b, const scn_gen_args* a, scn_str
     scn::PlacePlan plan;
     if (int r = plan_place(c, b, a, a ? a->max_steps : 0, &plan)) return r;
     if (a->use_graph) return run_place_graph(c, b, a, plan, (hipStream_t)stream);
+    return run_place(c, b, a, plan, nullptr, true, (hipStream_t)stream);
+}
+
+int scn_generate_scenes_noalloc(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
+                                scn_stream stream) {
+    if (int r = check_ctx(c)) return r;
+    if (!b) return fail(SCN_E_INVALID_ARG, "null batch");
+    if (b->n_scenes > SCN_NOALLOC_MAX_SCENES)
+        return fail(SCN_E_INVALID_ARG, "%d scenes exceed the fixed scratch of %d scenes",
+                    b->n_scenes, SCN_NOALLOC_MAX_SCENES);
+    if (int r = check_batch(b, true)) return r;
+    if (!a) return fail(SCN_E_INVALID_ARG, "null args");
+    if (a->use_graph)
+        return fail(SCN_E_UNSUPPORTED, "scn_generate_scenes_noalloc launches eagerly (use_graph = 0)");
+    void* ws = scratch_ptr(c->device);
+    if (!ws) return fail(SCN_E_HIP, "no scratch address for device %d", c->device);
+    scn::PlacePlan plan;
+    if (int r = plan_place(c, b, a, a->max_steps, &plan, ws)) return r;
     return run_place(c, b, a, plan, nullptr, true, (hipStream_t)stream);
 }
 

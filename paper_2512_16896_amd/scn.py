@@ -102,6 +102,7 @@ def _load():
         "scn_reset_scenes": [vp, C.POINTER(_Batch), vp],
         "scn_place_step": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp, vp],
         "scn_generate_scenes": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp],
+        "scn_generate_scenes_noalloc": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp],
         "scn_autotune": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), C.POINTER(C.c_int32),
                          C.POINTER(C.c_float), vp],
         "scn_autotune_save": [vp, C.c_char_p],
@@ -134,7 +135,8 @@ _lib = _load()
 EXPORTS = ("scn_ctx_create", "scn_ctx_destroy", "scn_status_string", "scn_last_error",
            "scn_workspace_bytes", "scn_set_workspace", "scn_reset_counters",
            "scn_read_counters", "scn_sample_poses", "scn_check_batch",
-           "scn_reset_scenes", "scn_place_step", "scn_generate_scenes", "scn_autotune",
+           "scn_reset_scenes", "scn_place_step", "scn_generate_scenes",
+           "scn_generate_scenes_noalloc", "scn_autotune",
            "scn_autotune_save", "scn_autotune_load", "scn_mlp_init", "scn_mlp_forward",
            "scn_mlp_backward", "scn_mlp_train_step", "scn_descriptors", "scn_heightmaps",
            "scn_features", "scn_proposal_topk", "scn_harvest_labels",
@@ -376,6 +378,16 @@ def generate_scenes(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None):
     ctx.ensure_workspace(workspace_bytes(WS_GENERATE, db))
     a = args.c()
     _ok(_lib.scn_generate_scenes(ctx.h, C.byref(db.c), C.byref(a), _stream(stream)))
+
+
+NOALLOC_MAX_SCENES = 1 << 20
+
+
+def generate_scenes_noalloc(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None):
+    """scn_generate_scenes with the scene-order scratch in the library's fixed
+    device array: attaches no workspace and allocates nothing."""
+    a = args.c()
+    _ok(_lib.scn_generate_scenes_noalloc(ctx.h, C.byref(db.c), C.byref(a), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------
