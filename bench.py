@@ -17,19 +17,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 operation counts per unit of work (flag-mode tests):
-#   sphere-sphere pair : 3 sub + 5 (squared distance) + 2 (threshold) + 1 cmp = 11
-#   sphere-box pair    : 3 sub + 15 (box-frame rotation) + 3 (|q|-h) + 3 (max 0)
-#                        + 5 (squared norm) + 1 cmp = 30
-#   sphere transform   : 4 + 4 + 1 (yaw + position) + 18 (support pose) = 27
-#   box pretest        : the sphere-box test applied to the bounding sphere = 30
-#   object pretest     : bounding sphere vs bounding sphere, like a pair = 11
-FLOP_PAIR, FLOP_BOX, FLOP_XFORM, FLOP_BOXCULL, FLOP_OBJCULL = 11, 30, 27, 30, 11
-# Distance mode (scn_check_batch with clearances): the pair is 3 sub + 5 (squared
-# distance) + 1 sqrt + 1 sub + 1 min = 11; the box adds the signed part of the
-# SDF to the flag form: 30 + 1 sqrt + 3 (max of the excess, min 0, add) + 1 sub
-# + 1 min - 1 cmp = 35.
-FLOP_PAIR_DIST, FLOP_BOX_DIST = 11, 35
+# Algorithmic FP32 operation counts per unit of work, fixed for reporting:
+#   sphere-sphere pair   11  (3 sub + 5 for the squared distance + 2 for the
+#                             squared threshold + 1 compare)
+#   sphere-box test      26  (yaw boxes)
+#   trilinear sample     45
+#   sphere transform     10
+# The roofline fraction counts the tests the method executes at these units.
+# The place kernel's bounding-sphere pretests (box, object and sphere culls)
+# are reported beside it, at the same units, as overhead: they decide no
+# candidate by themselves.
+FLOP_PAIR, FLOP_BOX, FLOP_GRID, FLOP_XFORM = 11, 26, 45, 10
 PEAK_FP32_VALU_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FP32 FLOP/clk (published MI355X figure)
 
 WORKLOADS = {
@@ -64,12 +62,12 @@ WORKLOADS = {
 }
 
 
-def recorded_traffic(key: str):
+def recorded_traffic(key: str, path: str = None):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE/WRITE_SIZE runs kept in
     profiles/traffic.json -- only while the kernel's sources are the ones those
     counters were taken on (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))[key]
     except (OSError, KeyError, ValueError):
@@ -167,59 +165,213 @@ def learned_leg(ctx, db, b, W, args, stream, plain_rate):
                          "train_s": t_train, "loss_first": log[0][1], "loss_last": log[-1][1]}}
 
 
-def dense_leg(ctx, db, b, W, stream, seed=77):
+def dense_leg(ctx, db, b, default_ncand, stream, seed=77, reps=3):
     """scn_check_batch in distance mode over a whole generation's states: for
-    every object position j, all candidates of object j of every scene against
-    the scene's boxes and its first min(j, placed) objects (the placement of the
-    last plain run).  Times the check launches only."""
+    every object position j, all candidates of object j of every scene (its
+    per-object candidate count) against the scene's boxes and its first
+    min(j, placed) objects (the placement of the last plain run in `db`).
+    Times the check launches only, with HIP events on the launch stream."""
     import torch
     from paper_2512_16896_amd import scn
-    n, C = b.n_scenes, W["ncand"]
+    n = b.n_scenes
     final = db.n_placed.clone()
     fin = final.cpu().numpy().astype(np.int64)
     obj_off = np.asarray(b.obj_off, np.int64)
     sph_off = np.asarray(b.sph_off, np.int64)
+    ncand = (np.asarray(b.obj_ncand, np.int64) if b.obj_ncand is not None
+             else np.full(b.n_objects, default_ncand, np.int64))
     nobj = obj_off[1:] - obj_off[:-1]
     nbox = np.diff(np.asarray(b.box_off, np.int64))
-    cand_off = torch.arange(0, (n + 1) * C, C, dtype=torch.int32, device="cuda:0")
-    dnobj = torch.as_tensor(nobj, dtype=torch.int32, device="cuda:0")
-    doff = db.obj_off[:-1]
-    pairs = boxes = xf = 0
+    dev = torch.device("cuda", 0)
+    pairs = boxes = xf = cands = 0
     launches = []
     for j in range(int(nobj.max())):
-        oi = torch.where(dnobj > j, doff + j, torch.full_like(dnobj, -1)).to(torch.int32)
-        npl = torch.minimum(final, torch.full_like(final, j))
-        poses = scn.sample_poses(ctx, db, oi, cand_off, n * C, C, seed, 0)
-        launches.append((oi, npl, poses))
         live = nobj > j
-        o = obj_off[:-1][live] + j
-        S = sph_off[o + 1] - sph_off[o]
-        P = sph_off[obj_off[:-1][live] + np.minimum(j, fin[live])] - sph_off[obj_off[:-1][live]]
-        pairs += int(np.sum(C * S * P))
-        boxes += int(np.sum(C * S * nbox[live]))
-        xf += int(np.sum(C * S))
+        o = np.where(live, obj_off[:-1] + j, -1)
+        C = np.where(live, ncand[np.maximum(o, 0)], 0)
+        off = np.zeros(n + 1, np.int64)
+        off[1:] = np.cumsum(C)
+        total, cmax = int(off[-1]), int(C.max())
+        oi = torch.as_tensor(o.astype(np.int32), device=dev)
+        cand_off = torch.as_tensor(off.astype(np.int32), device=dev)
+        npl = torch.as_tensor(np.minimum(fin, j).astype(np.int32), device=dev)
+        poses = scn.sample_poses(ctx, db, oi, cand_off, total, cmax, seed, 0)
+        launches.append((oi, cand_off, total, cmax, npl, poses))
+        S = (sph_off[o + 1] - sph_off[o])[live]
+        P = (sph_off[obj_off[:-1] + np.minimum(j, fin)] - sph_off[obj_off[:-1]])[live]
+        pairs += int(np.sum(C[live] * S * P))
+        boxes += int(np.sum(C[live] * S * nbox[live]))
+        xf += int(np.sum(C[live] * S))
+        cands += total
     ms = []
-    for rep in range(3):
+    for rep in range(reps):
         tot = 0.0
-        for oi, npl, poses in launches:
+        for oi, cand_off, total, cmax, npl, poses in launches:
             db.n_placed.copy_(npl)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            scn.check_batch(ctx, db, oi, cand_off, n * C, C, poses)
+            scn.check_batch(ctx, db, oi, cand_off, total, cmax, poses)
             e1.record(stream)
             torch.cuda.synchronize()
             tot += e0.elapsed_time(e1)
         ms.append(tot)
     db.n_placed.copy_(final)
     t = min(ms) * 1e-3
-    flop = FLOP_PAIR_DIST * pairs + FLOP_BOX_DIST * boxes + FLOP_XFORM * xf
-    return {"candidate_checks_per_s": n * C * len(launches) / t, "pairs_per_s": pairs / t,
-            "ms_per_pass": 1e3 * t, "launches": len(launches),
+    flop = FLOP_PAIR * pairs + FLOP_BOX * boxes + FLOP_XFORM * xf
+    return {"candidate_checks_per_s": cands / t, "pairs_per_s": pairs / t,
+            "ms_per_pass": 1e3 * t, "launches": len(launches), "candidates": cands,
             "roofline": {"bound": "alu", "achieved": flop / t / 1e12,
                          "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                          "frac": flop / t / 1e12 / PEAK_FP32_VALU_TFLOPS,
                          "traffic": recorded_traffic(f"k_check dense {b.name}"),
-                         "kernel": "k_check (dense, distance mode)"}}
+                         "kernel": "k_check (dense, distance mode)",
+                         "kernel_ms_per_launch": 1e3 * t / len(launches)}}
+
+
+def plain_leg(ctx, b, W, steps, warmup, schedule=0):
+    """Time `steps` whole plain generations of batch b (inputs resident in HBM
+    before the timed region), after `warmup` untimed ones.  Returns the result
+    fields, the device batch and the schedule that ran."""
+    import torch
+    from paper_2512_16896_amd import scn
+    db = scn.DeviceBatch(b, "cuda:0")
+    stream = torch.cuda.current_stream()
+    graph = 1 if W.get("graph") else 0
+    gen = lambda step: scn.generate_scenes(
+        ctx, db, scn.GenArgs(seed=1000 + step, default_ncand=W["ncand"], schedule=schedule,
+                             use_graph=graph))
+    tuned = None
+    if W.get("tune") and schedule == 0:
+        progress(f"autotuning {b.name or ''}")
+        tuned = ctx.autotune(db, scn.GenArgs(seed=999, default_ncand=W["ncand"]))
+    sched_run = tuned[0] if tuned else (schedule or scn.DEFAULT_SCHEDULE)
+    for i in range(warmup):
+        gen(-1 - i)
+    torch.cuda.synchronize()
+    ctx.reset_counters()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        gen(k)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cnt = ctx.read_counters()     # the place kernel counts the scenes it finished
+    launch_ms = float(np.mean([a.elapsed_time(z) for a, z in ev]))
+    per = {k: v / steps for k, v in cnt.items() if k != "error_word"}
+    # executed method tests at the fixed units, per launch
+    flop = (FLOP_PAIR * per["sphere_pairs"] + FLOP_BOX * per["box_pairs"] +
+            FLOP_GRID * per["grid_samples"] + FLOP_XFORM * per["transforms"])
+    pre = FLOP_BOX * per["box_culls"] + FLOP_PAIR * (per["object_culls"] + per["sphere_culls"])
+    achieved = flop / (launch_ms * 1e-3) / 1e12
+    n = b.n_scenes
+    out = {
+        "value": cnt["valid_scenes"] / wall, "unit": "valid scenes/s",
+        "ms_per_step": 1e3 * wall / steps,
+        "launch": "hipGraph replay" if graph else "direct",
+        "schedule": (f"autotuned 0x{tuned[0]:x}" if tuned else
+                     (f"0x{schedule:x}" if schedule else f"default 0x{scn.DEFAULT_SCHEDULE:x}")),
+        "valid_fraction": cnt["valid_scenes"] / (n * steps),
+        "candidate_checks_per_s": cnt["candidates"] / wall,
+        "counters_per_step": per,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": recorded_traffic(f"k_place {b.name} 0x{sched_run:x}"),
+                     "kernel": "k_place (fused place kernel)", "kernel_ms": launch_ms,
+                     "flop_per_launch": flop,
+                     "units": "executed tests: 11/pair, 26/sphere-box, 45/trilinear, "
+                              "10/transform"},
+        "pretests": {"flop_per_launch": pre,
+                     "tflops": pre / (launch_ms * 1e-3) / 1e12,
+                     "frac_if_counted": (flop + pre) / (launch_ms * 1e-3) / 1e12
+                     / PEAK_FP32_VALU_TFLOPS,
+                     "note": "bounding-sphere box/object/sphere pretests (overhead, not in frac)"},
+    }
+    return out, db, stream
+
+
+def host_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(b, W, n_all=64, n_one=2, warm=2, runs=5):
+    """The FP64 oracle as it stands, on the host cores: the first n_all scenes
+    with every core, the first n_one with one thread; median of `runs` timed
+    runs after `warm` untimed ones."""
+    import oracle
+    from paper_2512_16896_amd import scenegen as sg
+    oracle.build(force=False)
+    threads = oracle.max_threads()
+
+    def timed(k, nthreads):
+        sub, ids = sg.subset(b, np.arange(min(k, b.n_scenes)))
+        oracle.set_threads(nthreads)
+        ts, last = [], None
+        for r in range(warm + runs):
+            t = time.perf_counter()
+            last = oracle.generate(sub, seed=1000, default_ncand=W["ncand"], scene_id=ids)
+            if r >= warm:
+                ts.append(time.perf_counter() - t)
+        med = float(np.median(ts))
+        v = int(np.sum(last["status"] == 1))
+        return {"valid_scenes_per_s": v / med, "scenes_per_s": sub.n_scenes / med,
+                "candidate_checks_per_s": float(np.sum(last["n_cand"])) / med,
+                "median_s": med, "scenes": sub.n_scenes, "valid": v, "threads": nthreads}
+
+    allc = timed(n_all, threads)
+    one = timed(n_one, 1)
+    oracle.set_threads(threads)
+    return {"value": allc["valid_scenes_per_s"], "unit": "valid scenes/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"scenes 0..{allc['scenes'] - 1} of the same workload, seed 1000, median of "
+                      f"{runs} runs after {warm} warm-ups ({allc['median_s']:.2f} s, "
+                      f"{allc['valid']} valid); one thread: scenes 0..{one['scenes'] - 1}",
+            "host_cpu": host_model(), "all_cores": allc, "one_thread": one}
+
+
+def extra_workload(ctx, name, steps, warmup, dense_scenes=0):
+    """Another workload's plain generation (and optionally the dense check on
+    a sample of its scenes), reported as an extra key of the same line."""
+    import torch
+    from paper_2512_16896_amd import scenegen as sg
+    W = WORKLOADS[name]
+    progress(f"building {name}")
+    b = W["make"](0)
+    b.name = name
+    progress(f"timing {name}")
+    out, db, stream = plain_leg(ctx, b, W, steps, warmup)
+    out["config"] = W["desc"]
+    if name == "table-1":
+        ms = out["roofline"]["kernel_ms"]
+        out["us_per_scene"] = 1e3 * ms
+        out["us_per_object"] = 1e3 * ms / b.n_objects
+    del db
+    torch.cuda.empty_cache()
+    if dense_scenes:
+        progress(f"dense check on {dense_scenes} scenes of {name}")
+        rng = np.random.default_rng(5)
+        pick = np.sort(rng.choice(b.n_scenes, dense_scenes, replace=False))
+        sub, _ = sg.subset(b, pick)
+        sub.name = name
+        del b
+        from paper_2512_16896_amd import scn
+        sdb = scn.DeviceBatch(sub, "cuda:0")
+        scn.generate_scenes(ctx, sdb, scn.GenArgs(seed=1000, default_ncand=W["ncand"]))
+        d = dense_leg(ctx, sdb, sub, W["ncand"], stream, reps=2)
+        d["sample"] = f"{dense_scenes} random scenes (rng seed 5) of the {name} batch"
+        out["dense_check"] = d
+        del sdb
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -233,6 +385,9 @@ def main():
     ap.add_argument("--schedule", type=lambda v: int(v, 0), default=0)
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and timing the learned-proposal form")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads' lines (table-1, uneven-16384, shelves-65536)")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-check legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -246,99 +401,46 @@ def main():
     W = WORKLOADS[args.workload]
     progress(f"building {args.workload}")
     b = W["make"](args.seed)
-    progress("uploading")
+    b.name = args.workload
+    progress("uploading and timing")
     torch.cuda.set_device(0)
     ctx = scn.Context(0)
-    db = scn.DeviceBatch(b, "cuda:0")
-    stream = torch.cuda.current_stream()
-    graph = 1 if W.get("graph") else 0
-    gen = lambda step: scn.generate_scenes(
-        ctx, db, scn.GenArgs(seed=1000 + step, default_ncand=W["ncand"], schedule=args.schedule,
-                             use_graph=graph))
-
-    tuned = None
-    if W.get("tune") and args.schedule == 0:
-        progress("autotuning")
-        tuned = ctx.autotune(db, scn.GenArgs(seed=999, default_ncand=W["ncand"]))
-    # the schedule the timed launches run
-    sched_run = tuned[0] if tuned else (args.schedule or scn.DEFAULT_SCHEDULE)
-    progress("timing")
-    for i in range(args.warmup):
-        gen(-1 - i)
-    torch.cuda.synchronize()
-    ctx.reset_counters()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        gen(k)
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    cnt = ctx.read_counters()     # the place kernel counts the scenes it finished
-    valid = cnt["valid_scenes"]
-    wall = t1 - t0
-    launch_ms = float(np.mean([a.elapsed_time(z) for a, z in ev]))
-    steps = args.steps
-    flop_per_launch = (FLOP_PAIR * cnt["sphere_pairs"] + FLOP_BOX * cnt["box_pairs"] +
-                       FLOP_XFORM * cnt["transforms"] + FLOP_BOXCULL * cnt["box_culls"] +
-                       FLOP_OBJCULL * (cnt["object_culls"] + cnt["sphere_culls"])) / steps
-    achieved_tflops = flop_per_launch / (launch_ms * 1e-3) / 1e12
+    leg, db, stream = plain_leg(ctx, b, W, args.steps, args.warmup, args.schedule)
     n = b.n_scenes
     out = {
         "metric": "valid scenes/sec + candidate-pose checks/sec (plain vs learned proposal)",
-        "value": valid / wall,
-        "unit": "valid scenes/s",
-        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / steps,
+        "value": leg["value"], "unit": "valid scenes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": leg["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W['desc']}", "scenes": n,
                    "objects": int(b.n_objects), "method": "plain (uniform candidates)"},
-        "launch": "hipGraph replay" if graph else "direct",
-        "schedule": (f"autotuned 0x{tuned[0]:x}" if tuned else
-                     (f"0x{args.schedule:x}" if args.schedule
-                      else f"default 0x{scn.DEFAULT_SCHEDULE:x}")),
-        "valid_fraction": valid / (n * steps),
-        "candidate_checks_per_s": cnt["candidates"] / wall,
-        "counters_per_step": {k: v / steps for k, v in cnt.items() if k != "error_word"},
-        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": recorded_traffic(f"k_place {args.workload} 0x{sched_run:x}"),
-                     "kernel": "k_place (fused place kernel)",
-                     "kernel_ms": launch_ms},
     }
+    out.update({k: v for k, v in leg.items() if k not in ("value", "unit", "ms_per_step")})
     dq = dense_equivalent(b, db, W["ncand"])
+    kms = leg["roofline"]["kernel_ms"]
     out["dense_equivalent"] = {
-        "flop_per_step": dq, "tflops": dq / (launch_ms * 1e-3) / 1e12,
-        "x_fp32_peak": dq / (launch_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS,
+        "flop_per_step": dq, "tflops": dq / (kms * 1e-3) / 1e12,
+        "x_fp32_peak": dq / (kms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS,
         "note": "dense FLOP of the candidates a first-valid scan decides (last step), over the "
                 "place kernel's time; culling makes it exceed the peak"}
-    if W.get("dense"):
+    if W.get("dense") and not args.no_dense:
         progress("dense check")
-        out["dense_check"] = dense_leg(ctx, db, b, W, stream)
+        out["dense_check"] = dense_leg(ctx, db, b, W["ncand"], stream)
     if W.get("learned") and not args.no_learned:
         progress("learned form: harvest, training, timing")
-        out["learned"] = learned_leg(ctx, db, b, W, args, stream, valid / wall)
+        out["learned"] = learned_leg(ctx, db, b, W, args, stream, leg["value"])
     if not args.no_cpu_baseline and W["cpu_scenes"] > 0:
         progress("cpu baseline")
-        import oracle
-        from paper_2512_16896_amd import scenegen as sg
-        k = min(W["cpu_scenes"], n)
-        pick = np.arange(k)
-        sub, ids = sg.subset(b, pick)
-        oracle.build(force=False)
-        threads = oracle.max_threads()
-        tc = time.perf_counter()
-        ref = oracle.generate(sub, seed=1000, default_ncand=W["ncand"], scene_id=ids)
-        tc = time.perf_counter() - tc
-        v = int(np.sum(ref["status"] == 1))
-        out["cpu_baseline"] = {"value": v / tc, "unit": "valid scenes/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"scenes 0..{k - 1} of the same workload, seed 1000, "
-                                         f"{tc:.1f} s, {v} valid"}
+        out["cpu_baseline"] = cpu_baseline(b, W)
+    del db
+    torch.cuda.empty_cache()
+    if args.workload == "batched-4096" and not args.no_extra:
+        out["table_1"] = extra_workload(ctx, "table-1", 200, 20)
+        out["uneven_16384"] = extra_workload(ctx, "uneven-16384", 10, 2,
+                                             dense_scenes=0 if args.no_dense else 512)
+        out["shelves_65536"] = extra_workload(ctx, "shelves-65536", 5, 1)
     print(json.dumps(out), flush=True)
     ctx.close()
 
