@@ -18,7 +18,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "fk.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC",
                                "-shared", "-fno-fast-math", "-ffp-contract=off",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, *_SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -72,6 +72,9 @@ def lib():
                                        C.c_int] + [C.c_void_p] * 4
         L.orc_check.argtypes = [C.POINTER(_Batch)] + [C.c_void_p] * 9
         L.orc_generate.argtypes = [C.POINTER(_Batch), C.POINTER(_GenArgs), C.POINTER(_GenOut)]
+        L.orc_fk_links.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_uint64, C.c_int, C.c_void_p, C.c_void_p]
+        L.orc_fk_rows.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_max_threads.restype = C.c_int
         _lib = L
@@ -195,3 +198,30 @@ def generate(b, seed: int, margin: float = 0.005, retries: int = 10, default_nca
                   int(max_steps))
     lib().orc_generate(C.byref(K.cb), C.byref(ga), C.byref(go))
     return out
+
+
+# ---------------------------------------------------------------------------
+def forward_kinematics(joint_off, joint, base, seed: int = 0, q=None, scene_id=None,
+                       rows=()):
+    """Batched forward kinematics (fk.c): joint values (sampled from seed when
+    q is None), world link poses [n_joints][12], and for every (rows [n][16],
+    row_link [n], local [n][12]) in `rows` the rows with their linked entries
+    moved (FP64 copies).  Returns (q, link, [moved rows...])."""
+    jo = np.ascontiguousarray(joint_off, np.int32)
+    J = np.ascontiguousarray(joint, np.float64).reshape(-1, 24)
+    B = np.ascontiguousarray(base, np.float64).reshape(-1, 12)
+    n = int(len(jo) - 1)
+    nj = int(J.shape[0])
+    sid = None if scene_id is None else np.ascontiguousarray(scene_id, np.int32)
+    qq = np.zeros(nj, np.float64) if q is None else np.array(q, np.float64)
+    link = np.zeros((max(nj, 1), 12), np.float64)
+    lib().orc_fk_links(n, _p(jo), _p(J), _p(B), _p(sid), C.c_uint64(seed), int(q is None),
+                       _p(qq), _p(link))
+    moved = []
+    for table, row_link, local in rows:
+        R = np.array(table, np.float64).reshape(-1, 16).copy()
+        rl = np.ascontiguousarray(row_link, np.int32)
+        Lc = np.ascontiguousarray(local, np.float64).reshape(-1, 12)
+        lib().orc_fk_rows(int(R.shape[0]), _p(rl), _p(Lc), _p(link), _p(R))
+        moved.append(R)
+    return qq, link[:nj], moved
