@@ -204,6 +204,8 @@ def dense_leg(ctx, db, b, default_ncand, stream, seed=77, reps=3):
         xf += int(np.sum(C[live] * S))
         cands += total
     ms = []
+    torch.cuda.synchronize()
+    ctx.reset_counters()
     for rep in range(reps):
         tot = 0.0
         for oi, cand_off, total, cmax, npl, poses in launches:
@@ -215,11 +217,13 @@ def dense_leg(ctx, db, b, default_ncand, stream, seed=77, reps=3):
             torch.cuda.synchronize()
             tot += e0.elapsed_time(e1)
         ms.append(tot)
+    cnt = ctx.read_counters()
     db.n_placed.copy_(final)
     t = min(ms) * 1e-3
     flop = FLOP_PAIR * pairs + FLOP_BOX * boxes + FLOP_XFORM * xf
     return {"candidate_checks_per_s": cands / t, "pairs_per_s": pairs / t,
             "ms_per_pass": 1e3 * t, "launches": len(launches), "candidates": cands,
+            "refined_fraction": cnt["check_refined"] / (reps * max(cands, 1)),
             "roofline": {"bound": "alu", "achieved": flop / t / 1e12,
                          "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                          "frac": flop / t / 1e12 / PEAK_FP32_VALU_TFLOPS,

@@ -186,7 +186,10 @@ typedef struct {
     int64_t sphere_culls;  /* bounding-sphere vs placed-sphere pretests            */
     int64_t nonfinite;     /* decisions forced by non-finite input: objects failed
                             * by the place kernel, candidates by the dense check */
-    int64_t reserved[2];
+    int64_t check_refined; /* dense-check candidates with a sphere pair so close
+                            * that their pairs were evaluated again in the direct
+                            * form |p - q| (see scn_check_batch)                 */
+    int64_t reserved[1];
 } scn_counters;
 
 /* ---- context ---------------------------------------------------------- */

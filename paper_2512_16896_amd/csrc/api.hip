@@ -249,6 +249,7 @@ int scn_read_counters(scn_ctx* c, scn_counters* out, scn_stream stream) {
     out->invalid_scenes = h[scn::kInvalidScenes];
     out->sphere_culls = h[scn::kSphCulls];
     out->nonfinite = h[scn::kNonFinite];
+    out->check_refined = h[scn::kCheckRefined];
     if (out->error_word & scn::kErrCapacity)
         return fail(SCN_E_CAPACITY, "a scene exceeded the planned capacity and was skipped");
     if (out->error_word & scn::kErrGeometry)
@@ -287,7 +288,9 @@ int scn_check_batch(scn_ctx* c, const scn_batch* b, const int32_t* obj_idx,
     if (total > 0 && (!poses.x || !poses.y || !poses.z || !poses.yaw))
         return fail(SCN_E_INVALID_ARG, "pose arrays required");
     if (!(margin >= 0.f)) return fail(SCN_E_INVALID_ARG, "margin must be >= 0");
-    if ((int64_t)max_cand > 65535LL * 256) return fail(SCN_E_UNSUPPORTED, "max_cand too large");
+    if ((int64_t)max_cand > 65535LL * 128) return fail(SCN_E_UNSUPPORTED, "max_cand too large");
+    if (b->max_spheres_per_object > 256)
+        return fail(SCN_E_UNSUPPORTED, "max_spheres_per_object %d > 256", b->max_spheres_per_object);
     SCN_HIP(scn::launch_check(*b, obj_idx, cand_off, max_cand, poses, margin, clearance, collide,
                               c->d_counters, (hipStream_t)stream));
     return SCN_OK;

@@ -61,7 +61,8 @@ namespace scn {
 enum CounterSlot {
     kCandidates = 0, kSpherePairs = 1, kBoxPairs = 2, kGridSamples = 3, kAttempts = 4,
     kPlaced = 5, kErrorWord = 6, kTransforms = 7, kBoxCulls = 8, kObjCulls = 9,
-    kValidScenes = 10, kInvalidScenes = 11, kSphCulls = 12, kNonFinite = 13, kNumCounters = 16
+    kValidScenes = 10, kInvalidScenes = 11, kSphCulls = 12, kNonFinite = 13, kCheckRefined = 14,
+    kNumCounters = 16
 };
 enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2, kErrNonFinite = 4 };
 

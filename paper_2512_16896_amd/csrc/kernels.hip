@@ -2,8 +2,8 @@
 //
 //   k_reset   scene/record reset (graph-safe fill, no hipMemset)
 //   k_sample  candidate poses of one attempt, one lane per candidate
-//   k_check   dense exact clearance, one lane per candidate, obstacles
-//             wave-uniform (scalar loads from the read-only tables)
+//   k_check   dense exact clearance: sphere-pair distances on the FP32 matrix
+//             cores (one wave per candidate), boxes and grids on the vector ALU
 //   k_order_* longest-first scene order (counting sort by a work estimate)
 // The persistent fused place kernel is in place.hip.
 #include <climits>
@@ -93,11 +93,244 @@ hipError_t launch_sample(const scn_batch& b, const int32_t* obj_idx, const int32
 }
 
 // ---------------------------------------------------------------------------
-// Dense distance-mode check.  grid = (scenes, candidate tiles of 256); every
-// lane owns one candidate; spheres, boxes and placed spheres are uniform
-// across the wave, so they come through scalar loads.
+// Dense distance-mode check on the matrix cores.
+//
+// grid = (scenes, candidate tiles of kCheckTile); 4 waves per workgroup, and a
+// wave takes the tile's candidates one at a time (tile start + wave, + 4, ...).
+// For one candidate with world pose (Rw, tw), in the frame centred at tw:
+//   p'_k = Rw c_k              (template sphere k, |p'| <= the object's reach R)
+//   q'_j = q_j - tw            (placed sphere j of the scene)
+//   D[k][j] = |p'_k - q'_j|^2 = |p'_k|^2 - 2 p'_k . q'_j + |q'_j|^2
+// is a rank-4 product, so each 16 x 16 block of it is one
+// v_mfma_f32_16x16x4_f32:
+//   A row k    = (-2 p'x, -2 p'y, -2 p'z, |p'|^2)      lane l: row l % 16, entry l / 16
+//   B column j = (q'x, q'y, q'z, 1)                     lane l: column l % 16, entry l / 16
+//   C[.][j]    = |q'_j|^2                               lane l: rows 4 (l / 16) .. +3 of column l % 16
+// and the vector ALU keeps, per lane and row, min_j (sqrt|D| - r_j).
+//
+// Precision.  A pair close enough to matter has |p'| <= R and |q'| <= R + d,
+// so the expansion's terms and partial sums stay below 2 (R + d)^2 and its FP32
+// evaluation (the squares, the products and sums of the instruction) errs by
+// at most a few ulps of that: dD <= 8 * 2^-23 * 2 (R + 1 cm)^2.  The distance
+// sqrt(D + dD) is then within dD / (2 d) of the true one, under 8e-6 m once
+// d >= s_exact = dD / 1.6e-5 m (a few mm for objects of R ~ 0.2 m).  Every
+// candidate that has a pair closer than s_exact (tracked as the minimum of
+// sqrt|D| over all its pairs) has its pairs evaluated again in the direct
+// form |p' - q'| on the vector ALU; that happens to a small fraction of
+// candidates, since only near-concentric sphere pairs are that close.  |D|
+// under the root absorbs a tiny negative value of such a pair.
+//
+// The running minima are kept as the bit patterns of sqrt|D| + (O - r_j) with
+// O = 1 m + the scene's largest placed radius: that value is positive, so
+// unsigned integer order is float order (v_min3_u32, no NaN quieting of the
+// accumulator), and O is removed afterwards (FP32 rounding of the sum costs
+// at most half an ulp of O, ~6e-8 m).  Rows past the object's S spheres and
+// columns past the scene's placed spheres are padded with a huge |p'|^2 /
+// |q'|^2.  clearance = min over rows k of (row minimum - r_k), with the boxes
+// and grids (one sphere per lane, exact SDF and trilinear sample) folded in
+// before the wave minimum.
+constexpr int kCheckTile = 32;
+constexpr int kCheckWaves = 4;
+constexpr int kCheckMaxSpheres = 256;   // template spheres of one object (LDS copy)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct CheckIn {
+    const float4* stmpl;   // the object's template spheres, staged in LDS
+    const float4* placed;
+    __amdgpu_buffer_rsrc_t placed_rsrc;   // the scene's placed spheres; reads past them return 0
+    const float* box;
+    const float* grid;
+    const int32_t* grid_src;
+    const int64_t* grid_val_off;
+    const float* grid_val;
+    int S, first, pl_end, b0, b1, g0, g1;
+    float off;             // offset of the running minima (1 m + largest placed radius)
+    float s_exact;         // a pair closer than this sends the candidate to the direct form
+};
+
+// One candidate's sphere pairs for template rows [16 r0, 16 (r0 + NRT)):
+// min over those rows k and every placed sphere j of (|p_k - q_j| - r_j - r_k),
+// lane-partial (the caller takes the wave minimum).  smin receives the
+// smallest sqrt|D| seen (bit pattern).
+template <int NRT>
+__device__ __forceinline__ float pair_rows(const CheckIn& in, const float* Rw, const float* tw,
+                                           int r0, uint32_t& smin) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int col = lane & 15, grp = lane >> 4;
+    const float kBig = 1e30f;
+    const uint32_t kInfBits = 0x7f800000u;
+    // one-hot weights of this lane's operand entry (x, y, z, or the 4th):
+    // entry = sum of w_e * value_e, exact because the other products are +0
+    const float w0 = grp == 0 ? 1.f : 0.f, w1 = grp == 1 ? 1.f : 0.f;
+    const float w2 = grp == 2 ? 1.f : 0.f, w3 = grp == 3 ? 1.f : 0.f;
+    // A operands: row l % 16 of each 16-row tile, entry l / 16
+    float A[NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) {
+        const int k = 16 * (r0 + rt) + col;
+        const float4 c = in.stmpl[min(k, in.S - 1)];
+        const float ux = fmaf(Rw[0], c.x, fmaf(Rw[1], c.y, Rw[2] * c.z));
+        const float uy = fmaf(Rw[3], c.x, fmaf(Rw[4], c.y, Rw[5] * c.z));
+        const float uz = fmaf(Rw[6], c.x, fmaf(Rw[7], c.y, Rw[8] * c.z));
+        const float n2 = k < in.S ? fmaf(ux, ux, fmaf(uy, uy, uz * uz)) : kBig;
+        const float s2 = k < in.S ? -2.f : 0.f;
+        A[rt] = fmaf(w0 * s2, ux, fmaf(w1 * s2, uy, fmaf(w2 * s2, uz, w3 * n2)));
+    }
+    uint32_t acc[NRT][4];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[rt][i] = kInfBits;
+    uint32_t sm[NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) sm[rt] = kInfBits;
+    const int np = in.pl_end - in.first;
+    // two 16-column tiles per step (both loads in flight, and three-way
+    // minima); buffer reads past the scene's placed spheres return 0, and
+    // those columns are padded with a huge |q'|^2
+    for (int jb = 0; jb < np; jb += 32) {
+        float4 q[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            q[h] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                  in.placed_rsrc, 16 * (16 * h + col), 16 * jb, 0));
+        float bv[2], orj[2];
+        f32x4 cv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bool ok = jb + 16 * h + col < np;
+            const float qx = q[h].x - tw[0], qy = q[h].y - tw[1], qz = q[h].z - tw[2];
+            const float n2 = ok ? fmaf(qx, qx, fmaf(qy, qy, qz * qz)) : kBig;
+            orj[h] = ok ? in.off - q[h].w : in.off;
+            bv[h] = fmaf(w0, qx, fmaf(w1, qy, fmaf(w2, qz, w3)));
+            cv[h] = f32x4{n2, n2, n2, n2};
+        }
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) {
+            const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[rt], bv[0], cv[0], 0, 0, 0);
+            const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[rt], bv[1], cv[1], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float s0 = __builtin_amdgcn_sqrtf(fabsf(d0[i]));
+                const float s1 = __builtin_amdgcn_sqrtf(fabsf(d1[i]));
+                acc[rt][i] = min(acc[rt][i],
+                                 min(__float_as_uint(s0 + orj[0]), __float_as_uint(s1 + orj[1])));
+                sm[rt] = min(sm[rt], min(__float_as_uint(s0), __float_as_uint(s1)));
+            }
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) smin = min(smin, sm[rt]);
+    // rows 4 (l / 16) + i of each tile: remove the offset and the sphere's radius
+    float m = __builtin_huge_valf();
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 16 * (r0 + rt) + 4 * grp + i;
+            if (k < in.S && acc[rt][i] != kInfBits)
+                m = fminf(m, (__uint_as_float(acc[rt][i]) - in.off) - in.stmpl[k].w);
+        }
+    return m;
+}
+
+// The candidates t = t0, t0 + kCheckWaves, ... < t1 of one wave.  Returns how
+// many got a NaN clearance (non-finite input).
 template <bool kGrids>
-__global__ __launch_bounds__(256) void k_check(
+__device__ __forceinline__ unsigned check_candidates(const CheckIn& in, const Support& U,
+                                                     unsigned& nref,
+                                                     const float* __restrict__ px,
+                                                     const float* __restrict__ py,
+                                                     const float* __restrict__ pz,
+                                                     const float* __restrict__ pyaw, int t0,
+                                                     int t1, bool bad_wg, float margin,
+                                                     float* __restrict__ clr_out,
+                                                     uint8_t* __restrict__ col_out) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const float inf = __builtin_huge_valf();
+    const int nrt = (in.S + 15) >> 4;
+    unsigned nbad = 0;
+    for (int t = t0; t < t1; t += kCheckWaves) {
+        const float x = px[t], y = py[t], z = pz[t], yw = pyaw[t];
+        bool bad = bad_wg || !(__builtin_isfinite(x) & __builtin_isfinite(y) &
+                               __builtin_isfinite(z) & __builtin_isfinite(yw));
+        float sn, cs;
+        sincosf(yw, &sn, &cs);
+        // candidate -> world: Rw = R_u Rz(yaw), tw = R_u (x,y,z) + t_u
+        float Rw[9], tw[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            Rw[3 * r + 0] = fmaf(U.R[3 * r + 0], cs, U.R[3 * r + 1] * sn);
+            Rw[3 * r + 1] = fmaf(-U.R[3 * r + 0], sn, U.R[3 * r + 1] * cs);
+            Rw[3 * r + 2] = U.R[3 * r + 2];
+            tw[r] = fmaf(U.R[3 * r + 0], x, fmaf(U.R[3 * r + 1], y, fmaf(U.R[3 * r + 2], z, U.t[r])));
+        }
+        float m = inf;
+        if (in.first < in.pl_end) {
+            // 64 template rows (four 16-row tiles) per pass over the placed spheres
+            uint32_t smin = 0x7f800000u;
+            for (int r0 = 0; r0 < nrt; r0 += 4) {
+                const int n = nrt - r0;
+                m = fminf(m, n >= 4   ? pair_rows<4>(in, Rw, tw, r0, smin)
+                             : n == 3 ? pair_rows<3>(in, Rw, tw, r0, smin)
+                             : n == 2 ? pair_rows<2>(in, Rw, tw, r0, smin)
+                                      : pair_rows<1>(in, Rw, tw, r0, smin));
+            }
+            // a pair closer than s_exact: the candidate's pairs again, in the
+            // direct form (one template sphere per lane)
+            if (wave_min(__uint_as_float(smin)) < in.s_exact) {
+                ++nref;
+                m = inf;
+                for (int k = lane; k < in.S; k += kWave) {
+                    const float4 c = in.stmpl[k];
+                    const float ux = fmaf(Rw[0], c.x, fmaf(Rw[1], c.y, Rw[2] * c.z));
+                    const float uy = fmaf(Rw[3], c.x, fmaf(Rw[4], c.y, Rw[5] * c.z));
+                    const float uz = fmaf(Rw[6], c.x, fmaf(Rw[7], c.y, Rw[8] * c.z));
+                    float best = inf;
+                    for (int j = in.first; j < in.pl_end; ++j) {
+                        const float4 q = in.placed[j];
+                        const float dx = ux - (q.x - tw[0]), dy = uy - (q.y - tw[1]);
+                        const float dz = uz - (q.z - tw[2]);
+                        best = fminf(best, __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) - q.w);
+                    }
+                    m = fminf(m, best - c.w);
+                }
+            }
+        }
+        // boxes and grids: one template sphere per lane
+        for (int k = lane; k < in.S; k += kWave) {
+            const float4 c = in.stmpl[k];
+            const float wx = fmaf(Rw[0], c.x, fmaf(Rw[1], c.y, fmaf(Rw[2], c.z, tw[0])));
+            const float wy = fmaf(Rw[3], c.x, fmaf(Rw[4], c.y, fmaf(Rw[5], c.z, tw[1])));
+            const float wz = fmaf(Rw[6], c.x, fmaf(Rw[7], c.y, fmaf(Rw[8], c.z, tw[2])));
+            float best = inf;
+            for (int bx = in.b0; bx < in.b1; ++bx)
+                best = fminf(best, box_sdf(in.box + 16 * bx, wx, wy, wz));
+            if (kGrids) {
+                for (int g = in.g0; g < in.g1; ++g) {
+                    const float* G = in.grid + 24 * g;
+                    const float v =
+                        grid_sample(G, in.grid_val + in.grid_val_off[in.grid_src[g]], wx, wy, wz);
+                    bad |= v != v;
+                    best = fminf(best, v);
+                }
+            }
+            m = fminf(m, best - c.w);
+        }
+        const float clr_w = wave_min(m);
+        bad = __ballot(bad) != 0;
+        const float clr = bad ? __builtin_nanf("") : clr_w;
+        if (lane == 0) {
+            if (clr_out) clr_out[t] = clr;
+            if (col_out) col_out[t] = clr >= margin ? 0 : 1;
+        }
+        nbad += bad ? 1 : 0;
+    }
+    return nbad;
+}
+
+template <bool kGrids>
+__global__ __launch_bounds__(64 * kCheckWaves) __attribute__((amdgpu_waves_per_eu(5))) void k_check(
     const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
     const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
     const float* __restrict__ sup, const int32_t* __restrict__ box_off,
@@ -109,15 +342,16 @@ __global__ __launch_bounds__(256) void k_check(
     const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz,
     const float* __restrict__ pyaw, float margin, float* __restrict__ clr_out,
     uint8_t* __restrict__ col_out, unsigned long long* __restrict__ counters) {
+    __shared__ float4 s_tmpl[kCheckMaxSpheres];
+    __shared__ float s_rmax[kCheckWaves];
     const int s = blockIdx.x;
     const int o = obj_idx[s];
     if (o < obj_off[s] || o >= obj_off[s + 1]) return;   // -1 or not an object of scene s
     const int c0 = cand_off[s], c1 = cand_off[s + 1];
-    const int tbase = c0 + blockIdx.y * blockDim.x;
+    const int tbase = c0 + blockIdx.y * kCheckTile;
     if (tbase >= c1) return;
-    const int t = tbase + threadIdx.x;
-    const bool live = t < c1;
-    const int tt = live ? t : c1 - 1;
+    const int tend = min(c1, tbase + kCheckTile);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 
     const int oo = obj_off[s];
     const int first = sph_off[oo];
@@ -125,77 +359,56 @@ __global__ __launch_bounds__(256) void k_check(
     const int b0 = box_off[s], b1 = box_off[s + 1];
     int g0 = 0, g1 = 0;
     if (kGrids) { g0 = grid_off[s]; g1 = grid_off[s + 1]; }
+    const int k0 = sph_off[o], S = sph_off[o + 1] - k0;
+    if (S > kCheckMaxSpheres) return;    // refused on the host
     // Non-finite input makes a candidate collide with a NaN clearance: the
     // object's support row and spheres, the scene's box and grid rows and
     // placed spheres (shared by the workgroup), the candidate's own pose, and
-    // any grid sample that reads a non-finite node.
+    // any grid sample that reads a non-finite node.  The same pass stages the
+    // template in LDS and finds the largest placed radius.
     int bad_in = threadIdx.x < 16 ? !__builtin_isfinite(sup[16 * obj_sup[o] + threadIdx.x]) : 0;
-    for (int k = sph_off[o] + threadIdx.x; k < sph_off[o + 1]; k += blockDim.x)
-        bad_in |= !finite4(tmpl[k]);
+    for (int k = threadIdx.x; k < S; k += blockDim.x) {
+        const float4 v = tmpl[k0 + k];
+        bad_in |= !finite4(v);
+        s_tmpl[k] = v;
+    }
     for (int bx = b0 + threadIdx.x; bx < b1; bx += blockDim.x) bad_in |= !all_finite(box + 16 * bx, 15);
     for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) bad_in |= !all_finite(grid + 24 * g, 19);
-    for (int q = first + threadIdx.x; q < pl_end; q += blockDim.x) bad_in |= !finite4(placed[q]);
-    bool bad = __syncthreads_or(bad_in) != 0;
+    float rmax = 0.f;
+    for (int q = first + threadIdx.x; q < pl_end; q += blockDim.x) {
+        const float4 v = placed[q];
+        bad_in |= !finite4(v);
+        rmax = fmaxf(rmax, fabsf(v.w));
+    }
+    rmax = wave_max(rmax);
+    if (lane == 0) s_rmax[wave] = rmax;
+    const bool bad_wg = __syncthreads_or(bad_in) != 0;
+    for (int w = 0; w < kCheckWaves; ++w) rmax = fmaxf(rmax, s_rmax[w]);
 
+    // the object's reach about its frame origin, which bounds |p'| (see above)
+    float reach = 0.f;
+    for (int k = lane; k < S; k += kWave) {
+        const float4 c = s_tmpl[k];
+        reach = fmaxf(reach, __builtin_amdgcn_sqrtf(fmaf(c.x, c.x, fmaf(c.y, c.y, c.z * c.z))));
+    }
+    reach = wave_max(reach) + 0.01f;
+    const float s_exact = fmaxf(1e-4f, 8.f * 1.1920929e-7f * 2.f * reach * reach / 1.6e-5f);
+    // a buffer resource over the scene's placed spheres (CDNA dword 3 of a raw
+    // buffer: 0x00020000); a read at or past pl_end returns zeros
+    const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(placed + first), (short)0, 16 * (pl_end - first), 0x00020000);
+    const CheckIn in{s_tmpl, placed, prs, box, grid, grid_src, grid_val_off, grid_val,
+                     S, first, pl_end, b0, b1, g0, g1, 1.f + (bad_wg ? 0.f : rmax), s_exact};
     const Support U = load_support(sup, obj_sup[o]);
-    float sn, cs;
-    const float x = px[tt], y = py[tt], z = pz[tt], yw = pyaw[tt];
-    bad |= !(__builtin_isfinite(x) & __builtin_isfinite(y) & __builtin_isfinite(z) &
-             __builtin_isfinite(yw));
-    sincosf(yw, &sn, &cs);
-    // candidate -> world: Rw = R_u Rz(yaw), tw = R_u (x,y,z) + t_u
-    float Rw[9], tw[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        Rw[3 * r + 0] = fmaf(U.R[3 * r + 0], cs, U.R[3 * r + 1] * sn);
-        Rw[3 * r + 1] = fmaf(-U.R[3 * r + 0], sn, U.R[3 * r + 1] * cs);
-        Rw[3 * r + 2] = U.R[3 * r + 2];
-        tw[r] = fmaf(U.R[3 * r + 0], x, fmaf(U.R[3 * r + 1], y, fmaf(U.R[3 * r + 2], z, U.t[r])));
-    }
-    float clr = __builtin_huge_valf();
-    for (int k = sph_off[o]; k < sph_off[o + 1]; ++k) {
-        const float4 c = tmpl[k];
-        const float wx = fmaf(Rw[0], c.x, fmaf(Rw[1], c.y, fmaf(Rw[2], c.z, tw[0])));
-        const float wy = fmaf(Rw[3], c.x, fmaf(Rw[4], c.y, fmaf(Rw[5], c.z, tw[1])));
-        const float wz = fmaf(Rw[6], c.x, fmaf(Rw[7], c.y, fmaf(Rw[8], c.z, tw[2])));
-        float best = __builtin_huge_valf();
-        for (int bx = b0; bx < b1; ++bx) best = fminf(best, box_sdf(box + 16 * bx, wx, wy, wz));
-        if (kGrids) {
-            for (int g = g0; g < g1; ++g) {
-                const float* G = grid + 24 * g;
-                const float v = grid_sample(G, grid_val + grid_val_off[grid_src[g]], wx, wy, wz);
-                bad |= v != v;
-                best = fminf(best, v);
-            }
-        }
-        int j = first;
-        for (; j + 4 <= pl_end; j += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const float4 q = placed[j + u];
-                const float dx = wx - q.x, dy = wy - q.y, dz = wz - q.z;
-                const float d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-                best = fminf(best, d - q.w);
-            }
-        }
-        for (; j < pl_end; ++j) {
-            const float4 q = placed[j];
-            const float dx = wx - q.x, dy = wy - q.y, dz = wz - q.z;
-            const float d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-            best = fminf(best, d - q.w);
-        }
-        clr = fminf(clr, best - c.w);
-    }
-    if (bad) clr = __builtin_nanf("");
-    if (live) {
-        if (clr_out) clr_out[t] = clr;
-        if (col_out) col_out[t] = clr >= margin ? 0 : 1;
-    }
-    const unsigned long long nbad = __ballot(bad && live);
-    if (nbad && (threadIdx.x & (kWave - 1)) == 0) {
+    unsigned nref = 0;
+    const unsigned nbad = check_candidates<kGrids>(in, U, nref, px, py, pz, pyaw,
+                                                   tbase + uniform_int(wave), tend, bad_wg,
+                                                   margin, clr_out, col_out);
+    if (nbad && lane == 0) {
         atomicOr(counters + kErrorWord, (unsigned long long)kErrNonFinite);
-        atomicAdd(counters + kNonFinite, (unsigned long long)__popcll(nbad));
+        atomicAdd(counters + kNonFinite, (unsigned long long)nbad);
     }
+    if (nref && lane == 0) atomicAdd(counters + kCheckRefined, (unsigned long long)nref);
 }
 
 // Any non-finite node value in the grid assets sets the non-finite error bit
@@ -224,20 +437,20 @@ hipError_t launch_check(const scn_batch& b, const int32_t* obj_idx, const int32_
                         int max_cand, scn_poses P, float margin, float* clr, uint8_t* col,
                         int64_t* counters, hipStream_t st) {
     if (b.n_scenes == 0 || max_cand == 0) return hipSuccess;
-    dim3 grid(b.n_scenes, (max_cand + 255) / 256);
+    dim3 grid(b.n_scenes, (max_cand + kCheckTile - 1) / kCheckTile);
     auto* ctr = (unsigned long long*)counters;
     if (b.grid_off) {
         hipError_t e = launch_scan_grid_values(b, counters, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_check<true>, grid, dim3(256), 0, st, b.obj_off, b.sph_off,
-                           (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box, b.grid_off,
-                           b.grid, b.grid_src, b.grid_val_off, b.grid_val,
+        hipLaunchKernelGGL(k_check<true>, grid, dim3(64 * kCheckWaves), 0, st, b.obj_off,
+                           b.sph_off, (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box,
+                           b.grid_off, b.grid, b.grid_src, b.grid_val_off, b.grid_val,
                            (const float4*)b.placed, b.n_placed, obj_idx, cand_off, P.x, P.y, P.z,
                            P.yaw, margin, clr, col, ctr);
     } else {
-        hipLaunchKernelGGL(k_check<false>, grid, dim3(256), 0, st, b.obj_off, b.sph_off,
-                           (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box, nullptr,
-                           nullptr, nullptr, nullptr, nullptr, (const float4*)b.placed,
+        hipLaunchKernelGGL(k_check<false>, grid, dim3(64 * kCheckWaves), 0, st, b.obj_off,
+                           b.sph_off, (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box,
+                           nullptr, nullptr, nullptr, nullptr, nullptr, (const float4*)b.placed,
                            b.n_placed, obj_idx, cand_off, P.x, P.y, P.z, P.yaw, margin, clr, col,
                            ctr);
     }

@@ -63,7 +63,8 @@ class Counters(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "candidates", "sphere_pairs", "box_pairs", "grid_samples", "attempts", "placed",
         "error_word", "transforms", "box_culls", "object_culls", "valid_scenes",
-        "invalid_scenes", "sphere_culls", "nonfinite")] + [("reserved", C.c_int64 * 2)]
+        "invalid_scenes", "sphere_culls", "nonfinite", "check_refined")] + \
+        [("reserved", C.c_int64 * 1)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}
