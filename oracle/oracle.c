@@ -22,8 +22,11 @@
  * Philox counter layout) are the project's and are listed in the design notes.
  *
  * Everything is FP64 except the random bits, which are exact integers.
- * There is no culling, no early exit inside a candidate and no blocking: every
- * candidate's clearance is the plain minimum over all sphere/obstacle pairs.
+ * There is no culling and no blocking: every candidate's clearance is the
+ * plain minimum over all sphere/obstacle pairs.  (orc_generate's optional
+ * early_exit mode, used by tests that replay large scenes, stops a candidate
+ * at its first term below margin - band: such a candidate collides and is not
+ * banded whatever its exact minimum, so every output is the same.)
  */
 #include <math.h>
 #include <stdint.h>
@@ -91,6 +94,9 @@ typedef struct {
     int      default_ncand;
     double   band;          /* |clearance - margin| < band marks a candidate as banded */
     int      max_steps;     /* place at most this many objects per scene (<=0: all) */
+    int      early_exit;    /* nonzero: a candidate's clearance stops at its first term
+                               below margin - band (the candidate collides and is not
+                               banded either way; results are identical, only faster) */
 } orc_gen_args;
 
 /* Pose of a candidate in its support frame: position (x,y,z), yaw about z. */
@@ -199,6 +205,9 @@ static int finite_n(const double *v, int n)
 /* Clearance of one placed sphere set against the obstacles of scene s:
  * min over its spheres of (signed distance to every box, grid and already
  * placed sphere) minus the sphere radius.  +inf with no obstacles.
+ * stop_below (-inf: never): return the first term found below it instead of
+ * the minimum.  The minimum is then below stop_below too, which is all a
+ * caller that only compares the minimum with stop_below needs to know.
  *
  * Non-finite input (the paper is silent; the project's reading): a candidate
  * whose world spheres, or any box row, grid instance row, placed sphere or
@@ -206,7 +215,7 @@ static int finite_n(const double *v, int n)
  * clearance: the result is NaN, which no margin test accepts, so the
  * candidate collides.                                                        */
 static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
-                        const double *placed, int n_placed_sph)
+                        const double *placed, int n_placed_sph, double stop_below)
 {
     double best = INFINITY;
     if (!finite_n(sph, 4 * n_sph)) return NAN;
@@ -222,6 +231,7 @@ static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
             const double *B = b->box + 16 * bx;
             double v = orc_box_sdf(B, B + 9, B + 12, p) - p[3];
             if (v < best) best = v;
+            if (v < stop_below) return v;
         }
         if (b->grid_off) {
             for (int g = b->grid_off[s]; g < b->grid_off[s + 1]; ++g) {
@@ -234,6 +244,7 @@ static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
                 double v = orc_grid_sample(b->grid_val[b->grid_src[g]], dims, G + 12, G[15], pg) - p[3];
                 if (isnan(v)) return NAN;
                 if (v < best) best = v;
+                if (v < stop_below) return v;
             }
         }
         for (int j = 0; j < n_placed_sph; ++j) {
@@ -241,6 +252,7 @@ static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
             double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
             double v = sqrt(dx * dx + dy * dy + dz * dz) - q[3] - p[3];
             if (v < best) best = v;
+            if (v < stop_below) return v;
         }
     }
     return best;
@@ -286,7 +298,7 @@ void orc_check(const orc_batch *b, const int32_t *obj_idx, const int32_t *cand_o
         for (int t = cand_off[s]; t < cand_off[s + 1]; ++t) {
             orc_pose p = {x[t], y[t], z[t], yaw[t]};
             for (int k = 0; k < ns; ++k) world_sphere(b, o, b->sph_off[o] + k, p, sph + 4 * k);
-            clr[t] = clearance(b, s, sph, ns, placed + 4 * first, n_pl);
+            clr[t] = clearance(b, s, sph, ns, placed + 4 * first, n_pl, -INFINITY);
         }
         free(sph);
     }
@@ -336,7 +348,8 @@ void orc_generate(const orc_batch *b, const orc_gen_args *g, orc_gen_out *out)
                 for (int i = 0; i < nc; ++i) {
                     orc_pose p = sample_pose(b, g->seed, s, step, o, a, i);
                     for (int k = 0; k < ns; ++k) world_sphere(b, o, b->sph_off[o] + k, p, sph + 4 * k);
-                    double cl = clearance(b, s, sph, ns, out->placed + 4 * first, n_pl);
+                    double cl = clearance(b, s, sph, ns, out->placed + 4 * first, n_pl,
+                                          g->early_exit ? g->margin - g->band : -INFINITY);
                     ++ncand;
                     if (fabs(cl - g->margin) < g->band) banded = 1;
                     if (cl >= g->margin) {   /* collision-free: clearance not below the margin */

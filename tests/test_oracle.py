@@ -371,3 +371,22 @@ def test_grid_sampler_nodes_and_affine_fields(orc):
         assert orc.grid_sample(aff.astype(np.float64), origin, h, p) == pytest.approx(want, abs=2e-6)
     # outside the node box: nothing there
     assert math.isinf(orc.grid_sample(vals, origin, h, origin - 0.01))
+
+
+@pytest.mark.parametrize("which", ["batched", "uneven", "shelves"])
+def test_early_exit_mode_gives_identical_results(orc, which):
+    """The replay mode that stops a candidate at its first term below
+    margin - band decides every candidate the same way (and the chosen
+    candidates' clearances are still the full minima)."""
+    from paper_2512_16896_amd import scenegen as sg
+    if which == "batched":
+        b, nc = sg.batched_scenes(6, seed=8), 1024
+    elif which == "uneven":
+        b, nc = sg.uneven_batch(6, seed=8, n_obj=(5, 14), n_cand=(64, 512)), 512
+    else:
+        b, nc = sg.shelf_scenes(2, seed=8, n_obj=24), 2048
+    a = orc.generate(b, seed=3, default_ncand=nc)
+    e = orc.generate(b, seed=3, default_ncand=nc, early_exit=True)
+    for k in a:
+        assert np.array_equal(a[k], e[k], equal_nan=True), k
+    assert np.any(a["status"] == 1)
