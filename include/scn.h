@@ -239,8 +239,9 @@ int scn_set_workspace(scn_ctx *ctx, void *ptr, size_t bytes);
 int scn_reset_counters(scn_ctx *ctx, scn_stream stream);
 /* Synchronize `stream` and copy the counters to *out (host).  Returns
  * SCN_E_CAPACITY if bit 0 of the device error word is set, SCN_E_INVALID_ARG
- * if bit 1 is (a scene broke the declared SCN_GEOM_YAW geometry); *out is
- * filled either way.                                                        */
+ * if bit 1 is (a scene broke the declared SCN_GEOM_YAW geometry) or bit 3 (a
+ * joint or link index out of range in scn_forward_kinematics),
+ * SCN_E_NONFINITE if bit 2 is (non-finite input); *out is filled either way. */
 int scn_read_counters(scn_ctx *ctx, scn_counters *out, scn_stream stream);
 
 /* ---- the hot path ------------------------------------------------------ */
@@ -308,6 +309,48 @@ int scn_generate_scenes(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
 #define SCN_NOALLOC_MAX_SCENES (1 << 20)
 int scn_generate_scenes_noalloc(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
                                 scn_stream stream);
+
+/* ---- articulated parts: batched forward kinematics --------------------- */
+
+/* Articulated furniture of a batch (Sec. IV-B: one transform per scene
+ * instance on every scene-graph edge, moved by a batched forward-kinematics
+ * function; Sec. V-A: drawer joint states randomized per scene).  Device
+ * arrays, caller-owned:
+ *   joint_off [n_scenes+1]   joints of scene s, in topological order
+ *   joint     [n_joints][24] type (0 prismatic, 1 revolute), parent (index of
+ *                            an earlier joint of the same scene, -1 = the
+ *                            scene's base), lower, upper, axis[3] (in the joint
+ *                            frame; unit length for revolute joints, the step
+ *                            per unit of q for prismatic ones), pad,
+ *                            R_j[9], t_j[3] (joint frame in the parent link
+ *                            frame), pad[4]
+ *   base      [n_scenes][12] R[9], t[3]: world pose of each scene's base link */
+typedef struct {
+    int32_t n_scenes, n_joints;
+    const int32_t *joint_off;
+    const float *joint;
+    const float *base;
+} scn_joints;
+
+/* Joint values and link poses of every scene, then the rows carried by links:
+ *   q     [n_joints] (device) joint values: drawn when sample_q != 0 as
+ *         lower + u (upper - lower), u from Philox4x32-10 (key = seed, counter
+ *         = (joint index within its scene, 0x30000, 0, scene)); read otherwise
+ *   link  [n_joints][12] (device, out) world pose of each joint's child link:
+ *         link_i = link_parent * [R_j | t_j] * M(q_i), M = translation by q a
+ *         (prismatic) or rotation by q about a (revolute, Rodrigues)
+ *   box rows b with box_link[b] >= 0 (global joint index) get R and centre of
+ *         link[box_link[b]] * box_local[b] (box_local [n_box][12]: R[9], t[3]);
+ *         half extents are kept.  support rows likewise (R and t; sizes kept).
+ *         box_link / sup_link NULL: no rows of that kind move.
+ * A parent that is not an earlier joint of its scene, or a link index >=
+ * n_joints, leaves that link (NaN) / row untouched and is reported as
+ * SCN_E_INVALID_ARG by the next scn_read_counters.  Asynchronous.          */
+int scn_forward_kinematics(scn_ctx *ctx, const scn_joints *joints, uint64_t seed, int32_t sample_q,
+                           float *q, float *link, int32_t n_box, const int32_t *box_link,
+                           const float *box_local, float *box, int32_t n_sup,
+                           const int32_t *sup_link, const float *sup_local, float *sup,
+                           scn_stream stream);
 
 /* ---- uneven batching: autotuned schedules ------------------------------ */
 

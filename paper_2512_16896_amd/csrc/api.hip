@@ -255,6 +255,10 @@ int scn_read_counters(scn_ctx* c, scn_counters* out, scn_stream stream) {
     if (out->error_word & scn::kErrGeometry)
         return fail(SCN_E_INVALID_ARG,
                     "a scene breaks the batch's declared SCN_GEOM_YAW geometry and was marked invalid");
+    if (out->error_word & scn::kErrBadJoint)
+        return fail(SCN_E_INVALID_ARG,
+                    "a joint's parent is not an earlier joint of its scene, or a row's link index "
+                    "is out of range (those links and rows were not computed)");
     if (out->error_word & scn::kErrNonFinite)
         return fail(SCN_E_NONFINITE,
                     "non-finite input: the candidates tested against it collided (%lld counted)",

@@ -64,7 +64,7 @@ enum CounterSlot {
     kValidScenes = 10, kInvalidScenes = 11, kSphCulls = 12, kNonFinite = 13, kCheckRefined = 14,
     kNumCounters = 16
 };
-enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2, kErrNonFinite = 4 };
+enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2, kErrNonFinite = 4, kErrBadJoint = 8 };
 
 // Bytes of dynamic LDS the place kernel adds for a scene's depth map (batches
 // without grids).
@@ -159,5 +159,10 @@ hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);
 
 hipError_t launch_longest_first(const scn_batch& b, int32_t* order, int32_t* hist,
                                 hipStream_t st);
+// batched forward kinematics (fk.hip)
+hipError_t launch_fk(const scn_joints& j, uint64_t seed, int sample, float* q, float* link,
+                     int n_box, const int32_t* box_link, const float* box_local, float* box,
+                     int n_sup, const int32_t* sup_link, const float* sup_local, float* sup,
+                     int64_t* counters, hipStream_t st);
 
 }  // namespace scn

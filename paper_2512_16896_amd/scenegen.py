@@ -347,6 +347,98 @@ def shelf_scenes(n_scenes: int = 65536, seed: int = 0, n_obj: int = 100, n_sph: 
                     n_shelves=n_shelves, seed=seed))
 
 
+# Drawer cabinet (base link frame: x out of the front, z up; metres).  Static
+# boards as (centre, half extents); each drawer is a prismatic joint along +x
+# at height z_d with its bottom as a support surface and four walls as boxes,
+# given in the drawer link frame.
+CABINET_BOARDS = (((0.0, 0.31, 0.42), (0.25, 0.01, 0.42)),     # left side
+                  ((0.0, -0.31, 0.42), (0.25, 0.01, 0.42)),    # right side
+                  ((-0.26, 0.0, 0.42), (0.01, 0.30, 0.42)),    # back
+                  ((0.0, 0.0, 0.83), (0.25, 0.30, 0.01)),      # top
+                  ((0.0, 0.0, 0.42), (0.25, 0.30, 0.01)),      # middle board
+                  ((0.0, 0.0, 0.01), (0.25, 0.30, 0.01)))      # bottom board
+DRAWER_Z = (0.05, 0.46)
+DRAWER_TRAVEL = (0.0, 0.35)
+DRAWER_HALF = (0.21, 0.26)           # support half sizes of a drawer bottom
+DRAWER_WALLS = (((0.23, 0.0, 0.09), (0.01, 0.29, 0.09)),      # front panel
+                ((-0.22, 0.0, 0.07), (0.01, 0.27, 0.07)),     # back
+                ((0.0, 0.27, 0.07), (0.22, 0.01, 0.07)),      # left
+                ((0.0, -0.27, 0.07), (0.22, 0.01, 0.07)))     # right
+
+
+def drawer_scenes(n_scenes: int = 4096, seed: int = 0, n_obj_per_drawer: int = 4,
+                  n_sph: int = 32, n_cand: int = 256, side=(0.04, 0.12),
+                  rad=(0.01, 0.03)) -> SceneBatch:
+    """Every scene: a two-drawer cabinet at a random world pose (yaw about z,
+    translation); the drawers are prismatic joints along the cabinet's +x with
+    a travel drawn per scene by the forward kinematics; n_obj_per_drawer
+    objects of n_sph spheres (cube side ~ U(side), radii ~ U(rad)) go into
+    each drawer, resting on its bottom.  The batch's box and support rows of
+    the drawers are left zero: they are the forward kinematics' output.
+    b.params["art"] holds the articulation: joint_off, joint [n_j][24], base
+    [n][12], box_link / box_local, sup_link / sup_local (scenegen layout of
+    the scn_joints arrays)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0xD2A3]))
+    nd = len(DRAWER_Z)
+    n_obj = nd * n_obj_per_drawer
+    yaw = rng.uniform(0, 2 * np.pi, n_scenes)
+    R = rotz(yaw)
+    t = np.stack([rng.uniform(-1, 1, n_scenes), rng.uniform(-1, 1, n_scenes),
+                  np.zeros(n_scenes)], 1)
+    base = np.concatenate([R.reshape(n_scenes, 9), t], 1)
+    nb_static, nb_drawer = len(CABINET_BOARDS), len(DRAWER_WALLS)
+    B = nb_static + nd * nb_drawer
+    box = np.zeros((n_scenes * B, 16), np.float64)
+    box_link = -np.ones(n_scenes * B, np.int32)
+    box_local = np.zeros((n_scenes * B, 12), np.float64)
+    for k, (c, h) in enumerate(CABINET_BOARDS):
+        rows = np.arange(n_scenes) * B + k
+        box[rows, 0:9] = R.reshape(n_scenes, 9)
+        box[rows, 9:12] = np.einsum('nij,j->ni', R, np.asarray(c)) + t
+        box[rows, 12:15] = h
+    eye = np.eye(3).ravel()
+    for d in range(nd):
+        for w, (c, h) in enumerate(DRAWER_WALLS):
+            rows = np.arange(n_scenes) * B + nb_static + d * nb_drawer + w
+            box[rows, 12:15] = h
+            box_link[rows] = np.arange(n_scenes) * nd + d
+            box_local[rows, 0:9] = eye
+            box_local[rows, 9:12] = c
+    joint = np.zeros((n_scenes * nd, 24), np.float64)
+    for d in range(nd):
+        rows = np.arange(n_scenes) * nd + d
+        joint[rows, 0] = 0           # prismatic
+        joint[rows, 1] = -1          # hangs from the base
+        joint[rows, 2:4] = DRAWER_TRAVEL
+        joint[rows, 4:7] = (1.0, 0.0, 0.0)
+        joint[rows, 8:17] = eye
+        joint[rows, 17:20] = (0.0, 0.0, DRAWER_Z[d])
+    sup = np.zeros((n_scenes * nd, 16), np.float64)
+    sup[:, 12] = DRAWER_HALF[0]
+    sup[:, 13] = DRAWER_HALF[1]
+    sup_link = np.arange(n_scenes * nd, dtype=np.int32)
+    sup_local = np.zeros((n_scenes * nd, 12), np.float64)
+    sup_local[:, 0:9] = eye
+    sph_off, tmpl = _templates(rng, n_scenes * n_obj, n_sph, side, rad)
+    obj_off = np.arange(n_scenes + 1, dtype=np.int64) * n_obj
+    perm = _footprint_order(obj_off, sph_off, tmpl)
+    sph_off, tmpl = _reorder_objects(perm, sph_off, tmpl)
+    obj_sup = (np.repeat(np.arange(n_scenes), n_obj) * nd +
+               np.tile(np.arange(n_obj) % nd, n_scenes)).astype(np.int32)
+    art = dict(joint_off=(np.arange(n_scenes + 1) * nd).astype(np.int32),
+               joint=joint.astype(np.float32), base=base.astype(np.float32),
+               box_link=box_link, box_local=box_local.astype(np.float32),
+               sup_link=sup_link, sup_local=sup_local.astype(np.float32))
+    return SceneBatch(
+        obj_off=obj_off.astype(np.int32), sph_off=sph_off.astype(np.int32),
+        tmpl=tmpl.astype(np.float32), obj_sup=obj_sup,
+        obj_ncand=np.full(n_scenes * n_obj, n_cand, np.int32), sup=sup.astype(np.float32),
+        box_off=(np.arange(n_scenes + 1) * B).astype(np.int32), box=box.astype(np.float32),
+        name=f"drawers-{n_scenes}",
+        params=dict(n_scenes=n_scenes, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand, seed=seed,
+                    art=art))
+
+
 def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
     """The scenes `scenes` of a batch as a batch of their own, plus the
     original scene indices (which the random-number counters must keep)."""

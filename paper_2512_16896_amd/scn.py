@@ -48,6 +48,11 @@ class _Batch(C.Structure):
             "placed", "n_placed", "status", "rec")]
 
 
+class _Joints(C.Structure):
+    _fields_ = [("n_scenes", C.c_int32), ("n_joints", C.c_int32), ("joint_off", C.c_void_p),
+                ("joint", C.c_void_p), ("base", C.c_void_p)]
+
+
 class _Poses(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("yaw", C.c_void_p)]
 
@@ -104,6 +109,8 @@ def _load():
         "scn_place_step": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp, vp],
         "scn_generate_scenes": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp],
         "scn_generate_scenes_noalloc": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp],
+        "scn_forward_kinematics": [vp, C.POINTER(_Joints), u64, i32, vp, vp, i32, vp, vp, vp,
+                                   i32, vp, vp, vp, vp],
         "scn_autotune": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), C.POINTER(C.c_int32),
                          C.POINTER(C.c_float), vp],
         "scn_autotune_save": [vp, C.c_char_p],
@@ -137,7 +144,7 @@ EXPORTS = ("scn_ctx_create", "scn_ctx_destroy", "scn_status_string", "scn_last_e
            "scn_workspace_bytes", "scn_set_workspace", "scn_reset_counters",
            "scn_read_counters", "scn_sample_poses", "scn_check_batch",
            "scn_reset_scenes", "scn_place_step", "scn_generate_scenes",
-           "scn_generate_scenes_noalloc", "scn_autotune",
+           "scn_generate_scenes_noalloc", "scn_forward_kinematics", "scn_autotune",
            "scn_autotune_save", "scn_autotune_load", "scn_mlp_init", "scn_mlp_forward",
            "scn_mlp_backward", "scn_mlp_train_step", "scn_descriptors", "scn_heightmaps",
            "scn_features", "scn_proposal_topk", "scn_harvest_labels",
@@ -327,6 +334,14 @@ class DeviceBatch:
                      "placed", "n_placed", "status", "rec"):
             setattr(c, name, None if getattr(self, name) is None else getattr(self, name).data_ptr())
 
+    def refresh_geometry(self):
+        """Re-derive the declared geometry class from the device's support and
+        box rows (after a call that rewrote them, e.g. forward kinematics)."""
+        import dataclasses
+        h = dataclasses.replace(self.host, sup=self.sup.cpu().numpy(),
+                                box=self.box.cpu().numpy()[:self.host.n_boxes])
+        self.c.geometry = GEOM_YAW if geometry_is_yaw(h) else GEOM_GENERAL
+
     # -- views of the state ------------------------------------------------
     def records(self):
         r = self.rec.cpu()
@@ -379,6 +394,41 @@ def generate_scenes(ctx: Context, db: DeviceBatch, args: GenArgs, stream=None):
     ctx.ensure_workspace(workspace_bytes(WS_GENERATE, db))
     a = args.c()
     _ok(_lib.scn_generate_scenes(ctx.h, C.byref(db.c), C.byref(a), _stream(stream)))
+
+
+class Joints:
+    """Device copies of a batch's articulation (scn_joints) and of the rows the
+    links carry, plus the joint values and link poses FK writes."""
+
+    def __init__(self, art: dict, device: str = "cuda"):
+        dev = torch.device(device)
+        t = lambda a, dt: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+        self.joint_off = t(art["joint_off"], torch.int32)
+        self.joint = t(np.asarray(art["joint"]).reshape(-1, 24), torch.float32)
+        self.base = t(np.asarray(art["base"]).reshape(-1, 12), torch.float32)
+        self.box_link = t(art.get("box_link"), torch.int32)
+        self.box_local = t(art.get("box_local"), torch.float32)
+        self.sup_link = t(art.get("sup_link"), torch.int32)
+        self.sup_local = t(art.get("sup_local"), torch.float32)
+        n, nj = int(self.joint_off.numel() - 1), int(self.joint.shape[0])
+        self.q = torch.zeros(max(nj, 1), dtype=torch.float32, device=dev)
+        self.link = torch.zeros((max(nj, 1), 12), dtype=torch.float32, device=dev)
+        self.c = _Joints(n, nj, self.joint_off.data_ptr(), self.joint.data_ptr(),
+                         self.base.data_ptr())
+
+
+def forward_kinematics(ctx: Context, joints: Joints, db: Optional["DeviceBatch"] = None,
+                       seed: int = 0, sample: bool = True, stream=None):
+    """scn_forward_kinematics: joint values (drawn from seed, or joints.q as
+    set), link poses, and the box / support rows of db that links carry."""
+    nb = 0 if db is None or joints.box_link is None else int(joints.box_link.numel())
+    ns = 0 if db is None or joints.sup_link is None else int(joints.sup_link.numel())
+    _ok(_lib.scn_forward_kinematics(
+        ctx.h, C.byref(joints.c), int(seed) & (2 ** 64 - 1), int(bool(sample)), _ptr(joints.q),
+        _ptr(joints.link), nb, _ptr(joints.box_link) if nb else None,
+        _ptr(joints.box_local) if nb else None, _ptr(db.box) if nb else None, ns,
+        _ptr(joints.sup_link) if ns else None, _ptr(joints.sup_local) if ns else None,
+        _ptr(db.sup) if ns else None, _stream(stream)))
 
 
 NOALLOC_MAX_SCENES = 1 << 20

@@ -67,23 +67,62 @@ def box_distance(B, p):
     return np.where(inside, -np.min(h - np.abs(loc), axis=1), out)
 
 
+def _grid_sample_np(vals, G, pts):
+    """Trilinear samples of a node-centred grid instance at world points
+    (FP64; +inf outside the node box; NaN where a node read is not finite)."""
+    G = np.asarray(G, np.float64)
+    pg = pts @ G[:9].reshape(3, 3).T + G[9:12]
+    f = (pg - G[12:15]) / G[15]
+    n = np.array([vals.shape[2], vals.shape[1], vals.shape[0]])
+    inside = np.all((f >= 0) & (f <= n - 1), axis=1)
+    out = np.full(len(pts), np.inf)
+    if not np.any(inside):
+        return out
+    fi = f[inside]
+    i0 = np.minimum(np.floor(fi).astype(np.int64), n - 2)
+    t = fi - i0
+    v = vals.astype(np.float64)
+    acc = np.zeros(len(fi))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                w = (t[:, 0] if dx else 1 - t[:, 0]) * (t[:, 1] if dy else 1 - t[:, 1]) * \
+                    (t[:, 2] if dz else 1 - t[:, 2])
+                acc += w * v[i0[:, 2] + dz, i0[:, 1] + dy, i0[:, 0] + dx]
+    out[inside] = acc
+    return out
+
+
 def audit_placements(b, placed, n_placed, margin=MARGIN, tol=CLR_TOL):
-    """Every placed object of every scene is at least margin - tol away from
-    the boxes and from every earlier placed object (property of the output)."""
+    """Property of the output, in FP64: every placed object of every scene is
+    at least margin - tol away from the scene's boxes and grids and from every
+    other placed object of the scene (pairs found with a k-d tree; objects
+    overlap only within 2 r_max + margin).  Returns the smallest clearance."""
+    from scipy.spatial import cKDTree
     worst = np.inf
+    placed = np.asarray(placed)
     for s in range(b.n_scenes):
-        o0 = b.obj_off[s]
-        boxes = b.box[b.box_off[s]:b.box_off[s + 1]]
-        for j in range(int(n_placed[s])):
-            o = o0 + j
-            sp = placed[b.sph_off[o]:b.sph_off[o + 1]].astype(np.float64)
-            assert np.all(np.isfinite(sp))
-            for B in boxes:
-                worst = min(worst, float(np.min(box_distance(B, sp[:, :3]) - sp[:, 3])))
-            prev = placed[b.sph_off[o0]:b.sph_off[o]].astype(np.float64)
-            if len(prev):
-                d = np.linalg.norm(sp[:, None, :3] - prev[None, :, :3], axis=2)
-                worst = min(worst, float(np.min(d - sp[:, None, 3] - prev[None, :, 3])))
+        o0, npl = int(b.obj_off[s]), int(n_placed[s])
+        if npl == 0:
+            continue
+        a0, a1 = int(b.sph_off[o0]), int(b.sph_off[o0 + npl])
+        sp = placed[a0:a1].astype(np.float64)
+        assert np.all(np.isfinite(sp)), f"scene {s}: non-finite placed sphere"
+        owner = np.repeat(np.arange(npl), np.diff(b.sph_off[o0:o0 + npl + 1]))
+        for B in b.box[b.box_off[s]:b.box_off[s + 1]]:
+            worst = min(worst, float(np.min(box_distance(B, sp[:, :3]) - sp[:, 3])))
+        if b.grid_off is not None:
+            for g in range(b.grid_off[s], b.grid_off[s + 1]):
+                v = _grid_sample_np(b.grid_vals[b.grid_src[g]], b.grid[g], sp[:, :3])
+                assert not np.any(np.isnan(v))
+                worst = min(worst, float(np.min(v - sp[:, 3])))
+        rmax = float(np.max(sp[:, 3]))
+        pairs = cKDTree(sp[:, :3]).query_pairs(2 * rmax + margin + tol, output_type="ndarray")
+        if len(pairs):
+            pairs = pairs[owner[pairs[:, 0]] != owner[pairs[:, 1]]]
+        if len(pairs):
+            d = np.linalg.norm(sp[pairs[:, 0], :3] - sp[pairs[:, 1], :3], axis=1)
+            worst = min(worst, float(np.min(d - sp[pairs[:, 0], 3] - sp[pairs[:, 1], 3])))
     assert worst >= margin - tol, worst
     return worst
 

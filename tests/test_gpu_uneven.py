@@ -91,9 +91,32 @@ def test_autotune_picks_a_schedule_and_round_trips(dev, tmp_path, mid_uneven):
     ctx2.close()
 
 
+def _extremes(b, rng, n_random):
+    """Scenes that stress the launch: the largest by objects x spheres, ones
+    holding 256-sphere objects and 4096-candidate objects, the smallest and
+    the largest of the scenes on each side of a 32 KB LDS budget for placed
+    spheres (the two halves of a split launch), and random ones."""
+    nobj = b.objects_per_scene()
+    sph_scene = b.spheres_per_scene()
+    S = np.diff(b.sph_off)
+    work = nobj * sph_scene
+    obj_scene = np.repeat(np.arange(b.n_scenes), nobj)
+    pick = list(np.argsort(-work)[:4])
+    pick += list(rng.choice(np.unique(obj_scene[S == S.max()]), 4, replace=False))
+    pick += list(rng.choice(np.unique(obj_scene[b.obj_ncand == b.obj_ncand.max()]), 4,
+                            replace=False))
+    small = np.nonzero(16 * sph_scene + 80 * nobj <= 32768)[0]
+    large = np.nonzero(16 * sph_scene + 80 * nobj > 32768)[0]
+    pick += list(rng.choice(small, 4, replace=False)) + list(rng.choice(large, 4, replace=False))
+    rest = np.setdiff1d(np.arange(b.n_scenes), pick)
+    pick += list(rng.choice(rest, n_random, replace=False))
+    return np.unique(np.asarray(pick, np.int64))
+
+
 def test_full_uneven_16384_sampled(dev, orc):
     """16384 uneven scenes in the benchmark's tuned launch; the oracle replays
-    the first objects of sampled scenes; properties checked on the rest."""
+    64+ sampled scenes (extremes included) through all their objects, and
+    256 scenes are audited in FP64; properties checked on every scene."""
     scn, ctx, torch = dev
     b = sg.uneven_batch(16384, seed=0)
     db = scn.DeviceBatch(b)
@@ -105,11 +128,17 @@ def test_full_uneven_16384_sampled(dev, orc):
     assert np.all(status != 0)
     assert np.all(npl[status == 1] == nobj[status == 1])
     assert np.all(npl[status == 2] < nobj[status == 2])
-    pick = np.random.default_rng(5).choice(b.n_scenes, size=6, replace=False)
+    rng = np.random.default_rng(5)
+    pick = _extremes(b, rng, 44)
+    assert len(pick) >= 64
     sub, ids = sg.subset(b, pick)
-    ref = orc.generate(sub, seed=77, scene_id=ids, max_steps=3)
+    print(f"oracle replay of {len(pick)} scenes ({sub.n_objects} objects)", flush=True)
+    ref = orc.generate(sub, seed=77, scene_id=ids, early_exit=True)
     objs = objects_of(b, pick)
-    compare_generation(sub, ref, status[pick], rec_i[objs], rec_f[objs], max_steps=3)
-    small = pick[:3]
-    sidx = np.concatenate([np.arange(b.sph_off[b.obj_off[s]], b.sph_off[b.obj_off[s + 1]]) for s in small])
-    audit_placements(sg.subset(b, small)[0], placed[sidx], npl[small])
+    n_cmp, n_band = compare_generation(sub, ref, status[pick], rec_i[objs], rec_f[objs])
+    print(f"compared {n_cmp} objects, {n_band} scenes with a banded decision", flush=True)
+    assert n_cmp >= 0.9 * sub.n_objects
+    aud = np.sort(rng.choice(b.n_scenes, 256, replace=False))
+    asub, _ = sg.subset(b, aud)
+    sidx = np.concatenate([np.arange(b.sph_off[b.obj_off[s]], b.sph_off[b.obj_off[s + 1]]) for s in aud])
+    audit_placements(asub, placed[sidx], npl[aud])
