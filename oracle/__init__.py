@@ -40,13 +40,14 @@ class _Batch(C.Structure):
                 ("obj_sup", C.c_void_p), ("obj_ncand", C.c_void_p), ("sup", C.c_void_p),
                 ("box_off", C.c_void_p), ("box", C.c_void_p),
                 ("grid_off", C.c_void_p), ("grid", C.c_void_p), ("grid_src", C.c_void_p),
-                ("grid_val", C.c_void_p), ("scene_id", C.c_void_p)]
+                ("grid_val", C.c_void_p), ("scene_id", C.c_void_p),
+                ("obj_rel", C.c_void_p), ("rel", C.c_void_p), ("obj_ratio", C.c_void_p)]
 
 
 class _GenArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("margin", C.c_double), ("retries", C.c_int),
                 ("default_ncand", C.c_int), ("band", C.c_double), ("max_steps", C.c_int),
-                ("early_exit", C.c_int)]
+                ("early_exit", C.c_int), ("band_region", C.c_double)]
 
 
 class _GenOut(C.Structure):
@@ -76,6 +77,8 @@ def lib():
         L.orc_fk_links.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_uint64, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_fk_rows.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_sample_relation.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                          C.c_void_p, C.c_double, C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_max_threads.restype = C.c_int
         _lib = L
@@ -107,12 +110,17 @@ class _Keep:
             self.grid_src = np.ascontiguousarray(b.grid_src, np.int32)
             self._vals = [np.ascontiguousarray(v, np.float32) for v in b.grid_vals]
             self.grid_ptrs = (C.c_void_p * len(self._vals))(*[v.ctypes.data for v in self._vals])
+        rel = getattr(b, "obj_rel", None)
+        self.obj_rel = None if rel is None else np.ascontiguousarray(rel, np.int32)
+        self.rel = None if rel is None else np.ascontiguousarray(b.rel, np.float64).reshape(-1, 16)
+        ratio = getattr(b, "obj_ratio", None)
+        self.obj_ratio = None if ratio is None else np.ascontiguousarray(ratio, np.float64)
         self.cb = _Batch(int(len(self.obj_off) - 1), _p(self.obj_off), _p(self.sph_off),
                          _p(self.tmpl), _p(self.obj_sup), _p(self.obj_ncand), _p(self.sup),
                          _p(self.box_off), _p(self.box), _p(self.grid_off), _p(self.grid),
                          _p(self.grid_src),
                          C.cast(self.grid_ptrs, C.c_void_p) if self.grid_ptrs is not None else None,
-                         _p(self.scene_id))
+                         _p(self.scene_id), _p(self.obj_rel), _p(self.rel), _p(self.obj_ratio))
 
 
 # ---------------------------------------------------------------------------
@@ -180,7 +188,7 @@ def check(b, obj_idx, cand_off, n_placed, placed, poses, scene_id=None) -> np.nd
 
 def generate(b, seed: int, margin: float = 0.005, retries: int = 10, default_ncand: int = 1024,
              band: float = 1e-5, max_steps: int = 0, scene_id=None, threads=None,
-             early_exit: bool = False) -> dict:
+             early_exit: bool = False, band_region: float = 1e-6) -> dict:
     """Batched rejection-sampling placement; returns per-scene status
     (1 valid, 2 invalid), per-object chosen (attempt, idx), poses, band flags,
     and the world spheres of the placed objects.  early_exit: stop each
@@ -199,7 +207,7 @@ def generate(b, seed: int, margin: float = 0.005, retries: int = 10, default_nca
                                          "rec_pose", "rec_banded", "rec_clear", "placed",
                                          "n_cand")])
     ga = _GenArgs(int(seed), float(margin), int(retries), int(default_ncand), float(band),
-                  int(max_steps), int(bool(early_exit)))
+                  int(max_steps), int(bool(early_exit)), float(band_region))
     lib().orc_generate(C.byref(K.cb), C.byref(ga), C.byref(go))
     return out
 
@@ -229,3 +237,26 @@ def forward_kinematics(joint_off, joint, base, seed: int = 0, q=None, scene_id=N
         lib().orc_fk_rows(int(R.shape[0]), _p(rl), _p(Lc), _p(link), _p(R))
         moved.append(R)
     return qq, link[:nj], moved
+
+
+def sample_relation(rel, anchors, ax: float, ay: float, words, band: float = 1e-6):
+    """One sample of a spatial relation (oracle.c sample_relation): returns
+    (x, y, yaw, inside, banded) for the four Philox words of a candidate."""
+    r = np.ascontiguousarray(rel, np.float64)
+    a = np.ascontiguousarray(anchors, np.float64).reshape(-1, 2)
+    w = np.ascontiguousarray(words, np.uint32)
+    out = np.zeros(5, np.float64)
+    lib().orc_sample_relation(_p(r), _p(a), float(ax), float(ay), _p(w), float(band), _p(out))
+    return out[0], out[1], out[2], bool(out[3]), bool(out[4])
+
+
+def relation_row(kind: int, anchors, v=(0.0, 0.0), min_r=0.0, max_r=np.inf, theta=np.pi,
+                 face_to=False) -> np.ndarray:
+    """A relation row in the layout sample_relation reads (16 floats)."""
+    row = np.zeros(16, np.float64)
+    row[0], row[1] = kind, len(anchors)
+    row[2:2 + len(anchors)] = anchors
+    row[10:12] = v
+    row[12], row[13], row[14] = min_r, max_r, theta
+    row[15] = 1.0 if face_to else 0.0
+    return row

@@ -85,6 +85,9 @@ typedef struct {
     const float  **grid_val;  /* [n_asset] node values, x fastest                     */
     const int32_t *scene_id;  /* [n_scenes] scene number used in the random counter
                                  (NULL: the position in the batch)                   */
+    const int32_t *obj_rel;   /* [n_obj] spatial relation row of the object, -1 none (NULL: none) */
+    const double  *rel;       /* [n_rel][16] relation rows (see sample_relation)      */
+    const double  *obj_ratio; /* [n_obj] ratio_on_support (NULL: 0)                   */
 } orc_batch;
 
 typedef struct {
@@ -97,6 +100,8 @@ typedef struct {
     int      early_exit;    /* nonzero: a candidate's clearance stops at its first term
                                below margin - band (the candidate collides and is not
                                banded either way; results are identical, only faster) */
+    double   band_region;   /* a relation sample within this of its region's boundary
+                               marks the decision as banded (FP32 may decide it either way) */
 } orc_gen_args;
 
 /* Pose of a candidate in its support frame: position (x,y,z), yaw about z. */
@@ -113,23 +118,132 @@ static double zrest_of(const orc_batch *b, int o)
     return lift;
 }
 
-/* Candidate i of attempt a for the object at position `step` of scene s. */
+/* ratio_on_support (Sec. IV-F): the support is eroded by ratio x half the
+ * shorter edge of the object's projection, taken as the x / y extent of its
+ * sphere set in the object frame (centres +- radii).                         */
+static double erosion_of(const orc_batch *b, int o)
+{
+    if (!b->obj_ratio || !(b->obj_ratio[o] > 0.0)) return 0.0;
+    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+    for (int k = b->sph_off[o]; k < b->sph_off[o + 1]; ++k)
+        for (int d = 0; d < 2; ++d) {
+            double c = b->tmpl[4 * k + d], r = b->tmpl[4 * k + 3];
+            if (c - r < lo[d]) lo[d] = c - r;
+            if (c + r > hi[d]) hi[d] = c + r;
+        }
+    double ex = hi[0] - lo[0], ey = hi[1] - lo[1];
+    return b->obj_ratio[o] * 0.5 * (ex < ey ? ex : ey);
+}
+
+/* Candidate i of attempt a for the object at position `step` of scene s:
+ * the four Philox words of counter (i, a, step, scene).                      */
+static void candidate_words(const orc_batch *b, uint64_t seed, int s, int step, int attempt, int i,
+                            uint32_t w[4])
+{
+    uint32_t sid = b->scene_id ? (uint32_t)b->scene_id[s] : (uint32_t)s;
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)attempt, (uint32_t)step, sid};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, w);
+}
+
 static orc_pose sample_pose(const orc_batch *b, uint64_t seed, int s, int step, int o,
                             int attempt, int i)
 {
     const double *u = b->sup + 16 * b->obj_sup[o];
-    uint32_t sid = b->scene_id ? (uint32_t)b->scene_id[s] : (uint32_t)s;
-    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)attempt, (uint32_t)step, sid};
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t w[4];
-    orc_philox4x32_10(ctr, key, w);
-    double ax = u[12] - u[14], ay = u[13] - u[14];
+    candidate_words(b, seed, s, step, attempt, i, w);
+    double e = erosion_of(b, o);
+    double ax = u[12] - u[14] - e, ay = u[13] - u[14] - e;
     orc_pose p;
     p.x = ax * (2.0 * orc_u01(w[0]) - 1.0);
     p.y = ay * (2.0 * orc_u01(w[1]) - 1.0);
     p.yaw = 2.0 * M_PI * orc_u01(w[2]);
     p.z = u[15] + zrest_of(b, o);
     return p;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Object-object spatial relations (Sec. IV-F).  A relation row (16 values): */
+/*   [0] kind: 1 = one anchor (partial annulus), 2 = several anchors         */
+/*       ('middle'); [1] number of anchors; [2..9] anchors (positions of     */
+/*       earlier objects of the scene); [10..11] direction v in the support  */
+/*       frame ((0,0): every direction); [12] min_r, [13] max_r (may be      */
+/*       +inf); [14] direction_angle_threshold theta; [15] flags, bit 0 =    */
+/*       face_to (the object's x axis points at the first anchor).           */
+/* Single anchor: the region S' = S_r cap S, S_r the points p with           */
+/*   min_r <= |p - a| <= max_r and the direction of p - a within theta of v, */
+/* S the (eroded) support rectangle.  Sampled uniformly by area in the       */
+/* annulus sector: r = sqrt(min_r^2 + u0 (R^2 - min_r^2)), angle = angle(v) +  */
+/* theta (2 u1 - 1), with R = min(max_r, the farthest corner of S from a);   */
+/* a point outside S is rejected (the candidate is not valid).               */
+/* Several anchors: the region is the anchors' convex hull cap S, sampled    */
+/* uniformly in the anchors' bounding box (u0, u1) and rejected outside the  */
+/* hull or outside S.  Fewer than 3 anchors enclose no area: no candidate is */
+/* valid.  Yaw: face_to, else 2 pi u2.                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct { double x, y, yaw; int inside; int banded; } orc_rel_sample;
+
+static double cross2(double ax, double ay, double bx, double by) { return ax * by - ay * bx; }
+
+static orc_rel_sample sample_relation(const double *rel, const double anc[][2], double ax,
+                                      double ay, const uint32_t w[4], double band)
+{
+    orc_rel_sample r = {0.0, 0.0, 0.0, 0, 0};
+    double u0 = orc_u01(w[0]), u1 = orc_u01(w[1]), u2 = orc_u01(w[2]);
+    int n = (int)rel[1];
+    if ((int)rel[0] == 1) {
+        double a0 = anc[0][0], a1 = anc[0][1];
+        double far = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            double cx = (c & 1 ? ax : -ax) - a0, cy = (c & 2 ? ay : -ay) - a1;
+            double d = sqrt(cx * cx + cy * cy);
+            if (d > far) far = d;
+        }
+        double rmin = rel[12], rmax = rel[13] < far ? rel[13] : far;
+        if (!(rmin < rmax)) return r;
+        int dir = rel[10] != 0.0 || rel[11] != 0.0;
+        double th = dir ? (rel[14] < M_PI ? rel[14] : M_PI) : M_PI;
+        double phi0 = dir ? atan2(rel[11], rel[10]) : 0.0;
+        double rr = sqrt(rmin * rmin + u0 * (rmax * rmax - rmin * rmin));
+        double phi = phi0 + th * (2.0 * u1 - 1.0);
+        r.x = a0 + rr * cos(phi);
+        r.y = a1 + rr * sin(phi);
+    } else {
+        if (n < 3) return r;
+        double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+        for (int k = 0; k < n; ++k)
+            for (int d = 0; d < 2; ++d) {
+                if (anc[k][d] < lo[d]) lo[d] = anc[k][d];
+                if (anc[k][d] > hi[d]) hi[d] = anc[k][d];
+            }
+        r.x = lo[0] + u0 * (hi[0] - lo[0]);
+        r.y = lo[1] + u1 * (hi[1] - lo[1]);
+        /* hull edges: (i, k) with every other anchor strictly to its left */
+        int inside = 1, nedge = 0;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                if (i == k) continue;
+                double ex = anc[k][0] - anc[i][0], ey = anc[k][1] - anc[i][1];
+                int edge = 1;
+                for (int m = 0; m < n && edge; ++m)
+                    if (m != i && m != k && !(cross2(ex, ey, anc[m][0] - anc[i][0], anc[m][1] - anc[i][1]) > 0.0))
+                        edge = 0;
+                if (!edge) continue;
+                ++nedge;
+                double c = cross2(ex, ey, r.x - anc[i][0], r.y - anc[i][1]);
+                double len = sqrt(ex * ex + ey * ey);
+                if (fabs(c) < band * len) r.banded = 1;
+                if (c < 0.0) inside = 0;
+            }
+        if (nedge < 3) return r;
+        if (!inside) { r.inside = 0; goto yaw; }
+    }
+    r.inside = fabs(r.x) <= ax && fabs(r.y) <= ay;
+    if (fabs(fabs(r.x) - ax) < band || fabs(fabs(r.y) - ay) < band) r.banded = 1;
+yaw:
+    if (((int)rel[15]) & 1) r.yaw = atan2(anc[0][1] - r.y, anc[0][0] - r.x);
+    else r.yaw = 2.0 * M_PI * u2;
+    return r;
 }
 
 /* World sphere k of object o at pose p on support u:
@@ -258,6 +372,17 @@ static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
     return best;
 }
 
+/* One relation sample (tests): out = x, y, yaw, inside, banded.            */
+void orc_sample_relation(const double rel[16], const double *anchors, double ax, double ay,
+                         const uint32_t w[4], double band, double out[5])
+{
+    double anc[8][2];
+    int n = (int)rel[1];
+    for (int k = 0; k < n && k < 8; ++k) { anc[k][0] = anchors[2 * k]; anc[k][1] = anchors[2 * k + 1]; }
+    orc_rel_sample r = sample_relation(rel, (const double (*)[2])anc, ax, ay, w, band);
+    out[0] = r.x; out[1] = r.y; out[2] = r.yaw; out[3] = r.inside; out[4] = r.banded;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Exported: sample poses for one attempt, dense clearance of given poses,   */
 /* and the whole batched rejection-sampling generation.                      */
@@ -344,9 +469,38 @@ void orc_generate(const orc_batch *b, const orc_gen_args *g, orc_gen_out *out)
             double chosen_clr = NAN;
             orc_pose chosen_pose = {0, 0, 0, 0};
             int8_t banded = 0;
+            /* the object's relation: its anchors' recorded positions (earlier
+             * objects of the scene, on the same support) */
+            const double *rel = (b->obj_rel && b->obj_rel[o] >= 0) ? b->rel + 16 * b->obj_rel[o] : NULL;
+            double anc[8][2];
+            int rel_ok = 1;
+            if (rel) {
+                int na = (int)rel[1];
+                if (na < 1 || na > 8) rel_ok = 0;
+                for (int k = 0; k < na && k < 8 && rel_ok; ++k) {
+                    int ja = (int)rel[2 + k];
+                    if (ja < 0 || ja >= step || b->obj_sup[o0 + ja] != b->obj_sup[o]) { rel_ok = 0; break; }
+                    anc[k][0] = out->rec_pose[4 * (o0 + ja) + 0];
+                    anc[k][1] = out->rec_pose[4 * (o0 + ja) + 1];
+                }
+            }
+            const double *uu = b->sup + 16 * b->obj_sup[o];
+            const double ero = erosion_of(b, o);
+            const double rax = uu[12] - uu[14] - ero, ray = uu[13] - uu[14] - ero;
             for (int a = 0; a <= g->retries && chosen < 0; ++a) {
                 for (int i = 0; i < nc; ++i) {
                     orc_pose p = sample_pose(b, g->seed, s, step, o, a, i);
+                    if (rel) {
+                        uint32_t w[4];
+                        candidate_words(b, g->seed, s, step, a, i, w);
+                        orc_rel_sample q = sample_relation(rel, (const double (*)[2])anc, rax, ray, w,
+                                                           g->band_region);
+                        ++ncand;
+                        if (q.banded) banded = 1;
+                        if (!rel_ok || !q.inside) continue;   /* outside the region: not valid */
+                        --ncand;
+                        p.x = q.x; p.y = q.y; p.yaw = q.yaw;
+                    }
                     for (int k = 0; k < ns; ++k) world_sphere(b, o, b->sph_off[o] + k, p, sph + 4 * k);
                     double cl = clearance(b, s, sph, ns, out->placed + 4 * first, n_pl,
                                           g->early_exit ? g->margin - g->band : -INFINITY);

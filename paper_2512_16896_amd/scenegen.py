@@ -55,6 +55,10 @@ class SceneBatch:
     grid: Optional[np.ndarray] = None         # float32 [n_grid,24] see grid_instance()
     grid_src: Optional[np.ndarray] = None     # int32 [n_grid] asset index
     grid_vals: Optional[list] = None          # list of float32 [nz,ny,nx] assets
+    # object-object spatial relations and support erosion (None when absent)
+    obj_rel: Optional[np.ndarray] = None      # int32 [n_obj] relation row, -1 none
+    rel: Optional[np.ndarray] = None          # float32 [n_rel,16] relation rows
+    obj_ratio: Optional[np.ndarray] = None    # float32 [n_obj] ratio_on_support
     name: str = ""
     params: dict = dataclasses.field(default_factory=dict)
 
@@ -439,6 +443,63 @@ def drawer_scenes(n_scenes: int = 4096, seed: int = 0, n_obj_per_drawer: int = 4
                     art=art))
 
 
+def relation_scenes(n_scenes: int = 4096, seed: int = 0, n_sph: int = 32, n_cand: int = 256,
+                    n_box: int = 4, side=(0.05, 0.15), rad=(0.01, 0.03)) -> SceneBatch:
+    """Object-object spatial relations (Sec. IV-F) on a 2.0 x 1.0 m support at
+    a random world pose with n_box cuboids; 8 objects per scene, in this
+    order (anchors are always earlier objects):
+      0  free, ratio_on_support 1 (the projection stays on the support)
+      1  'less' than 0.45 m from object 0, within pi/4 of a random direction,
+         face_to object 0
+      2  'greater' than 0.5 m from object 0, any direction
+      3  'equal' to 0.35 +- 0.03 m from object 1, within pi/2 of a random
+         direction
+      4  'middle' of objects 0, 1 and 2
+      5  'less' than 0.3 m from object 4, face_to
+      6, 7 free, ratio_on_support 0.5
+    Relation rows follow the oracle's layout: kind, anchor count, anchor
+    positions, direction, min_r, max_r, angle threshold, flags."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x2E1A]))
+    n_obj, hx, hy = 8, 1.0, 0.5
+    sup_R, sup_t = _support_poses(rng, n_scenes)
+    sup = _support_rows(sup_R, sup_t, hx, hy, 0.0, 0.0)
+    obj_off = np.arange(n_scenes + 1, dtype=np.int64) * n_obj
+    sph_off, tmpl = _templates(rng, n_scenes * n_obj, n_sph, side, rad)
+    box_off, box = _boxes(rng, n_scenes, n_box, hx, hy, 0.5, sup_R, sup_t, half=(0.05, 0.2))
+    rel = np.zeros((n_scenes, 5, 16), np.float64)
+    ang = rng.uniform(0, 2 * np.pi, size=(n_scenes, 2))
+    inf = np.inf
+    spec = [  # (object, kind, anchors, direction index or -1, min_r, max_r, theta, face_to)
+        (1, 1, [0], 0, 0.0, 0.45, np.pi / 4, 1),
+        (2, 1, [0], -1, 0.5, inf, np.pi, 0),
+        (3, 1, [1], 1, 0.32, 0.38, np.pi / 2, 0),
+        (4, 2, [0, 1, 2], -1, 0.0, 0.0, np.pi, 0),
+        (5, 1, [4], -1, 0.0, 0.3, np.pi, 1),
+    ]
+    obj_rel = -np.ones(n_scenes * n_obj, np.int32)
+    for k, (o, kind, anc, di, r0, r1, th, ft) in enumerate(spec):
+        rel[:, k, 0] = kind
+        rel[:, k, 1] = len(anc)
+        rel[:, k, 2:2 + len(anc)] = anc
+        if di >= 0:
+            rel[:, k, 10] = np.cos(ang[:, di])
+            rel[:, k, 11] = np.sin(ang[:, di])
+        rel[:, k, 12], rel[:, k, 13], rel[:, k, 14], rel[:, k, 15] = r0, r1, th, ft
+        obj_rel[np.arange(n_scenes) * n_obj + o] = np.arange(n_scenes) * 5 + k
+    ratio = np.zeros(n_scenes * n_obj, np.float32)
+    ratio[np.arange(n_scenes) * n_obj] = 1.0
+    ratio[np.arange(n_scenes) * n_obj + 6] = 0.5
+    ratio[np.arange(n_scenes) * n_obj + 7] = 0.5
+    return SceneBatch(
+        obj_off=obj_off.astype(np.int32), sph_off=sph_off.astype(np.int32),
+        tmpl=tmpl.astype(np.float32), obj_sup=np.repeat(np.arange(n_scenes), n_obj).astype(np.int32),
+        obj_ncand=np.full(n_scenes * n_obj, n_cand, np.int32), sup=sup,
+        box_off=box_off.astype(np.int32), box=box, obj_rel=obj_rel,
+        rel=rel.reshape(-1, 16).astype(np.float32), obj_ratio=ratio,
+        name=f"relations-{n_scenes}",
+        params=dict(n_scenes=n_scenes, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand, seed=seed))
+
+
 def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
     """The scenes `scenes` of a batch as a batch of their own, plus the
     original scene indices (which the random-number counters must keep)."""
@@ -462,6 +523,11 @@ def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
         obj_ncand=b.obj_ncand[objs].copy(), sup=b.sup[sups].copy(),
         box_off=box_off.astype(np.int32), box=b.box[boxes].copy(),
         name=b.name + "-subset", params=dict(b.params))
+    if b.obj_rel is not None:
+        out.obj_rel = b.obj_rel[objs].copy()
+        out.rel = b.rel
+    if b.obj_ratio is not None:
+        out.obj_ratio = b.obj_ratio[objs].copy()
     if b.grid_off is not None:
         grids = _ranges(b.grid_off[scenes], b.grid_off[scenes + 1] - b.grid_off[scenes])
         goff = np.zeros(len(scenes) + 1, np.int64)
