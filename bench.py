@@ -59,6 +59,24 @@ WORKLOADS = {
                           make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                        fromlist=["x"]).shelf_scenes(65536, seed=seed),
                           ncand=2048, cpu_scenes=0, tune=True),
+    "relations-4096": dict(desc="4096 scenes on a 2.0x1.0 m support with 4 cuboids; 8 objects x 32 "
+                                "spheres with object-object relations: within 0.45 m of object 0 "
+                                "inside a pi/4 cone (face_to), beyond 0.5 m, 0.35+-0.03 m from "
+                                "object 1 in a pi/2 cone, in the middle of objects 0-2, within "
+                                "0.3 m of that one (face_to); ratio_on_support 1 / 0.5 on the "
+                                "free objects; 256 candidates per attempt; margin 5 mm; 10 retries",
+                           make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                        fromlist=["x"]).relation_scenes(4096, seed=seed),
+                           ncand=256, cpu_scenes=0),
+    "drawers-4096": dict(desc="4096 two-drawer cabinets at random world poses; drawers are "
+                              "prismatic joints with travel U[0, 0.35] m drawn per scene by the "
+                              "batched forward kinematics, which moves their walls (boxes) and "
+                              "bottoms (supports); 4 objects x 32 spheres per drawer (cube side "
+                              "U[0.04,0.12] m, r~U[0.01,0.03] m); 256 candidates per attempt; "
+                              "6 static cabinet boards; margin 5 mm; 10 retries",
+                         make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                      fromlist=["x"]).drawer_scenes(4096, seed=seed),
+                         ncand=256, cpu_scenes=0),
 }
 
 
@@ -378,6 +396,47 @@ def extra_workload(ctx, name, steps, warmup, dense_scenes=0):
     return out
 
 
+def drawers_leg(ctx, steps, warmup):
+    """Articulated scenes: the batched forward kinematics (joint values, links,
+    moved rows; timed alone with HIP events) and then the plain generation on
+    the moved drawers."""
+    import torch
+    from paper_2512_16896_amd import scn
+    W = WORKLOADS["drawers-4096"]
+    progress("building drawers-4096")
+    b = W["make"](0)
+    b.name = "drawers-4096"
+    db = scn.DeviceBatch(b, "cuda:0")
+    J = scn.Joints(b.params["art"])
+    stream = torch.cuda.current_stream()
+    for i in range(3):
+        scn.forward_kinematics(ctx, J, db, seed=50 + i)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(20)]
+    for k in range(20):
+        ev[k][0].record(stream)
+        scn.forward_kinematics(ctx, J, db, seed=60 + k)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    ctx.read_counters()
+    fk_ms = float(np.mean([a.elapsed_time(z) for a, z in ev]))
+    nj = int(J.joint.shape[0])
+    rows = int(J.box_link.numel() + J.sup_link.numel())
+    db.refresh_geometry()
+    b.box = db.box.cpu().numpy()[:b.n_boxes]
+    b.sup = db.sup.cpu().numpy()
+    del db
+    out, db, _ = plain_leg(ctx, b, W, steps, warmup)
+    out["config"] = W["desc"]
+    out["forward_kinematics"] = {"us_per_call": 1e3 * fk_ms, "joints": nj, "rows": rows,
+                                 "joints_per_s": nj / (fk_ms * 1e-3),
+                                 "note": "joint values, link poses and moved box/support rows "
+                                         "of all 4096 scenes per call (three launches)"}
+    del db
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,6 +504,8 @@ def main():
         out["uneven_16384"] = extra_workload(ctx, "uneven-16384", 10, 2,
                                              dense_scenes=0 if args.no_dense else 512)
         out["shelves_65536"] = extra_workload(ctx, "shelves-65536", 5, 1)
+        out["drawers_4096"] = drawers_leg(ctx, 20, 3)
+        out["relations_4096"] = extra_workload(ctx, "relations-4096", 20, 3)
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -144,6 +144,32 @@ typedef struct scn_batch {
     int32_t *n_placed;
     int8_t *status;
     scn_pose_rec *rec;
+    /* Object-object spatial relations and support erosion (Sec. IV-F),
+     * optional (NULL: none), read by the place calls:
+     *   obj_rel   [n_objects] relation row of object o, -1 none
+     *   rel       [n_rel][16] kind (1 = one anchor, partial annulus; 2 =
+     *             'middle' of several anchors), anchor count, anchors[8]
+     *             (positions of earlier objects of the same scene on the same
+     *             support), direction v[2] in the support frame ((0,0): any),
+     *             min_r, max_r (may be +inf), direction angle threshold theta,
+     *             flags (bit 0: face_to, the object's x axis points at the
+     *             first anchor).  One anchor: the candidate's (x, y) is drawn
+     *             area-uniformly in the sector min_r <= |p - a| <= R, angle of
+     *             p - a within theta of v (R = max_r clipped to the farthest
+     *             corner of the support); 'middle': uniformly in the anchors'
+     *             bounding box.  A point outside the region (the support
+     *             rectangle, and for 'middle' the anchors' convex hull) is not
+     *             a valid candidate.  Anchors that are not earlier objects on
+     *             the same support, or fewer than 3 'middle' anchors, leave no
+     *             valid candidate.  Counter and words as for uniform
+     *             candidates (u0, u1: position; u2: yaw unless face_to).
+     *   obj_ratio [n_objects] ratio_on_support: the support rectangle is
+     *             eroded by ratio * half the shorter x / y extent of the
+     *             object's sphere set (also in scn_sample_poses).
+     * The learned-proposal calls refuse batches that have them.             */
+    const int32_t *obj_rel;
+    const float *rel;
+    const float *obj_ratio;
 } scn_batch;
 
 /* Candidate poses in the support frame, structure of arrays (device). */

@@ -339,6 +339,9 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
         return fail(SCN_E_INVALID_ARG, "default_ncand must be > 0 when obj_ncand is NULL");
     const int S = b->max_spheres_per_object;
     if (S > 256) return fail(SCN_E_UNSUPPORTED, "max_spheres_per_object %d > 256", S);
+    if (b->obj_rel && b->grid_off)
+        return fail(SCN_E_UNSUPPORTED, "spatial relations in voxel-grid batches are not supported");
+    if (b->obj_rel && !b->rel) return fail(SCN_E_INVALID_ARG, "obj_rel given without rel");
     plan->spl = S <= 64 ? 1 : (S <= 128 ? 2 : 4);
     int sched = a->schedule;
     if (sched == 0) {

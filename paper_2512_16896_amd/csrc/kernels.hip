@@ -63,9 +63,10 @@ __device__ __forceinline__ float rest_lift(const float4* __restrict__ tmpl, int 
 __global__ __launch_bounds__(256) void k_sample(
     const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
     const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
-    const float* __restrict__ sup, const int32_t* __restrict__ obj_idx,
-    const int32_t* __restrict__ cand_off, uint64_t seed, int attempt, float* __restrict__ ox,
-    float* __restrict__ oy, float* __restrict__ oz, float* __restrict__ oyaw) {
+    const float* __restrict__ sup, const float* __restrict__ obj_ratio,
+    const int32_t* __restrict__ obj_idx, const int32_t* __restrict__ cand_off, uint64_t seed,
+    int attempt, float* __restrict__ ox, float* __restrict__ oy, float* __restrict__ oz,
+    float* __restrict__ oyaw) {
     const int s = blockIdx.x;
     const int o = obj_idx[s];
     if (o < obj_off[s] || o >= obj_off[s + 1]) return;   // -1 or not an object of scene s
@@ -74,8 +75,20 @@ __global__ __launch_bounds__(256) void k_sample(
     if (t >= c1) return;
     const Support U = load_support(sup, obj_sup[o]);
     const float lift = rest_lift(tmpl, sph_off[o], sph_off[o + 1]);
+    // ratio_on_support: erosion by ratio x half the shorter x / y extent
+    float ero = 0.f;
+    if (obj_ratio && obj_ratio[o] > 0.f) {
+        float lx = 1e30f, hx = -1e30f, ly = 1e30f, hy = -1e30f;
+        for (int k = sph_off[o]; k < sph_off[o + 1]; ++k) {
+            const float4 c = tmpl[k];
+            lx = fminf(lx, c.x - c.w); hx = fmaxf(hx, c.x + c.w);
+            ly = fminf(ly, c.y - c.w); hy = fmaxf(hy, c.y + c.w);
+        }
+        ero = obj_ratio[o] * 0.5f * fminf(hx - lx, hy - ly);
+    }
     const Pose P = sample_pose(seed, (uint32_t)s, (uint32_t)(o - obj_off[s]), (uint32_t)attempt,
-                               (uint32_t)(t - c0), U.hx - U.inset, U.hy - U.inset, U.lift + lift);
+                               (uint32_t)(t - c0), U.hx - U.inset - ero, U.hy - U.inset - ero,
+                               U.lift + lift);
     ox[t] = P.x;
     oy[t] = P.y;
     oz[t] = P.z;
@@ -87,8 +100,8 @@ hipError_t launch_sample(const scn_batch& b, const int32_t* obj_idx, const int32
     if (b.n_scenes == 0 || max_cand == 0) return hipSuccess;
     dim3 grid(b.n_scenes, (max_cand + 255) / 256);
     hipLaunchKernelGGL(k_sample, grid, dim3(256), 0, st, b.obj_off, b.sph_off,
-                       (const float4*)b.tmpl, b.obj_sup, b.sup, obj_idx, cand_off, seed, attempt,
-                       out.x, out.y, out.z, out.yaw);
+                       (const float4*)b.tmpl, b.obj_sup, b.sup, b.obj_ratio, obj_idx, cand_off,
+                       seed, attempt, out.x, out.y, out.z, out.yaw);
     return hipGetLastError();
 }
 

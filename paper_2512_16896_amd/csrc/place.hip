@@ -32,6 +32,121 @@
 
 namespace scn {
 
+// Object-object spatial relation of the object being placed (Sec. IV-F), set
+// up once per object in LDS.  kind 1: the partial annulus around one anchor,
+// sampled area-uniformly in the sector r^2 in [r0sq, r0sq + dr2], angle
+// phi0 +- th; kind 2 ('middle'): the anchors' convex hull, sampled uniformly
+// in the anchors' bounding box [lo, lo + d] and rejected outside the hull
+// (edges (a, e): inside when cross(e, p - a) >= 0); kind -1: no valid region.
+// Either kind rejects points outside the (eroded) support rectangle ax x ay.
+// face_to turns the object's x axis to the first anchor.
+struct RelState {
+    int kind, face_to, nedge, pad;
+    float a0x, a0y, r0sq, dr2, phi0, th;
+    float lox, loy, dx, dy;
+    float edge[8][4];
+};
+
+// Relation sample from the candidate's Philox words: the pose (z = zc) and
+// whether it lies in the relation's region.
+__device__ __forceinline__ Pose relation_pose(const RelState& R, U4 w, float ax, float ay,
+                                              float zc, bool* inside) {
+    const float u0 = unit01(w.a), u1 = unit01(w.b), u2 = unit01(w.c);
+    Pose p;
+    bool in = R.kind > 0;
+    if (R.kind == 1) {
+        const float rr = sqrtf(fmaf(u0, R.dr2, R.r0sq));
+        float sn, cs;
+        sincosf(fmaf(R.th, fmaf(2.f, u1, -1.f), R.phi0), &sn, &cs);
+        p.x = fmaf(rr, cs, R.a0x);
+        p.y = fmaf(rr, sn, R.a0y);
+    } else {
+        p.x = fmaf(u0, R.dx, R.lox);
+        p.y = fmaf(u1, R.dy, R.loy);
+        for (int e = 0; e < R.nedge; ++e)
+            in &= R.edge[e][2] * (p.y - R.edge[e][1]) - R.edge[e][3] * (p.x - R.edge[e][0]) >= 0.f;
+    }
+    in &= fabsf(p.x) <= ax && fabsf(p.y) <= ay;
+    if (R.face_to) {
+        const float fx = R.a0x - p.x, fy = R.a0y - p.y;
+        const float n = sqrtf(fmaf(fx, fx, fy * fy));
+        p.yaw = atan2f(fy, fx);
+        p.c = n > 0.f ? fx / n : 1.f;
+        p.s = n > 0.f ? fy / n : 0.f;
+    } else {
+        p.yaw = 6.28318530717958647692f * u2;
+        sincospif(2.0f * u2, &p.s, &p.c);
+    }
+    p.z = zc;
+    *inside = in;
+    return p;
+}
+
+// Sets up the relation of object o (at position j of the scene whose first
+// object is o0) from its row and its anchors' records; one thread.
+__device__ void relation_setup(RelState& R, const float* __restrict__ row, int j, int o0,
+                               const int32_t* __restrict__ obj_sup, int o,
+                               const scn_pose_rec* __restrict__ rec, float ax, float ay) {
+    R.kind = -1;
+    R.face_to = ((int)row[15]) & 1;
+    R.nedge = 0;
+    const int kind = (int)row[0], n = (int)row[1];
+    if (n < 1 || n > 8 || (kind != 1 && kind != 2)) return;
+    float anc[8][2];
+    for (int k = 0; k < n; ++k) {
+        const int ja = (int)row[2 + k];
+        if (ja < 0 || ja >= j || obj_sup[o0 + ja] != obj_sup[o]) return;
+        anc[k][0] = rec[o0 + ja].x;
+        anc[k][1] = rec[o0 + ja].y;
+    }
+    R.a0x = anc[0][0];
+    R.a0y = anc[0][1];
+    if (kind == 1) {
+        float far = 0.f;
+        for (int c = 0; c < 4; ++c) {
+            const float cx = (c & 1 ? ax : -ax) - R.a0x, cy = (c & 2 ? ay : -ay) - R.a0y;
+            far = fmaxf(far, sqrtf(fmaf(cx, cx, cy * cy)));
+        }
+        const float rmin = row[12], rmax = fminf(row[13], far);
+        if (!(rmin < rmax)) return;
+        const bool dir = row[10] != 0.f || row[11] != 0.f;
+        R.th = dir ? fminf(row[14], 3.14159265358979323846f) : 3.14159265358979323846f;
+        R.phi0 = dir ? atan2f(row[11], row[10]) : 0.f;
+        R.r0sq = rmin * rmin;
+        R.dr2 = rmax * rmax - R.r0sq;
+        R.kind = 1;
+        return;
+    }
+    if (n < 3) return;
+    float lo[2] = {anc[0][0], anc[0][1]}, hi[2] = {anc[0][0], anc[0][1]};
+    for (int k = 1; k < n; ++k)
+        for (int d = 0; d < 2; ++d) {
+            lo[d] = fminf(lo[d], anc[k][d]);
+            hi[d] = fmaxf(hi[d], anc[k][d]);
+        }
+    R.lox = lo[0]; R.loy = lo[1];
+    R.dx = hi[0] - lo[0]; R.dy = hi[1] - lo[1];
+    // hull edges: (i, k) with every other anchor strictly to its left
+    int ne = 0;
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) {
+            if (i == k) continue;
+            const float ex = anc[k][0] - anc[i][0], ey = anc[k][1] - anc[i][1];
+            bool edge = true;
+            for (int m = 0; m < n && edge; ++m)
+                if (m != i && m != k &&
+                    !(ex * (anc[m][1] - anc[i][1]) - ey * (anc[m][0] - anc[i][0]) > 0.f))
+                    edge = false;
+            if (edge && ne < 8) {
+                R.edge[ne][0] = anc[i][0]; R.edge[ne][1] = anc[i][1];
+                R.edge[ne][2] = ex; R.edge[ne][3] = ey;
+                ++ne;
+            }
+        }
+    R.nedge = ne;
+    if (ne >= 3) R.kind = 2;
+}
+
 // Pose of entry g of an object's candidate list.  Entries 0..prop_k-1 are the
 // learned proposal's bins in rank order: one pose drawn uniformly inside the
 // bin (x cell, y cell, yaw cell of the 32 x 16 x 8 grid) with Philox counter
@@ -39,7 +154,8 @@ namespace scn {
 // prop_k + a C + i being candidate i of attempt a (counter (i, a, j, s)).
 __device__ __forceinline__ Pose entry_pose(int g, int prop_k, const int32_t* __restrict__ bins,
                                            int C, uint64_t seed, uint32_t s, uint32_t j, float ax,
-                                           float ay, float zc, int* att, int* idx) {
+                                           float ay, float zc, int* att, int* idx,
+                                           const RelState* rs = nullptr, bool* inside = nullptr) {
     if (g < prop_k) {
         const int bin = min(max(bins[g], 0), 4095);
         const U4 w = philox10(U4{(uint32_t)g, 0x10000u, j, s}, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -60,6 +176,12 @@ __device__ __forceinline__ Pose entry_pose(int g, int prop_k, const int32_t* __r
     const int a = e / C, i = e - a * C;
     *att = a;
     *idx = i;
+    if (rs) {
+        const U4 w = philox10(U4{(uint32_t)i, (uint32_t)a, j, s}, (uint32_t)seed,
+                              (uint32_t)(seed >> 32));
+        return relation_pose(*rs, w, ax, ay, zc, inside);
+    }
+    if (inside) *inside = true;
     return sample_pose(seed, s, j, (uint32_t)a, (uint32_t)i, ax, ay, zc);
 }
 
@@ -353,12 +475,13 @@ __device__ __forceinline__ unsigned long long reachable_boxes(const ObjConsts& K
     int32_t* __restrict__ resume, int chunk, int j_cap, int32_t* __restrict__ n_active, \
     const int32_t* __restrict__ grid_off, const float* __restrict__ grid, \
     const int32_t* __restrict__ grid_src, const int64_t* __restrict__ grid_val_off, \
-    const float* __restrict__ grid_val
+    const float* __restrict__ grid_val, const int32_t* __restrict__ obj_rel, \
+    const float* __restrict__ rel, const float* __restrict__ obj_ratio
 #define SCN_PLACE_ARGS \
     obj_off, sph_off, tmpl, obj_sup, obj_ncand, sup, box_off, box, placed, n_placed, status, rec, chosen, counters, order, seed, margin, retries, default_ncand, max_steps, cap_sph, cap_obj, split, split_sph, prop_bins, prop_k, resume, chunk, j_cap, n_active, \
-    grid_off, grid, grid_src, grid_val_off, grid_val
+    grid_off, grid, grid_src, grid_val_off, grid_val, obj_rel, rel, obj_ratio
 
-template <int SPL, bool kLds, bool kGrids, bool kYaw>
+template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kRel>
 __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     // placed objects covered by a candidate's object mask: 64 per word; the
     // dense multi-shelf (grid) scenes carry 100 objects, so they get two words
@@ -378,6 +501,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     // per object): x, y, z, c, s, yaw, attempt, index
     __shared__ float s_found[16][8];
     __shared__ DepthMap s_dm;   // read where used (volatile), not held in registers
+    __shared__ RelState s_rel;  // the current object's spatial relation
 
     const int s = order ? order[blockIdx.x] : (int)blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
@@ -581,7 +705,32 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         const float prm2b = (probe2.w + margin) * (probe2.w + margin);
 
         const Support U = load_support(sup, obj_sup[o]);
-        const float ax = U.hx - U.inset, ay = U.hy - U.inset, zc = U.lift + lift;
+        // ratio_on_support (Sec. IV-F): the support eroded by ratio x half
+        // the shorter x / y extent of the object's sphere set
+        float ero = 0.f;
+        if (obj_ratio) {
+            const float ratio = obj_ratio[o];
+            if (ratio > 0.f) {
+                float lx0 = 1e30f, hx0 = -1e30f, ly0 = 1e30f, hy0 = -1e30f;
+#pragma unroll
+                for (int q = 0; q < SPL; ++q)
+                    if (act[q]) {
+                        lx0 = fminf(lx0, cx[q] - cr[q]); hx0 = fmaxf(hx0, cx[q] + cr[q]);
+                        ly0 = fminf(ly0, cy[q] - cr[q]); hy0 = fmaxf(hy0, cy[q] + cr[q]);
+                    }
+                const float ex = wave_max(hx0) - wave_min(lx0), ey = wave_max(hy0) - wave_min(ly0);
+                ero = ratio * 0.5f * fminf(ex, ey);
+            }
+        }
+        const float ax = U.hx - U.inset - ero, ay = U.hy - U.inset - ero, zc = U.lift + lift;
+        // spatial relations: instances for batches that have them (kRel)
+        const RelState* rs = nullptr;
+        if constexpr (kRel) {
+            const int rel_row = obj_rel ? obj_rel[o] : -1;
+            if (rel_row >= 0 && threadIdx.x == 0)
+                relation_setup(s_rel, rel + 16 * rel_row, j, o0, obj_sup, o, rec, ax, ay);
+            if (rel_row >= 0) rs = &s_rel;
+        }
         // planar form: supports and boxes turn about z only; world z of each
         // sphere, of the bounding centre and of the probe is then the same
         // for every candidate
@@ -684,8 +833,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             const int g = gb + W * lane;
             const bool live = g < g_hi;
             int ga, gi;
+            bool inside;
             const Pose L = entry_pose(live ? g : 0, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
-                                      ay, zc, &ga, &gi);
+                                      ay, zc, &ga, &gi, rs, &inside);
             float lx, ly, lz;   // world centre of this candidate's bounding sphere
             float qx, qy, qz;   // world centres of its probe spheres
             float ux, uy, uz;
@@ -703,13 +853,16 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 to_world(U, L, probe.x, probe.y, probe.z, qx, qy, qz);
                 to_world(U, L, probe2.x, probe2.y, probe2.z, ux, uy, uz);
             }
-            bool sure = false;  // the probe collides: the candidate is rejected
+            // rejected: a point outside its relation's region, or a probe
+            // that collides
+            bool sure = !inside;
             unsigned long long bmask = 0, gmask = 0;
             // the probes against the depth map of the placed spheres first:
             // the cheapest rejection
             if (kMap && use_map && j > 0) {
                 const DepthMap dmq = map_params(&s_dm);
-                sure = map_hit(lmap, dmq, fmaf(L.c, probe.x, fmaf(-L.s, probe.y, L.x)),
+                if (!sure)
+                    sure = map_hit(lmap, dmq, fmaf(L.c, probe.x, fmaf(-L.s, probe.y, L.x)),
                                fmaf(L.s, probe.x, fmaf(L.c, probe.y, L.y)), probe.z + zc,
                                probe.w, margin);
                 if (two && !sure)
@@ -916,8 +1069,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                     // wave and object) rather than by every wave after the
                     // barrier or kept live in registers
                     int fa, fi;
+                    bool fin_in;
                     const Pose F = entry_pose(gt, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
-                                              ay, zc, &fa, &fi);
+                                              ay, zc, &fa, &fi, rs, &fin_in);
                     if (lane == 0) {
                         float* f = s_found[wave];
                         f[0] = F.x; f[1] = F.y; f[2] = F.z; f[3] = F.c; f[4] = F.s; f[5] = F.yaw;
@@ -1030,20 +1184,23 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
 // batches with up to 128 spheres per object, asked for 5 waves per SIMD
 // (their code sits a few registers above it, and a few bytes of spills cost
 // less than a fifth of the waves; 256-sphere objects would spill far more).
-template <int SPL, bool kLds, bool kGrids, bool kYaw>
+template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kRel>
 __global__ __launch_bounds__(1024) void k_place(SCN_PLACE_PARAMS) {
-    place_scenes<SPL, kLds, kGrids, kYaw>(SCN_PLACE_ARGS);
+    place_scenes<SPL, kLds, kGrids, kYaw, kRel>(SCN_PLACE_ARGS);
 }
 template <int SPL, bool kLds, bool kYaw>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_place_g5(
     SCN_PLACE_PARAMS) {
-    place_scenes<SPL, kLds, true, kYaw>(SCN_PLACE_ARGS);
+    place_scenes<SPL, kLds, true, kYaw, false>(SCN_PLACE_ARGS);
 }
 
-template <int SPL, bool kLds, bool kGrids, bool kYaw>
+// Spatial relations are compiled only into grid-free instances (kRel); a
+// grid batch with relations is refused by the launcher.
+template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kRel>
 static auto place_kernel() {
     if constexpr (kGrids && SPL <= 2) return k_place_g5<SPL, kLds, kYaw>;
-    else return k_place<SPL, kLds, kGrids, kYaw>;
+    else if constexpr (kGrids) return k_place<SPL, kLds, true, kYaw, false>;
+    else return k_place<SPL, kLds, false, kYaw, kRel>;
 }
 
 template <int SPL, bool kLds>
@@ -1051,10 +1208,14 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                    const PlacePlan& plan, int cap_sph, int split, int32_t* chosen,
                                    unsigned long long* ctr, hipStream_t st) {
     const bool yaw = b.geometry == SCN_GEOM_YAW;
-    auto kern = b.grid_off ? (yaw ? place_kernel<SPL, kLds, true, true>()
-                                  : place_kernel<SPL, kLds, true, false>())
-                           : (yaw ? place_kernel<SPL, kLds, false, true>()
-                                  : place_kernel<SPL, kLds, false, false>());
+    const bool relp = b.obj_rel != nullptr;
+    if (relp && b.grid_off) return hipErrorNotSupported;
+    auto kern = b.grid_off ? (yaw ? place_kernel<SPL, kLds, true, true, false>()
+                                  : place_kernel<SPL, kLds, true, false, false>())
+                : relp     ? (yaw ? place_kernel<SPL, kLds, false, true, true>()
+                                  : place_kernel<SPL, kLds, false, false, true>())
+                           : (yaw ? place_kernel<SPL, kLds, false, true, false>()
+                                  : place_kernel<SPL, kLds, false, false, false>());
     const int bytes = 16 * ((kLds ? cap_sph : 0) + kObjLds * plan.cap_obj) + kBoxLdsBytes +
                       (b.grid_off ? 0 : kMapBytes);
     if (bytes > 64 * 1024) {
@@ -1069,7 +1230,7 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                        plan.max_steps, cap_sph, plan.cap_obj, split, plan.split_sph,
                        plan.prop_bins, plan.prop_k, plan.resume, plan.chunk, plan.j_cap,
                        plan.n_active, b.grid_off, b.grid, b.grid_src,
-                       b.grid_val_off, b.grid_val);
+                       b.grid_val_off, b.grid_val, b.obj_rel, b.rel, b.obj_ratio);
     return hipGetLastError();
 }
 

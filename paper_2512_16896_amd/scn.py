@@ -45,7 +45,7 @@ class _Batch(C.Structure):
         [(n, C.c_void_p) for n in (
             "obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
             "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
-            "placed", "n_placed", "status", "rec")]
+            "placed", "n_placed", "status", "rec", "obj_rel", "rel", "obj_ratio")]
 
 
 class _Joints(C.Structure):
@@ -310,6 +310,12 @@ class DeviceBatch:
             self.grid_val_off = t(off, torch.int64)
             self.grid_val = t(np.concatenate(vals), torch.float32)
             n_assets = len(vals)
+        self.obj_rel = self.rel = self.obj_ratio = None
+        if getattr(b, "obj_rel", None) is not None:
+            self.obj_rel = t(b.obj_rel, torch.int32)
+            self.rel = t(np.asarray(b.rel, np.float32).reshape(-1, 16), torch.float32)
+        if getattr(b, "obj_ratio", None) is not None:
+            self.obj_ratio = t(b.obj_ratio, torch.float32)
         n, n_obj, n_sph = b.n_scenes, b.n_objects, b.n_spheres
         self.placed = torch.full((max(n_sph, 1), 4), float("nan"), dtype=torch.float32, device=dev)
         self.n_placed = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
@@ -331,7 +337,7 @@ class DeviceBatch:
         c.geometry = GEOM_YAW if geometry_is_yaw(b) else GEOM_GENERAL
         for name in ("obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
                      "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
-                     "placed", "n_placed", "status", "rec"):
+                     "placed", "n_placed", "status", "rec", "obj_rel", "rel", "obj_ratio"):
             setattr(c, name, None if getattr(self, name) is None else getattr(self, name).data_ptr())
 
     def refresh_geometry(self):
