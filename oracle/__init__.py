@@ -41,7 +41,9 @@ class _Batch(C.Structure):
                 ("box_off", C.c_void_p), ("box", C.c_void_p),
                 ("grid_off", C.c_void_p), ("grid", C.c_void_p), ("grid_src", C.c_void_p),
                 ("grid_val", C.c_void_p), ("scene_id", C.c_void_p),
-                ("obj_rel", C.c_void_p), ("rel", C.c_void_p), ("obj_ratio", C.c_void_p)]
+                ("obj_rel", C.c_void_p), ("rel", C.c_void_p), ("obj_ratio", C.c_void_p),
+                ("robot", C.c_void_p), ("obj_reach", C.c_void_p), ("reach_map", C.c_void_p),
+                ("reach_geom", C.c_void_p)]
 
 
 class _GenArgs(C.Structure):
@@ -77,6 +79,8 @@ def lib():
         L.orc_fk_links.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_uint64, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_fk_rows.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_reach_query.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
         L.orc_sample_relation.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                           C.c_void_p, C.c_double, C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -115,12 +119,20 @@ class _Keep:
         self.rel = None if rel is None else np.ascontiguousarray(b.rel, np.float64).reshape(-1, 16)
         ratio = getattr(b, "obj_ratio", None)
         self.obj_ratio = None if ratio is None else np.ascontiguousarray(ratio, np.float64)
+        self.robot = self.obj_reach = self.reach_map = self.reach_geom = None
+        if getattr(b, "robot", None) is not None:
+            self.robot = np.ascontiguousarray(b.robot, np.float64).reshape(-1, 12)
+            self.obj_reach = np.ascontiguousarray(b.obj_reach, np.float64)
+            self.reach_map = np.ascontiguousarray(b.reach_map, np.uint8)
+            self.reach_geom = np.ascontiguousarray(b.reach_geom, np.float64)
         self.cb = _Batch(int(len(self.obj_off) - 1), _p(self.obj_off), _p(self.sph_off),
                          _p(self.tmpl), _p(self.obj_sup), _p(self.obj_ncand), _p(self.sup),
                          _p(self.box_off), _p(self.box), _p(self.grid_off), _p(self.grid),
                          _p(self.grid_src),
                          C.cast(self.grid_ptrs, C.c_void_p) if self.grid_ptrs is not None else None,
-                         _p(self.scene_id), _p(self.obj_rel), _p(self.rel), _p(self.obj_ratio))
+                         _p(self.scene_id), _p(self.obj_rel), _p(self.rel), _p(self.obj_ratio),
+                         _p(self.robot), _p(self.obj_reach), _p(self.reach_map),
+                         _p(self.reach_geom))
 
 
 # ---------------------------------------------------------------------------
@@ -260,3 +272,19 @@ def relation_row(kind: int, anchors, v=(0.0, 0.0), min_r=0.0, max_r=np.inf, thet
     row[12], row[13], row[14] = min_r, max_r, theta
     row[15] = 1.0 if face_to else 0.0
     return row
+
+
+def reach_query(reach_map, geom, robot, pose, theta, band: float = 1e-6):
+    """Batched reachability queries (oracle.c reachable): object-frame world
+    poses [n][12], robot base poses [n][12], approach angles [n] ->
+    (reachable [n] bool, banded [n] bool)."""
+    m = np.ascontiguousarray(reach_map, np.uint8)
+    g = np.ascontiguousarray(geom, np.float64)
+    r = np.ascontiguousarray(robot, np.float64).reshape(-1, 12)
+    P = np.ascontiguousarray(pose, np.float64).reshape(-1, 12)
+    th = np.ascontiguousarray(theta, np.float64)
+    n = int(P.shape[0])
+    out = np.zeros(n, np.int8)
+    bd = np.zeros(n, np.int8)
+    lib().orc_reach_query(n, _p(m), _p(g), _p(r), _p(P), _p(th), float(band), _p(out), _p(bd))
+    return out.astype(bool), bd.astype(bool)

@@ -88,6 +88,10 @@ typedef struct {
     const int32_t *obj_rel;   /* [n_obj] spatial relation row of the object, -1 none (NULL: none) */
     const double  *rel;       /* [n_rel][16] relation rows (see sample_relation)      */
     const double  *obj_ratio; /* [n_obj] ratio_on_support (NULL: 0)                   */
+    const double  *robot;     /* [n_scenes][12] robot base pose R[9] t[3] (NULL: no reachability) */
+    const double  *obj_reach; /* [n_obj] approach angle of the reachability check, < 0 none */
+    const uint8_t *reach_map; /* 4-D map, 1 = reachable (see reachable())             */
+    const double  *reach_geom;/* lo[4], h[4], dims[4] of the map axes (z*, theta, x*, y*) */
 } orc_batch;
 
 typedef struct {
@@ -246,6 +250,17 @@ yaw:
     return r;
 }
 
+/* World position of an object-frame point c under pose p (as world_sphere). */
+static void world_point(const orc_batch *b, int o, const double c[4], orc_pose p, double out[4])
+{
+    const double *u = b->sup + 16 * b->obj_sup[o];
+    double cs = cos(p.yaw), sn = sin(p.yaw);
+    double l[3] = {cs * c[0] - sn * c[1] + p.x, sn * c[0] + cs * c[1] + p.y, c[2] + p.z};
+    for (int r = 0; r < 3; ++r)
+        out[r] = u[3 * r + 0] * l[0] + u[3 * r + 1] * l[1] + u[3 * r + 2] * l[2] + u[9 + r];
+    out[3] = 0.0;
+}
+
 /* World sphere k of object o at pose p on support u:
  *   world = R_u * (Rz(yaw) * c_k + (x,y,z)) + t_u                             */
 static void world_sphere(const orc_batch *b, int o, int k, orc_pose p, double out[4])
@@ -370,6 +385,56 @@ static double clearance(const orc_batch *b, int s, const double *sph, int n_sph,
         }
     }
     return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reachability (Sec. IV-E): a 4-D map over (z*, theta, x*, y*), the         */
+/* single-structure parametrization of RM4D (Rudorfer et al. 2024) that     */
+/* uses the robot's symmetry about its base z axis.  For an object frame at  */
+/* world position p with x axis d, in the base frame (R_b, t_b):             */
+/*   q = R_b^T (p - t_b),  e = R_b^T d,  psi = angle of (e_x, e_y),          */
+/*   (x*, y*) = (q_x, q_y) turned by -psi about z,  z* = q_z,                */
+/* theta = the object's approach angle.  Cell index i_d = floor((v_d - lo_d) */
+/* / h_d); outside the map, or a zero cell, is not reachable.  A coordinate  */
+/* within `band` of a cell boundary marks the decision as banded.            */
+/* ------------------------------------------------------------------------ */
+static int reachable(const uint8_t *map, const double *geom, const double *robot,
+                     const double p[3], const double d[3], double theta, double band,
+                     int *banded)
+{
+    const double *R = robot, *t = robot + 9;
+    double v[3] = {p[0] - t[0], p[1] - t[1], p[2] - t[2]};
+    double q[3], e[2];
+    for (int c = 0; c < 3; ++c) q[c] = R[c] * v[0] + R[3 + c] * v[1] + R[6 + c] * v[2];
+    for (int c = 0; c < 2; ++c) e[c] = R[c] * d[0] + R[3 + c] * d[1] + R[6 + c] * d[2];
+    double n = sqrt(e[0] * e[0] + e[1] * e[1]);
+    double cs = n > 0.0 ? e[0] / n : 1.0, sn = n > 0.0 ? e[1] / n : 0.0;
+    double coord[4] = {q[2], theta, cs * q[0] + sn * q[1], -sn * q[0] + cs * q[1]};
+    int idx[4];
+    for (int a = 0; a < 4; ++a) {
+        double f = (coord[a] - geom[a]) / geom[4 + a];
+        double fl = floor(f);
+        if (fabs(f - fl) * geom[4 + a] < band || fabs(fl + 1.0 - f) * geom[4 + a] < band) *banded = 1;
+        if (!(f >= 0.0) || !(f < geom[8 + a])) return 0;
+        idx[a] = (int)fl;
+    }
+    long cell = (((long)idx[0] * (long)geom[9] + idx[1]) * (long)geom[10] + idx[2]) * (long)geom[11] + idx[3];
+    return map[cell] != 0;
+}
+
+/* Batched reachability queries (tests): pose[n][12] (world R[9] t[3] of the
+ * object frame), robot[n][12], theta[n] -> out[n] (1 reachable), banded[n]. */
+void orc_reach_query(int n, const uint8_t *map, const double *geom, const double *robot,
+                     const double *pose, const double *theta, double band, int8_t *out,
+                     int8_t *banded)
+{
+    for (int i = 0; i < n; ++i) {
+        const double *P = pose + 12 * i;
+        double p[3] = {P[9], P[10], P[11]}, d[3] = {P[0], P[3], P[6]};
+        int bd = 0;
+        out[i] = (int8_t)reachable(map, geom, robot + 12 * i, p, d, theta[i], band, &bd);
+        banded[i] = (int8_t)bd;
+    }
 }
 
 /* One relation sample (tests): out = x, y, yaw, inside, banded.            */
@@ -500,6 +565,19 @@ void orc_generate(const orc_batch *b, const orc_gen_args *g, orc_gen_out *out)
                         if (!rel_ok || !q.inside) continue;   /* outside the region: not valid */
                         --ncand;
                         p.x = q.x; p.y = q.y; p.yaw = q.yaw;
+                    }
+                    if (b->robot && b->obj_reach && b->obj_reach[o] >= 0.0) {
+                        /* the object frame's world origin and x axis */
+                        double org[4], ex[4];
+                        double c0[4] = {0, 0, 0, 0}, c1[4] = {1, 0, 0, 0};
+                        world_point(b, o, c0, p, org);
+                        world_point(b, o, c1, p, ex);
+                        double d[3] = {ex[0] - org[0], ex[1] - org[1], ex[2] - org[2]};
+                        int bd = 0;
+                        int ok = reachable(b->reach_map, b->reach_geom, b->robot + 12 * s, org, d,
+                                           b->obj_reach[o], g->band_region, &bd);
+                        if (bd) banded = 1;
+                        if (!ok) { ++ncand; continue; }   /* not reachable: not valid */
                     }
                     for (int k = 0; k < ns; ++k) world_sphere(b, o, b->sph_off[o] + k, p, sph + 4 * k);
                     double cl = clearance(b, s, sph, ns, out->placed + 4 * first, n_pl,

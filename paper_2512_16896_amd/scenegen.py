@@ -59,6 +59,11 @@ class SceneBatch:
     obj_rel: Optional[np.ndarray] = None      # int32 [n_obj] relation row, -1 none
     rel: Optional[np.ndarray] = None          # float32 [n_rel,16] relation rows
     obj_ratio: Optional[np.ndarray] = None    # float32 [n_obj] ratio_on_support
+    # reachability (None when absent)
+    robot: Optional[np.ndarray] = None        # float32 [n,12] robot base pose per scene
+    obj_reach: Optional[np.ndarray] = None    # float32 [n_obj] approach angle, < 0 no check
+    reach_map: Optional[np.ndarray] = None    # uint8 [nz, ntheta, nx, ny], 1 = reachable
+    reach_geom: Optional[np.ndarray] = None   # float32 [12] lo[4], h[4], dims[4]
     name: str = ""
     params: dict = dataclasses.field(default_factory=dict)
 
@@ -500,6 +505,57 @@ def relation_scenes(n_scenes: int = 4096, seed: int = 0, n_sph: int = 32, n_cand
         params=dict(n_scenes=n_scenes, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand, seed=seed))
 
 
+# Synthetic reachability map of a 6-axis arm (no robot model is available):
+# axes (z*, theta, x*, y*) of the base-symmetric parametrization, with the
+# reachable shell of a shoulder 0.35 m above the base (0.25 .. 0.80 m, the
+# outer radius shrinking by 0.15 m towards side approaches), a floor 0.25 m
+# below the base and a wrist limit x* >= -0.15 m (the object's x axis may not
+# point back at the base by much).  Values at the cell centres.
+REACH_LO = (-0.3, -np.pi / 32, -1.0, -1.0)     # approach angles 0, pi/16, ... at cell centres
+REACH_H = (0.05, np.pi / 16, 1.0 / 32, 1.0 / 32)
+REACH_DIMS = (24, 9, 64, 64)
+
+
+def reach_map():
+    c = [REACH_LO[a] + REACH_H[a] * (np.arange(REACH_DIMS[a]) + 0.5) for a in range(4)]
+    z, th, x, y = np.meshgrid(*c, indexing="ij")
+    rho = np.sqrt(x * x + y * y + (z - 0.35) ** 2)
+    ok = (rho >= 0.25) & (rho <= 0.80 - 0.15 * th / (np.pi / 2)) & (z >= -0.25) & (x >= -0.15)
+    geom = np.array(list(REACH_LO) + list(REACH_H) + list(REACH_DIMS), np.float32)
+    return ok.astype(np.uint8), geom
+
+
+def reach_scenes(n_scenes: int = 4096, seed: int = 0, n_obj: int = 8, n_sph: int = 32,
+                 n_cand: int = 256, n_box: int = 4, side=(0.05, 0.15),
+                 rad=(0.01, 0.03)) -> SceneBatch:
+    """Robot-manipulation tables (Sec. IV-E): a 1.2 x 0.8 m support at a
+    random world pose with n_box cuboids and a robot base 0.15 m off the
+    middle of its near long edge, 0.2 m below the top, facing across the
+    table; every object must be reachable, objects 0..5 from above
+    (approach angle 0), the rest at 45 degrees."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x2EAC]))
+    hx, hy = 0.6, 0.4
+    sup_R, sup_t = _support_poses(rng, n_scenes)
+    sup = _support_rows(sup_R, sup_t, hx, hy, 0.0, 0.0)
+    obj_off = np.arange(n_scenes + 1, dtype=np.int64) * n_obj
+    sph_off, tmpl = _templates(rng, n_scenes * n_obj, n_sph, side, rad)
+    perm = _footprint_order(obj_off, sph_off, tmpl)
+    sph_off, tmpl = _reorder_objects(perm, sph_off, tmpl)
+    box_off, box = _boxes(rng, n_scenes, n_box, hx, hy, 0.5, sup_R, sup_t, half=(0.05, 0.2))
+    Rb = np.einsum('nij,jk->nik', sup_R, rotz(np.array(np.pi / 2)))
+    tb = np.einsum('nij,j->ni', sup_R, np.array([0.0, -hy - 0.15, -0.2])) + sup_t
+    robot = np.concatenate([Rb.reshape(n_scenes, 9), tb], 1).astype(np.float32)
+    reach = np.tile(np.array([0.0] * 6 + [np.pi / 4] * (n_obj - 6), np.float32), n_scenes)
+    m, geom = reach_map()
+    return SceneBatch(
+        obj_off=obj_off.astype(np.int32), sph_off=sph_off.astype(np.int32),
+        tmpl=tmpl.astype(np.float32), obj_sup=np.repeat(np.arange(n_scenes), n_obj).astype(np.int32),
+        obj_ncand=np.full(n_scenes * n_obj, n_cand, np.int32), sup=sup,
+        box_off=box_off.astype(np.int32), box=box, robot=robot, obj_reach=reach, reach_map=m,
+        reach_geom=geom, name=f"reach-{n_scenes}",
+        params=dict(n_scenes=n_scenes, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand, seed=seed))
+
+
 def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
     """The scenes `scenes` of a batch as a batch of their own, plus the
     original scene indices (which the random-number counters must keep)."""
@@ -528,6 +584,10 @@ def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
         out.rel = b.rel
     if b.obj_ratio is not None:
         out.obj_ratio = b.obj_ratio[objs].copy()
+    if b.robot is not None:
+        out.robot = b.robot[scenes].copy()
+        out.obj_reach = b.obj_reach[objs].copy()
+        out.reach_map, out.reach_geom = b.reach_map, b.reach_geom
     if b.grid_off is not None:
         grids = _ranges(b.grid_off[scenes], b.grid_off[scenes + 1] - b.grid_off[scenes])
         goff = np.zeros(len(scenes) + 1, np.int64)
