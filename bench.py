@@ -68,6 +68,13 @@ WORKLOADS = {
                            make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                         fromlist=["x"]).relation_scenes(4096, seed=seed),
                            ncand=256, cpu_scenes=0),
+    "reach-4096": dict(desc="4096 robot tables (1.2x0.8 m, 4 cuboids, robot base 0.15 m off the "
+                            "near edge); 8 objects x 32 spheres that must be reachable on a "
+                            "24x9x64x64 base-symmetric 4-D map (6 from above, 2 at 45 deg); 256 "
+                            "candidates per attempt; margin 5 mm; 10 retries",
+                       make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                    fromlist=["x"]).reach_scenes(4096, seed=seed),
+                       ncand=256, cpu_scenes=0),
     "drawers-4096": dict(desc="4096 two-drawer cabinets at random world poses; drawers are "
                               "prismatic joints with travel U[0, 0.35] m drawn per scene by the "
                               "batched forward kinematics, which moves their walls (boxes) and "
@@ -437,6 +444,39 @@ def drawers_leg(ctx, steps, warmup):
     return out
 
 
+def reach_query_leg(ctx, n=1 << 22):
+    """scn_reach_query alone: n queries (random robot bases, object poses and
+    approach angles) against the synthetic map; queries per second."""
+    import torch
+    from paper_2512_16896_amd import scn, scenegen as sg
+    m, g = sg.reach_map()
+    rng = np.random.default_rng(1)
+    robot = np.zeros((n, 12), np.float32)
+    robot[:, 0] = robot[:, 4] = robot[:, 8] = 1.0
+    pose = np.zeros((n, 12), np.float32)
+    yaw = rng.uniform(0, 2 * np.pi, n)
+    pose[:, 0], pose[:, 1], pose[:, 3], pose[:, 4], pose[:, 8] = \
+        np.cos(yaw), -np.sin(yaw), np.sin(yaw), np.cos(yaw), 1.0
+    pose[:, 9:] = rng.uniform(-1, 1, (n, 3))
+    dev = torch.device("cuda", 0)
+    dm = torch.tensor(m.ravel(), device=dev)
+    tr, tp = torch.tensor(robot, device=dev), torch.tensor(pose, device=dev)
+    th = torch.tensor(rng.uniform(0, 1.5, n).astype(np.float32), device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        scn.reach_query(ctx, dm, g, tr, tp, th)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        scn.reach_query(ctx, dm, g, tr, tp, th)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    return {"queries": n, "us_per_call": 1e3 * ms, "queries_per_s": n / (ms * 1e-3),
+            "bytes_per_query": 12 * 4 * 2 + 4 + 1,
+            "hbm_gbs": n * (12 * 4 * 2 + 4 + 1) / (ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -506,6 +546,8 @@ def main():
         out["shelves_65536"] = extra_workload(ctx, "shelves-65536", 5, 1)
         out["drawers_4096"] = drawers_leg(ctx, 20, 3)
         out["relations_4096"] = extra_workload(ctx, "relations-4096", 20, 3)
+        out["reach_4096"] = extra_workload(ctx, "reach-4096", 20, 3)
+        out["reach_4096"]["reach_query"] = reach_query_leg(ctx)
     print(json.dumps(out), flush=True)
     ctx.close()
 

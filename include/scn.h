@@ -122,6 +122,21 @@ typedef struct {
  */
 #define SCN_GEOM_GENERAL 0
 #define SCN_GEOM_YAW 1
+
+/* Reachability map (Sec. IV-E): a 4-D map over (z*, theta, x*, y*), the
+ * base-symmetric single-structure parametrization of the reachability map
+ * the paper uses.  For an object frame at world position p with x axis d and
+ * a robot base at (R_b, t_b): q = R_b^T (p - t_b), e = R_b^T d, psi = the
+ * angle of (e_x, e_y); (x*, y*) = (q_x, q_y) turned by -psi about z, z* = q_z;
+ * theta = the object's approach angle.  Cell i_a = floor((v_a - lo[a]) /
+ * h[a]) on each axis (z*, theta, x*, y*, with y* fastest in `map`); a query
+ * outside the map or on a zero cell is not reachable.                       */
+typedef struct {
+    const uint8_t *map;    /* device, dims[0] * dims[1] * dims[2] * dims[3] bytes */
+    float lo[4], h[4];     /* host values                                         */
+    int32_t dims[4];
+} scn_reach_map;
+
 typedef struct scn_batch {
     int32_t n_scenes, n_objects, n_spheres, n_supports, n_boxes, n_grids, n_grid_assets;
     int32_t max_objects_per_scene, max_spheres_per_object, max_spheres_per_scene;
@@ -170,6 +185,13 @@ typedef struct scn_batch {
     const int32_t *obj_rel;
     const float *rel;
     const float *obj_ratio;
+    /* Reachability (Sec. IV-E), optional (robot NULL: none), read by the
+     * place calls: a candidate of an object with obj_reach[o] >= 0 (its
+     * approach angle) that the robot of its scene (robot [n_scenes][12]:
+     * base pose R[9], t[3]) cannot reach, by `reach`, is not valid.         */
+    const float *robot;
+    const float *obj_reach;
+    scn_reach_map reach;
 } scn_batch;
 
 /* Candidate poses in the support frame, structure of arrays (device). */
@@ -335,6 +357,15 @@ int scn_generate_scenes(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
 #define SCN_NOALLOC_MAX_SCENES (1 << 20)
 int scn_generate_scenes_noalloc(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
                                 scn_stream stream);
+
+/* ---- reachability queries --------------------------------------------- */
+
+/* Batched reachability (Sec. IV-E: the map on the GPU, queries batched):
+ * pose [n][12] world pose (R[9], t[3]) of each object frame, robot [n][12]
+ * the robot base pose of each query, theta [n] approach angles (device);
+ * out [n] (device, uint8) = 1 if reachable by `map`.  Asynchronous.        */
+int scn_reach_query(scn_ctx *ctx, const scn_reach_map *map, int32_t n, const float *robot,
+                    const float *pose, const float *theta, uint8_t *out, scn_stream stream);
 
 /* ---- articulated parts: batched forward kinematics --------------------- */
 

@@ -339,9 +339,17 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
         return fail(SCN_E_INVALID_ARG, "default_ncand must be > 0 when obj_ncand is NULL");
     const int S = b->max_spheres_per_object;
     if (S > 256) return fail(SCN_E_UNSUPPORTED, "max_spheres_per_object %d > 256", S);
-    if (b->obj_rel && b->grid_off)
-        return fail(SCN_E_UNSUPPORTED, "spatial relations in voxel-grid batches are not supported");
+    if ((b->obj_rel || b->robot) && b->grid_off)
+        return fail(SCN_E_UNSUPPORTED,
+                    "spatial relations or reachability in voxel-grid batches are not supported");
     if (b->obj_rel && !b->rel) return fail(SCN_E_INVALID_ARG, "obj_rel given without rel");
+    if (b->robot) {
+        if (!b->obj_reach || !b->reach.map)
+            return fail(SCN_E_INVALID_ARG, "robot given without obj_reach / reach.map");
+        for (int a = 0; a < 4; ++a)
+            if (b->reach.dims[a] <= 0 || !(b->reach.h[a] > 0.f))
+                return fail(SCN_E_INVALID_ARG, "reach map axis %d: dims and h must be > 0", a);
+    }
     plan->spl = S <= 64 ? 1 : (S <= 128 ? 2 : 4);
     int sched = a->schedule;
     if (sched == 0) {

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "scn.h"
+
 namespace scn {
 
 constexpr int kWave = 64;
@@ -216,6 +218,32 @@ __device__ __forceinline__ float grid_box_d2(const float* G, float px, float py,
     const float dy = fmaxf(fmaxf(G[13] - gy, gy - (G[13] + ey)), 0.f);
     const float dz = fmaxf(fmaxf(G[14] - gz, gz - (G[14] + ez)), 0.f);
     return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+// Reachability of an object frame at world position p with x axis d by the
+// robot at base pose rb (R[9], t[3]) on the 4-D map (z*, theta, x*, y*):
+// base-frame position turned by the object's yaw about the base z axis.
+__device__ __forceinline__ bool reach_ok(const uint8_t* __restrict__ map, const scn_reach_map& m,
+                                         const float* rb, float px, float py, float pz, float dx,
+                                         float dy, float dz, float theta) {
+    const float vx = px - rb[9], vy = py - rb[10], vz = pz - rb[11];
+    const float qx = fmaf(rb[0], vx, fmaf(rb[3], vy, rb[6] * vz));
+    const float qy = fmaf(rb[1], vx, fmaf(rb[4], vy, rb[7] * vz));
+    const float qz = fmaf(rb[2], vx, fmaf(rb[5], vy, rb[8] * vz));
+    const float ex = fmaf(rb[0], dx, fmaf(rb[3], dy, rb[6] * dz));
+    const float ey = fmaf(rb[1], dx, fmaf(rb[4], dy, rb[7] * dz));
+    const float n = sqrtf(fmaf(ex, ex, ey * ey));
+    const float cs = n > 0.f ? ex / n : 1.f, sn = n > 0.f ? ey / n : 0.f;
+    const float v[4] = {qz, theta, fmaf(cs, qx, sn * qy), fmaf(-sn, qx, cs * qy)};
+    int idx[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const float f = floorf((v[a] - m.lo[a]) / m.h[a]);
+        if (!(f >= 0.f) || !(f < (float)m.dims[a])) return false;
+        idx[a] = (int)f;
+    }
+    const size_t cell = (((size_t)idx[0] * m.dims[1] + idx[1]) * m.dims[2] + idx[2]) * m.dims[3] + idx[3];
+    return map[cell] != 0;
 }
 
 __device__ __forceinline__ float bcast(float v, int lane) {

@@ -14,10 +14,10 @@ namespace {
 // spheres only: batches with voxel grids, or more supports than scenes (some
 // scene's objects on several supports), are outside what it computes.
 int check_single_support(const scn_batch* b) {
-    if (b->obj_rel || b->obj_ratio)
+    if (b->obj_rel || b->obj_ratio || b->robot)
         return scn_fail(SCN_E_UNSUPPORTED,
-                        "the learned proposal does not support spatial relations or "
-                        "ratio_on_support (its bins cover the whole support)");
+                        "the learned proposal does not support spatial relations, "
+                        "ratio_on_support or reachability (its bins cover the whole support)");
     if (b->grid_off)
         return scn_fail(SCN_E_UNSUPPORTED, "the learned proposal does not support voxel-grid batches");
     if (b->n_supports > b->n_scenes)

@@ -476,12 +476,14 @@ __device__ __forceinline__ unsigned long long reachable_boxes(const ObjConsts& K
     const int32_t* __restrict__ grid_off, const float* __restrict__ grid, \
     const int32_t* __restrict__ grid_src, const int64_t* __restrict__ grid_val_off, \
     const float* __restrict__ grid_val, const int32_t* __restrict__ obj_rel, \
-    const float* __restrict__ rel, const float* __restrict__ obj_ratio
+    const float* __restrict__ rel, const float* __restrict__ obj_ratio, \
+    const float* __restrict__ robot, const float* __restrict__ obj_reach, scn_reach_map rmap
 #define SCN_PLACE_ARGS \
     obj_off, sph_off, tmpl, obj_sup, obj_ncand, sup, box_off, box, placed, n_placed, status, rec, chosen, counters, order, seed, margin, retries, default_ncand, max_steps, cap_sph, cap_obj, split, split_sph, prop_bins, prop_k, resume, chunk, j_cap, n_active, \
-    grid_off, grid, grid_src, grid_val_off, grid_val, obj_rel, rel, obj_ratio
+    grid_off, grid, grid_src, grid_val_off, grid_val, obj_rel, rel, obj_ratio, robot, obj_reach, \
+    rmap
 
-template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kRel>
+template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons>
 __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     // placed objects covered by a candidate's object mask: 64 per word; the
     // dense multi-shelf (grid) scenes carry 100 objects, so they get two words
@@ -723,13 +725,16 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             }
         }
         const float ax = U.hx - U.inset - ero, ay = U.hy - U.inset - ero, zc = U.lift + lift;
-        // spatial relations: instances for batches that have them (kRel)
+        // spatial relations and reachability: instances for batches that
+        // have them (kCons)
         const RelState* rs = nullptr;
-        if constexpr (kRel) {
+        float reach_theta = -1.f;
+        if constexpr (kCons) {
             const int rel_row = obj_rel ? obj_rel[o] : -1;
             if (rel_row >= 0 && threadIdx.x == 0)
                 relation_setup(s_rel, rel + 16 * rel_row, j, o0, obj_sup, o, rec, ax, ay);
             if (rel_row >= 0) rs = &s_rel;
+            if (robot && obj_reach) reach_theta = obj_reach[o];
         }
         // planar form: supports and boxes turn about z only; world z of each
         // sphere, of the bounding centre and of the probe is then the same
@@ -853,9 +858,25 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 to_world(U, L, probe.x, probe.y, probe.z, qx, qy, qz);
                 to_world(U, L, probe2.x, probe2.y, probe2.z, ux, uy, uz);
             }
-            // rejected: a point outside its relation's region, or a probe
-            // that collides
+            // rejected: a point outside its relation's region, one the robot
+            // cannot reach, or a probe that collides
             bool sure = !inside;
+            if constexpr (kCons) {
+                if (reach_theta >= 0.f && !sure) {
+                    const float* rb = robot + 12 * s;
+                    float ox, oy, oz, dx, dy, dz;
+                    if constexpr (kYaw) {
+                        ox = M.Tx; oy = M.Ty; oz = zc + U.t[2];
+                        dx = M.C; dy = M.S; dz = 0.f;
+                    } else {
+                        to_world(U, L, 0.f, 0.f, 0.f, ox, oy, oz);
+                        dx = fmaf(U.R[0], L.c, U.R[1] * L.s);
+                        dy = fmaf(U.R[3], L.c, U.R[4] * L.s);
+                        dz = fmaf(U.R[6], L.c, U.R[7] * L.s);
+                    }
+                    sure = !reach_ok(rmap.map, rmap, rb, ox, oy, oz, dx, dy, dz, reach_theta);
+                }
+            }
             unsigned long long bmask = 0, gmask = 0;
             // the probes against the depth map of the placed spheres first:
             // the cheapest rejection
@@ -1184,9 +1205,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
 // batches with up to 128 spheres per object, asked for 5 waves per SIMD
 // (their code sits a few registers above it, and a few bytes of spills cost
 // less than a fifth of the waves; 256-sphere objects would spill far more).
-template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kRel>
+template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons>
 __global__ __launch_bounds__(1024) void k_place(SCN_PLACE_PARAMS) {
-    place_scenes<SPL, kLds, kGrids, kYaw, kRel>(SCN_PLACE_ARGS);
+    place_scenes<SPL, kLds, kGrids, kYaw, kCons>(SCN_PLACE_ARGS);
 }
 template <int SPL, bool kLds, bool kYaw>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_place_g5(
@@ -1194,13 +1215,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void 
     place_scenes<SPL, kLds, true, kYaw, false>(SCN_PLACE_ARGS);
 }
 
-// Spatial relations are compiled only into grid-free instances (kRel); a
-// grid batch with relations is refused by the launcher.
-template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kRel>
+// Spatial relations and reachability are compiled only into grid-free
+// instances (kCons); a grid batch with either is refused by the launcher.
+template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons>
 static auto place_kernel() {
     if constexpr (kGrids && SPL <= 2) return k_place_g5<SPL, kLds, kYaw>;
     else if constexpr (kGrids) return k_place<SPL, kLds, true, kYaw, false>;
-    else return k_place<SPL, kLds, false, kYaw, kRel>;
+    else return k_place<SPL, kLds, false, kYaw, kCons>;
 }
 
 template <int SPL, bool kLds>
@@ -1208,7 +1229,7 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                    const PlacePlan& plan, int cap_sph, int split, int32_t* chosen,
                                    unsigned long long* ctr, hipStream_t st) {
     const bool yaw = b.geometry == SCN_GEOM_YAW;
-    const bool relp = b.obj_rel != nullptr;
+    const bool relp = b.obj_rel != nullptr || b.robot != nullptr;
     if (relp && b.grid_off) return hipErrorNotSupported;
     auto kern = b.grid_off ? (yaw ? place_kernel<SPL, kLds, true, true, false>()
                                   : place_kernel<SPL, kLds, true, false, false>())
@@ -1230,7 +1251,8 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                        plan.max_steps, cap_sph, plan.cap_obj, split, plan.split_sph,
                        plan.prop_bins, plan.prop_k, plan.resume, plan.chunk, plan.j_cap,
                        plan.n_active, b.grid_off, b.grid, b.grid_src,
-                       b.grid_val_off, b.grid_val, b.obj_rel, b.rel, b.obj_ratio);
+                       b.grid_val_off, b.grid_val, b.obj_rel, b.rel, b.obj_ratio, b.robot,
+                       b.obj_reach, b.reach);
     return hipGetLastError();
 }
 

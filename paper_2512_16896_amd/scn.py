@@ -37,6 +37,11 @@ class PoseRec(C.Structure):
                 ("attempt", C.c_int32), ("idx", C.c_int32)]
 
 
+class _ReachMap(C.Structure):
+    _fields_ = [("map", C.c_void_p), ("lo", C.c_float * 4), ("h", C.c_float * 4),
+                ("dims", C.c_int32 * 4)]
+
+
 class _Batch(C.Structure):
     _fields_ = [(n, C.c_int32) for n in (
         "n_scenes", "n_objects", "n_spheres", "n_supports", "n_boxes", "n_grids", "n_grid_assets",
@@ -45,7 +50,8 @@ class _Batch(C.Structure):
         [(n, C.c_void_p) for n in (
             "obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
             "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
-            "placed", "n_placed", "status", "rec", "obj_rel", "rel", "obj_ratio")]
+            "placed", "n_placed", "status", "rec", "obj_rel", "rel", "obj_ratio", "robot",
+            "obj_reach")] + [("reach", _ReachMap)]
 
 
 class _Joints(C.Structure):
@@ -111,6 +117,7 @@ def _load():
         "scn_generate_scenes_noalloc": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), vp],
         "scn_forward_kinematics": [vp, C.POINTER(_Joints), u64, i32, vp, vp, i32, vp, vp, vp,
                                    i32, vp, vp, vp, vp],
+        "scn_reach_query": [vp, C.POINTER(_ReachMap), i32, vp, vp, vp, vp, vp],
         "scn_autotune": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs), C.POINTER(C.c_int32),
                          C.POINTER(C.c_float), vp],
         "scn_autotune_save": [vp, C.c_char_p],
@@ -144,7 +151,8 @@ EXPORTS = ("scn_ctx_create", "scn_ctx_destroy", "scn_status_string", "scn_last_e
            "scn_workspace_bytes", "scn_set_workspace", "scn_reset_counters",
            "scn_read_counters", "scn_sample_poses", "scn_check_batch",
            "scn_reset_scenes", "scn_place_step", "scn_generate_scenes",
-           "scn_generate_scenes_noalloc", "scn_forward_kinematics", "scn_autotune",
+           "scn_generate_scenes_noalloc", "scn_forward_kinematics", "scn_reach_query",
+           "scn_autotune",
            "scn_autotune_save", "scn_autotune_load", "scn_mlp_init", "scn_mlp_forward",
            "scn_mlp_backward", "scn_mlp_train_step", "scn_descriptors", "scn_heightmaps",
            "scn_features", "scn_proposal_topk", "scn_harvest_labels",
@@ -316,6 +324,11 @@ class DeviceBatch:
             self.rel = t(np.asarray(b.rel, np.float32).reshape(-1, 16), torch.float32)
         if getattr(b, "obj_ratio", None) is not None:
             self.obj_ratio = t(b.obj_ratio, torch.float32)
+        self.robot = self.obj_reach = self.reach_map = None
+        if getattr(b, "robot", None) is not None:
+            self.robot = t(np.asarray(b.robot, np.float32).reshape(-1, 12), torch.float32)
+            self.obj_reach = t(b.obj_reach, torch.float32)
+            self.reach_map = t(np.asarray(b.reach_map, np.uint8).ravel(), torch.uint8)
         n, n_obj, n_sph = b.n_scenes, b.n_objects, b.n_spheres
         self.placed = torch.full((max(n_sph, 1), 4), float("nan"), dtype=torch.float32, device=dev)
         self.n_placed = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
@@ -337,8 +350,11 @@ class DeviceBatch:
         c.geometry = GEOM_YAW if geometry_is_yaw(b) else GEOM_GENERAL
         for name in ("obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
                      "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
-                     "placed", "n_placed", "status", "rec", "obj_rel", "rel", "obj_ratio"):
+                     "placed", "n_placed", "status", "rec", "obj_rel", "rel", "obj_ratio",
+                     "robot", "obj_reach"):
             setattr(c, name, None if getattr(self, name) is None else getattr(self, name).data_ptr())
+        if self.reach_map is not None:
+            c.reach = reach_map_struct(self.reach_map, b.reach_geom)
 
     def refresh_geometry(self):
         """Re-derive the declared geometry class from the device's support and
@@ -435,6 +451,27 @@ def forward_kinematics(ctx: Context, joints: Joints, db: Optional["DeviceBatch"]
         _ptr(joints.box_local) if nb else None, _ptr(db.box) if nb else None, ns,
         _ptr(joints.sup_link) if ns else None, _ptr(joints.sup_local) if ns else None,
         _ptr(db.sup) if ns else None, _stream(stream)))
+
+
+def reach_map_struct(dev_map: torch.Tensor, geom) -> _ReachMap:
+    """scn_reach_map over a device uint8 map; geom = lo[4], h[4], dims[4]."""
+    g = np.asarray(geom, np.float64)
+    m = _ReachMap()
+    m.map = dev_map.data_ptr()
+    for a in range(4):
+        m.lo[a], m.h[a], m.dims[a] = float(g[a]), float(g[4 + a]), int(g[8 + a])
+    return m
+
+
+def reach_query(ctx: Context, dev_map: torch.Tensor, geom, robot: torch.Tensor,
+                pose: torch.Tensor, theta: torch.Tensor, stream=None) -> torch.Tensor:
+    """scn_reach_query: reachable flags (uint8) of n object-frame world poses."""
+    n = int(pose.shape[0])
+    out = torch.empty(max(n, 1), dtype=torch.uint8, device=pose.device)
+    m = reach_map_struct(dev_map, geom)
+    _ok(_lib.scn_reach_query(ctx.h, C.byref(m), n, _ptr(robot), _ptr(pose), _ptr(theta),
+                             _ptr(out), _stream(stream)))
+    return out[:n]
 
 
 NOALLOC_MAX_SCENES = 1 << 20
