@@ -211,9 +211,12 @@ typedef struct {
                             * refreshes its arguments each call; the learned
                             * generation captures its step launch once per call */
     int32_t fallback_chunk;/* scn_generate_scenes_learned: uniform fallback entries
-                            * tried per step launch (0: one attempt of the largest
-                            * candidate count; < 0: the whole fallback at once)     */
-    int32_t reserved[3];   /* zero                                                  */
+                            * a pending object tries per tick (<= 0: all that
+                            * remain, in one launch)                                */
+    int32_t wide_schedule; /* scn_generate_scenes_learned: schedule of its
+                            * latency-bound launches (0: 4 waves, placed spheres
+                            * from global memory)                                   */
+    int32_t reserved[2];   /* zero                                                  */
 } scn_gen_args;
 
 /* Work counters accumulated on the device since the last scn_reset_counters. */
@@ -545,15 +548,21 @@ int scn_harvest_labels(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state,
  * pose bins of its state with the network, its top_k bins (one pose drawn in
  * each) are checked in rank order before the uniform attempts, and the exact
  * check alone decides validity.  Records of proposal picks have attempt = -2
- * and idx = rank.  Runs as a sequence of step launches; each tries the
- * proposals and args->fallback_chunk uniform entries of every scene's current
- * object and resumes the rest in the next launch, which gives the same
- * placements as one pass over the whole list.  The host waits on `stream`
- * after each step launch to read how many scenes still have work (one int),
- * so the call returns with the stream drained.  args->schedule 0 selects
- * 0xF02 here (2 waves, placed spheres from global memory), not the context's
- * tuned or default plain schedule: step launches last as long as their
- * slowest scene, and fewer waves per scene measured faster.                 */
+ * and idx = rank.  Runs as ticks on `stream` and a second stream of the
+ * context (default priority): each tick splits the scenes with work into
+ * those starting an object and those with a pending one; the first run the
+ * network over their compacted rows and try their proposals, while the
+ * others try args->fallback_chunk more uniform entries (<= 0: all) on the
+ * second stream.  Scenes progress independently and every scene's list is
+ * tried in order, which gives the placements of one pass over the whole
+ * list.  Launch sizes are fixed; kernels read the list sizes on the device.
+ * The host reads the two list sizes (8 bytes) after a first batch of ticks
+ * as long as a scene's object count, then every 8 ticks, so the call
+ * returns with the stream drained.  args->schedule (0: one wave per scene)
+ * shapes the first ticks' new-object launches, args->wide_schedule (0: 4
+ * waves) the rest; neither is the context's tuned plain schedule.  The
+ * workspace also keeps each scene's depth map, each placed object's bounding
+ * sphere and each object's constants across the ticks.                    */
 int scn_generate_scenes_learned(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
                                 const scn_mlp *net, int32_t top_k, scn_stream stream);
 

@@ -173,6 +173,9 @@ int scn_ctx_destroy(scn_ctx* c) {
     if (c->h_flag) (void)hipHostFree(c->h_flag);
     for (auto& kv : c->plain_graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+    for (auto e : c->ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return SCN_OK;
 }
@@ -422,22 +425,33 @@ int scn_place_step(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int32_t* cho
     return run_place(c, b, a, plan, chosen, false, (hipStream_t)stream);
 }
 
-// Plan + launch of the fused place kernel with an optional proposal list
-// (used by the learned generation pipeline; not part of the ABI).
-__attribute__((visibility("hidden"))) int scn_place_internal(
-    scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps, int32_t* chosen, bool reset,
-    const int32_t* prop_bins, int prop_k, int32_t* resume, int chunk, int j_cap,
-    int32_t* n_active, void* order_ws, hipStream_t st) {
-    if (int r = check_batch(b, true)) return r;
+// One object step of the scenes rows[0 .. *n_rows) (a list compacted on the
+// device; the launch covers n_scenes workgroups and the rest leave at once),
+// for the learned pipeline: entries per `chunk` as in scn_place_internal.
+__attribute__((visibility("hidden"))) int scn_place_rows(
+    scn_ctx* c, scn_batch* b, const scn_gen_args* a, const int32_t* prop_bins, int prop_k,
+    int32_t* resume, int chunk, int j_cap, const int32_t* rows, const int32_t* n_rows,
+    void* map_keep, void* bnd_keep, const void* info_keep, hipStream_t st) {
+    // the launch order is the list's: no longest-first order is computed
+    scn_gen_args a1 = *a;
+    if (a1.schedule != 0) a1.schedule &= ~SCN_SCHED_LONGEST_FIRST;
+    a = &a1;
     scn::PlacePlan plan;
-    if (int r = plan_place(c, b, a, max_steps, &plan, order_ws)) return r;
+    if (int r = plan_place(c, b, a, 1, &plan, nullptr)) return r;
+    plan.order = const_cast<int32_t*>(rows);   // read only by the kernel
+    plan.hist = nullptr;
+    plan.n_order = n_rows;
     plan.prop_bins = prop_bins;
     plan.prop_k = prop_bins ? prop_k : 0;
     plan.resume = resume;
     plan.chunk = chunk;
     plan.j_cap = j_cap;
-    plan.n_active = n_active;
-    return run_place(c, b, a, plan, chosen, reset, st);
+    plan.n_active = nullptr;
+    plan.map_keep = map_keep;
+    plan.bnd_keep = bnd_keep;
+    plan.info_keep = info_keep;
+    SCN_HIP(scn::launch_place(*b, *a, plan, nullptr, c->d_counters, st));
+    return SCN_OK;
 }
 
 // The generation's launches (reset, scene order, place kernel) as a hipGraph:

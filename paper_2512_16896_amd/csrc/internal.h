@@ -19,6 +19,8 @@ struct scn_ctx {
     size_t ws_bytes = 0;
     int32_t* h_flag = nullptr;   // pinned host words for small device-to-host reads
     hipStream_t cap_stream = nullptr;   // stream used only to capture graphs
+    hipStream_t aux_stream = nullptr;   // second stream of the learned pipeline (default priority)
+    hipEvent_t ev[2] = {nullptr, nullptr};   // its fork / join events
     std::map<std::string, hipGraphExec_t> plain_graphs;   // generation graphs per batch + plan
     struct Tuned { int schedule; float ms; };
     std::map<std::string, Tuned> tuned;   // autotuned schedule per batch shape bucket
@@ -44,9 +46,10 @@ size_t ws_learned_bytes(const scn_batch* b, const scn_mlp* n, int top_k);
 }  // namespace scn
 
 // Network forward with the hidden activations in `act_ws`
-// (ws_mlp_forward_bytes of it); used by the learned generation.
+// (ws_mlp_forward_bytes of it); used by the learned generation.  With m_dev
+// the live row count min(M, *m_dev) is read on the device.
 int scn_mlp_forward_ws(const scn_mlp* n, const uint16_t* x, int M, float* logits, void* act_ws,
-                       hipStream_t st);
+                       hipStream_t st, const int32_t* m_dev = nullptr);
 
 #define SCN_HIP(call)                                                                      \
     do {                                                                                   \
@@ -84,6 +87,7 @@ enum PlaceMode {
 
 struct PlacePlan {
     int32_t* order;   // scene launch order (nullptr: batch order), in the workspace
+    const int32_t* n_order = nullptr;   // device count of `order`'s live entries (nullptr: all)
     int32_t* hist;    // its bucket counters (kOrderBuckets + 1), in the workspace
     int waves;        // waves per workgroup (candidates in flight per scene)
     int spl;          // template spheres per lane (1, 2 or 4)
@@ -97,12 +101,19 @@ struct PlacePlan {
     // Resumable lists (learned path): a launch tries the proposals plus
     // `chunk` uniform entries of the current object (then `chunk` per launch)
     // and, when none is valid and entries remain, leaves the object pending
-    // with resume[s] = the next entry.  chunk <= 0: the whole list.
+    // with resume[s] = the next entry.  chunk == 0: the whole list; chunk < 0:
+    // the proposals alone (the uniform entries in later launches).
     int32_t* resume = nullptr;
     int chunk = 0;
     int j_cap = 0;                 // objects per scene in total (<= 0: all)
     int32_t* n_active = nullptr;   // [2]: scenes left active with work remaining, and those
                                    // of them that start a new object next
+    // State kept across the launches of one generation (learned pipeline):
+    // each scene's depth map (kMapBytes), each placed object's world bounding
+    // sphere (float4) and each object's constants (4 float4, k_object_info).
+    void* map_keep = nullptr;
+    void* bnd_keep = nullptr;
+    const void* info_keep = nullptr;
 };
 
 // learned-proposal kernels (learned.hip)
@@ -110,18 +121,19 @@ hipError_t launch_descriptor(const scn_batch& b, float* desc, hipStream_t st);
 hipError_t launch_hmap_boxes(const scn_batch& b, float* hmap, hipStream_t st);
 hipError_t launch_hmap_raise(const scn_batch& b, const int32_t* obj_idx, const int32_t* n_state,
                              float* hmap, hipStream_t st);
-hipError_t launch_next_object(const scn_batch& b, const int32_t* resume, int j_cap,
-                              int32_t* obj_idx, hipStream_t st);
-hipError_t launch_last_object(const scn_batch& b, const int32_t* before, int32_t* obj_idx,
-                              hipStream_t st);
 hipError_t launch_features(int n, const float* hmap, const float* desc, const int32_t* obj_idx,
-                           int ld, void* x, hipStream_t st);
+                           int ld, void* x, hipStream_t st, const int32_t* rows = nullptr,
+                           const int32_t* m_dev = nullptr);
 hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active, int32_t* bins,
-                       hipStream_t st);
+                       hipStream_t st, const int32_t* rows = nullptr,
+                       const int32_t* m_dev = nullptr);
+hipError_t launch_hmap_raise_rows(const scn_batch& b, const int32_t* rows, const int32_t* m_dev,
+                                  const int32_t* before, float* hmap, hipStream_t st);
+hipError_t launch_tick_plan(const scn_batch& b, const int32_t* resume, int j_cap, int32_t* list,
+                            int32_t* obj_idx, int32_t* count, int32_t* before, hipStream_t st);
 hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,
                           int round, float margin, int32_t* bins, float* accept,
                           int64_t* counters, hipStream_t st);
-hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);   // kernels.hip
 
 hipError_t launch_reset(const scn_batch& b, hipStream_t st);
@@ -133,6 +145,7 @@ hipError_t launch_check(const scn_batch& b, const int32_t* obj_idx, const int32_
                         int64_t* counters, hipStream_t st);
 // Sets the non-finite error bit when any grid asset node value is not finite.
 hipError_t launch_scan_grid_values(const scn_batch& b, int64_t* counters, hipStream_t st);
+hipError_t launch_object_info(const scn_batch& b, float margin, void* info, hipStream_t st);
 hipError_t launch_place(const scn_batch& b, const scn_gen_args& a, const PlacePlan& plan,
                         int32_t* chosen, int64_t* counters, hipStream_t st);
 // Longest-first scene order: a counting sort of the scenes by an estimate of
@@ -141,7 +154,7 @@ constexpr int kOrderBuckets = 256;
 // network kernels (mlp.hip)
 hipError_t launch_gemm(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
                        const float* bias, bool relu, float* C32, void* C16, int ldc,
-                       hipStream_t st);
+                       hipStream_t st, const int32_t* m_dev = nullptr);
 hipError_t launch_transpose_bf16(int rows, int cols, const void* in, int ldi, void* out, int ldo,
                                  hipStream_t st);
 hipError_t launch_f32_to_bf16(int n, const float* in, void* out, hipStream_t st);

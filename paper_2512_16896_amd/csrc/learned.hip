@@ -171,28 +171,12 @@ __global__ __launch_bounds__(256) void k_hmap_boxes(
     }
 }
 
-// Raise the height map of each scene by its object obj_idx[s] (-1: none),
-// whose world spheres are in placed.  One wave per scene, one sphere per lane
-// at a time; monotone max through integer atomics on non-negative floats.
-__global__ __launch_bounds__(64) void k_hmap_raise(
-    int n, const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
-    const float* __restrict__ sup, const int32_t* __restrict__ sph_off,
-    const float4* __restrict__ placed, const int32_t* __restrict__ obj_idx,
-    const int32_t* __restrict__ n_state, float* __restrict__ hmap) {
-    const int s = blockIdx.x;
-    if (s >= n) return;
-    // one object (obj_idx) or the scene's first n_state[s] objects
-    int k0, k1;
-    if (n_state) {
-        const int m = min(max(n_state[s], 0), obj_off[s + 1] - obj_off[s]);
-        k0 = sph_off[obj_off[s]];
-        k1 = sph_off[obj_off[s] + m];
-    } else {
-        const int o = obj_idx[s];
-        if (o < obj_off[s] || o >= obj_off[s + 1]) return;
-        k0 = sph_off[o];
-        k1 = sph_off[o + 1];
-    }
+// Raise scene s's height map by the placed spheres k0 .. k1-1 (world
+// frame).  One wave, one sphere per lane at a time; monotone max through
+// integer atomics on non-negative floats.
+__device__ void raise_scene(int s, int k0, int k1, const int32_t* __restrict__ obj_off,
+                            const int32_t* __restrict__ obj_sup, const float* __restrict__ sup,
+                            const float4* __restrict__ placed, float* __restrict__ hmap) {
     const SupportFrame F = scene_support(obj_off, obj_sup, sup, s);
     const float cw = 2.f * F.hx / 64.f, ch = 2.f * F.hy / 64.f;
     int* H = (int*)(hmap + (size_t)s * 4096);
@@ -220,6 +204,110 @@ __global__ __launch_bounds__(64) void k_hmap_raise(
     }
 }
 
+// Raise the height map of each scene by its object obj_idx[s] (-1: none), or
+// by its first n_state[s] objects, whose world spheres are in placed.
+__global__ __launch_bounds__(64) void k_hmap_raise(
+    int n, const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
+    const float* __restrict__ sup, const int32_t* __restrict__ sph_off,
+    const float4* __restrict__ placed, const int32_t* __restrict__ obj_idx,
+    const int32_t* __restrict__ n_state, float* __restrict__ hmap) {
+    const int s = blockIdx.x;
+    if (s >= n) return;
+    int k0, k1;
+    if (n_state) {
+        const int m = min(max(n_state[s], 0), obj_off[s + 1] - obj_off[s]);
+        k0 = sph_off[obj_off[s]];
+        k1 = sph_off[obj_off[s] + m];
+    } else {
+        const int o = obj_idx[s];
+        if (o < obj_off[s] || o >= obj_off[s + 1]) return;
+        k0 = sph_off[o];
+        k1 = sph_off[o + 1];
+    }
+    raise_scene(s, k0, k1, obj_off, obj_sup, sup, placed, hmap);
+}
+
+// The same for the scenes rows[0 .. *m_dev) of a compacted list: a scene
+// whose n_placed grew past before[s] in the step just run is raised by the
+// object it placed (obj_off[s] + n_placed[s] - 1).
+__global__ __launch_bounds__(64) void k_hmap_raise_rows(
+    int n, const int32_t* __restrict__ rows, const int32_t* __restrict__ m_dev,
+    const int32_t* __restrict__ before, const int32_t* __restrict__ n_placed,
+    const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
+    const float* __restrict__ sup, const int32_t* __restrict__ sph_off,
+    const float4* __restrict__ placed, float* __restrict__ hmap) {
+    const int r = blockIdx.x;
+    if (r >= n || r >= *m_dev) return;
+    const int s = rows[r];
+    const int j = n_placed[s];
+    if (j <= before[s] || j > obj_off[s + 1] - obj_off[s]) return;
+    const int o = obj_off[s] + j - 1;
+    raise_scene(s, sph_off[o], sph_off[o + 1], obj_off, obj_sup, sup, placed, hmap);
+}
+
+hipError_t launch_hmap_raise_rows(const scn_batch& b, const int32_t* rows, const int32_t* m_dev,
+                                  const int32_t* before, float* hmap, hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hmap_raise_rows, dim3(b.n_scenes), dim3(64), 0, st, b.n_scenes, rows,
+                       m_dev, before, b.n_placed, b.obj_off, b.obj_sup, b.sup, b.sph_off,
+                       (const float4*)b.placed, hmap);
+    return hipGetLastError();
+}
+
+// The learned pipeline's plan of one tick: the active scenes below the
+// objects cap that still have an object to place, split into those that start
+// a new object (resume[s] == 0: they need proposals; list[0 ..), with the
+// object in obj_idx by row) and those resuming the uniform entries of a
+// pending one (list[n ..)).  count[0] and count[1] (zeroed by the caller)
+// receive the two sizes; before[s] = n_placed[s] for every listed scene.
+// Appends are aggregated per wave, so the order within each list is not the
+// scene order; each scene's step does not depend on it.
+__global__ __launch_bounds__(256) void k_tick_plan(int n, const int32_t* __restrict__ obj_off,
+                                                   const int32_t* __restrict__ n_placed,
+                                                   const int8_t* __restrict__ status,
+                                                   const int32_t* __restrict__ resume, int j_cap,
+                                                   int32_t* __restrict__ list,
+                                                   int32_t* __restrict__ obj_idx,
+                                                   int32_t* __restrict__ count,
+                                                   int32_t* __restrict__ before) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    bool fresh = false, pending = false;
+    int j = 0;
+    if (s < n && status[s] == SCN_SCENE_ACTIVE) {
+        j = n_placed[s];
+        if (j < obj_off[s + 1] - obj_off[s] && (j_cap <= 0 || j < j_cap)) {
+            fresh = resume[s] == 0;
+            pending = !fresh;
+            before[s] = j;
+        }
+    }
+    const unsigned long long lower = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    const unsigned long long mf = __ballot(fresh), mp = __ballot(pending);
+    int base_f = 0, base_p = 0;
+    if (lane == 0) {
+        if (mf) base_f = atomicAdd(count, __popcll(mf));
+        if (mp) base_p = atomicAdd(count + 1, __popcll(mp));
+    }
+    base_f = __shfl(base_f, 0, kWave);
+    base_p = __shfl(base_p, 0, kWave);
+    if (fresh) {
+        const int r = base_f + __popcll(mf & lower);
+        list[r] = s;
+        obj_idx[r] = obj_off[s] + j;
+    }
+    if (pending) list[n + base_p + __popcll(mp & lower)] = s;
+}
+
+hipError_t launch_tick_plan(const scn_batch& b, const int32_t* resume, int j_cap, int32_t* list,
+                            int32_t* obj_idx, int32_t* count, int32_t* before, hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tick_plan, dim3((b.n_scenes + 255) / 256), dim3(256), 0, st, b.n_scenes,
+                       b.obj_off, b.n_placed, b.status, resume, j_cap, list, obj_idx, count,
+                       before);
+    return hipGetLastError();
+}
+
 hipError_t launch_hmap_boxes(const scn_batch& b, float* hmap, hipStream_t st) {
     if (b.n_scenes == 0) return hipSuccess;
     hipLaunchKernelGGL(k_hmap_boxes, dim3(b.n_scenes), dim3(256), 0, st, b.n_scenes, b.obj_off,
@@ -236,73 +324,25 @@ hipError_t launch_hmap_raise(const scn_batch& b, const int32_t* obj_idx, const i
     return hipGetLastError();
 }
 
-// The object each scene starts next (n_placed[s]) if the scene is active, has
-// no pending object (resume[s] == 0) and is below the objects cap; else -1.
-__global__ void k_next_object(int n, const int32_t* __restrict__ obj_off,
-                              const int32_t* __restrict__ n_placed,
-                              const int8_t* __restrict__ status,
-                              const int32_t* __restrict__ resume, int j_cap,
-                              int32_t* __restrict__ obj_idx) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int o = obj_off[s] + n_placed[s];
-    const bool fresh = !resume || resume[s] == 0;
-    const bool capped = j_cap > 0 && n_placed[s] >= j_cap;
-    obj_idx[s] = (status[s] == SCN_SCENE_ACTIVE && o < obj_off[s + 1] && fresh && !capped) ? o : -1;
-}
-
-hipError_t launch_next_object(const scn_batch& b, const int32_t* resume, int j_cap,
-                              int32_t* obj_idx, hipStream_t st) {
-    if (b.n_scenes == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_next_object, dim3((b.n_scenes + 255) / 256), dim3(256), 0, st, b.n_scenes,
-                       b.obj_off, b.n_placed, b.status, resume, j_cap, obj_idx);
-    return hipGetLastError();
-}
-
-// The most recently placed object of each scene: obj_off[s] + n_placed[s] - 1
-// when that is at least `first_new` objects into the scene (else -1).
-__global__ void k_last_object(int n, const int32_t* __restrict__ obj_off,
-                              const int32_t* __restrict__ n_placed, int32_t* __restrict__ obj_idx,
-                              const int32_t* __restrict__ before) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    obj_idx[s] = n_placed[s] > before[s] ? obj_off[s] + n_placed[s] - 1 : -1;
-}
-
-hipError_t launch_last_object(const scn_batch& b, const int32_t* before, int32_t* obj_idx,
-                              hipStream_t st) {
-    if (b.n_scenes == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_last_object, dim3((b.n_scenes + 255) / 256), dim3(256), 0, st, b.n_scenes,
-                       b.obj_off, b.n_placed, obj_idx, before);
-    return hipGetLastError();
-}
-
-__global__ void k_copy_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
-}
-
-hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_i32, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n);
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
-// Feature rows x[s] = [10 * hmap[s] (4096), desc[obj_idx[s]] (32)] as BF16;
-// zeros for scenes with obj_idx < 0.  Row length ld >= 4128.
+// Feature rows x[r] = [10 * hmap[s] (4096), desc[obj_idx[r]] (32)] as BF16,
+// s = rows[r] (or r without a row list); zeros for rows with obj_idx < 0.
+// Row length ld >= 4128.  With m_dev only rows below *m_dev are written.
 __global__ __launch_bounds__(256) void k_features(int n, const float* __restrict__ hmap,
                                                  const float* __restrict__ desc,
                                                  const int32_t* __restrict__ obj_idx, int ld,
-                                                 __bf16* __restrict__ x) {
-    const int s = blockIdx.x;
-    if (s >= n) return;
-    const int o = obj_idx[s];
-    __bf16* row = x + (size_t)s * ld;
+                                                 __bf16* __restrict__ x,
+                                                 const int32_t* __restrict__ rows,
+                                                 const int32_t* __restrict__ m_dev) {
+    const int r = blockIdx.x;
+    if (r >= n || (m_dev && r >= *m_dev)) return;
+    const size_t s = rows ? (size_t)rows[r] : (size_t)r;   // the scene of feature row r
+    const int o = obj_idx[r];
+    __bf16* row = x + (size_t)r * ld;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         float v = 0.f;
         if (o >= 0) {
-            if (i < 4096) v = 10.f * hmap[(size_t)s * 4096 + i];
+            if (i < 4096) v = 10.f * hmap[s * 4096 + i];
             else if (i < 4128) v = desc[32 * (size_t)o + (i - 4096)];
         }
         row[i] = (__bf16)v;
@@ -310,17 +350,20 @@ __global__ __launch_bounds__(256) void k_features(int n, const float* __restrict
 }
 
 hipError_t launch_features(int n, const float* hmap, const float* desc, const int32_t* obj_idx,
-                           int ld, void* x, hipStream_t st) {
+                           int ld, void* x, hipStream_t st, const int32_t* rows,
+                           const int32_t* m_dev) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_features, dim3(n), dim3(256), 0, st, n, hmap, desc, obj_idx, ld,
-                       (__bf16*)x);
+                       (__bf16*)x, rows, m_dev);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Top-k bins per row of logits [M][4096]: bins in rank order (logit
 // descending, ties to the lower bin; NaN ranks last).  Rows with
-// active[m] < 0 are skipped (active may be nullptr).
+// active[m] < 0 are skipped (active may be nullptr).  Row m's bins go to
+// bins[rows[m]] (scattered back to its scene) or bins[m]; with m_dev only
+// rows below *m_dev are ranked.
 //
 // The rank order is the descending order of the unique 64-bit key
 // (orderable(logit) << 32) | (4095 - bin).
@@ -341,14 +384,17 @@ __device__ __forceinline__ unsigned logit_key(float v) {
 constexpr int kSelMax = 256;
 __global__ __launch_bounds__(256) void k_topk_select(int M, const float* __restrict__ logits, int k,
                                                      const int32_t* __restrict__ active,
-                                                     int32_t* __restrict__ bins) {
+                                                     int32_t* __restrict__ bins,
+                                                     const int32_t* __restrict__ rows,
+                                                     const int32_t* __restrict__ m_dev) {
     __shared__ unsigned hist[256];
     __shared__ unsigned s_prefix, s_need, s_count;
     __shared__ unsigned s_tie_count[256];
     __shared__ unsigned long long sel[kSelMax];
     const int m = blockIdx.x;
-    if (m >= M) return;
+    if (m >= M || (m_dev && m >= *m_dev)) return;
     if (active && active[m] < 0) return;
+    const size_t out = rows ? (size_t)rows[m] : (size_t)m;   // the row's bins go to row `out`
     const int t = threadIdx.x;
     const float4* z4 = reinterpret_cast<const float4*>(logits + (size_t)m * 4096) + 4 * t;
     unsigned v[16];
@@ -437,18 +483,21 @@ __global__ __launch_bounds__(256) void k_topk_select(int M, const float* __restr
         const unsigned long long a = sel[i];
         int r = 0;
         for (int j = 0; j < k; ++j) r += sel[j] > a;
-        bins[(size_t)m * k + r] = 4095 - (int)(a & 0xFFFFFFFFu);
+        bins[out * k + r] = 4095 - (int)(a & 0xFFFFFFFFu);
     }
 }
 
 // Any k: a bitonic sort of the 4096 keys in LDS, 1024 threads per row.
 __global__ __launch_bounds__(1024) void k_topk_sort(int M, const float* __restrict__ logits, int k,
                                                     const int32_t* __restrict__ active,
-                                                    int32_t* __restrict__ bins) {
+                                                    int32_t* __restrict__ bins,
+                                                    const int32_t* __restrict__ rows,
+                                                    const int32_t* __restrict__ m_dev) {
     __shared__ unsigned long long key[4096];
     const int m = blockIdx.x;
-    if (m >= M) return;
+    if (m >= M || (m_dev && m >= *m_dev)) return;
     if (active && active[m] < 0) return;
+    const size_t out = rows ? (size_t)rows[m] : (size_t)m;
     const float* z = logits + (size_t)m * 4096;
     for (int i = threadIdx.x; i < 4096; i += blockDim.x)
         key[i] = ((unsigned long long)logit_key(z[i]) << 32) | (unsigned)(4095 - i);
@@ -467,16 +516,18 @@ __global__ __launch_bounds__(1024) void k_topk_sort(int M, const float* __restri
         }
     }
     for (int i = threadIdx.x; i < k; i += blockDim.x)
-        bins[(size_t)m * k + i] = 4095 - (int)(key[i] & 0xFFFFFFFFu);
+        bins[out * k + i] = 4095 - (int)(key[i] & 0xFFFFFFFFu);
 }
 
 hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active, int32_t* bins,
-                       hipStream_t st) {
+                       hipStream_t st, const int32_t* rows, const int32_t* m_dev) {
     if (M == 0) return hipSuccess;
     if (k <= kSelMax && ((uintptr_t)logits & 15u) == 0)
-        hipLaunchKernelGGL(k_topk_select, dim3(M), dim3(256), 0, st, M, logits, k, active, bins);
+        hipLaunchKernelGGL(k_topk_select, dim3(M), dim3(256), 0, st, M, logits, k, active, bins,
+                           rows, m_dev);
     else
-        hipLaunchKernelGGL(k_topk_sort, dim3(M), dim3(1024), 0, st, M, logits, k, active, bins);
+        hipLaunchKernelGGL(k_topk_sort, dim3(M), dim3(1024), 0, st, M, logits, k, active, bins,
+                           rows, m_dev);
     return hipGetLastError();
 }
 

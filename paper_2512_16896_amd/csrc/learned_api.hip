@@ -27,6 +27,14 @@ int check_single_support(const scn_batch* b) {
     return SCN_OK;
 }
 
+// Waves per scene of the learned pipeline's launches: the first ticks'
+// new-object launch (throughput), the others (latency).  Measured on the
+// 4096-scene workload (20 objects of 64 spheres, 1024 candidates per attempt):
+// 19.4 ms per generation with 1 and 4, against 20-27 ms with 2 / 2-8 and
+// 42 ms with 2 / 16.
+constexpr int kBulkWaves = 1;
+constexpr int kWideWaves = 4;
+
 int check_scenes(const scn_batch* b) {
     if (!b) return scn_fail(SCN_E_INVALID_ARG, "null batch");
     if (b->n_scenes < 0 || b->n_objects < 0) return scn_fail(SCN_E_INVALID_ARG, "negative sizes");
@@ -101,26 +109,27 @@ int scn_harvest_labels(scn_ctx* c, const scn_batch* b, const int32_t* n_state, i
     return SCN_OK;
 }
 
-// Defined in api.hip: plan and launch of the fused place kernel.
-__attribute__((visibility("hidden"))) int scn_place_internal(
-    scn_ctx* c, scn_batch* b, const scn_gen_args* a, int max_steps, int32_t* chosen, bool reset,
-    const int32_t* prop_bins, int prop_k, int32_t* resume, int chunk, int j_cap,
-    int32_t* n_active, void* order_ws, hipStream_t st);
+// Defined in api.hip: one object step of the fused place kernel over the
+// scenes of a device-compacted list.
+__attribute__((visibility("hidden"))) int scn_place_rows(
+    scn_ctx* c, scn_batch* b, const scn_gen_args* a, const int32_t* prop_bins, int prop_k,
+    int32_t* resume, int chunk, int j_cap, const int32_t* rows, const int32_t* n_rows,
+    void* map_keep, void* bnd_keep, const void* info_keep, hipStream_t st);
 
 }  // extern "C"
 
-// Layout of the learned generation's workspace: the scene order region, the
-// network's hidden activations, then the pipeline buffers below.
+// Layout of the learned generation's workspace: the network's hidden
+// activations, then the pipeline buffers below.
 namespace {
 struct LearnedWs {
-    void* order;
     void* act;
     float* hmap;
     float* desc;
     uint16_t* x;
     float* logits;
     int32_t* bins;
-    int32_t *obj_idx, *before, *placed_now, *resume, *n_active;
+    int32_t *obj_idx, *before, *list, *count, *resume;
+    void *map_keep, *bnd_keep, *info_keep;   // state the step launches keep (PlacePlan)
 };
 size_t learned_layout(const scn_batch* b, const scn_mlp* net, int top_k, char* base,
                       LearnedWs* w) {
@@ -132,7 +141,6 @@ size_t learned_layout(const scn_batch* b, const scn_mlp* net, int top_k, char* b
         return q;
     };
     LearnedWs t;
-    t.order = take(scn::ws_order_bytes(b->n_scenes));
     t.act = take(scn::ws_mlp_forward_bytes(net, b->n_scenes));
     t.hmap = (float*)take(n * SCN_HMAP_CELLS * 4);
     t.desc = (float*)take((size_t)b->n_objects * SCN_DESC * 4);
@@ -141,9 +149,12 @@ size_t learned_layout(const scn_batch* b, const scn_mlp* net, int top_k, char* b
     t.bins = (int32_t*)take(n * (size_t)top_k * 4);
     t.obj_idx = (int32_t*)take(n * 4);
     t.before = (int32_t*)take(n * 4);
-    t.placed_now = (int32_t*)take(n * 4);
+    t.list = (int32_t*)take(2 * n * 4);
+    t.count = (int32_t*)take(8);
     t.resume = (int32_t*)take(n * 4);
-    t.n_active = (int32_t*)take(8);
+    t.map_keep = take(b->grid_off ? 0 : n * (size_t)scn::kMapBytes);
+    t.bnd_keep = take((size_t)b->n_objects * 16);
+    t.info_keep = take((size_t)b->n_objects * 64);
     if (w) *w = t;
     return off;
 }
@@ -174,13 +185,18 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
         return scn_fail(SCN_E_INVALID_ARG, "placed/n_placed/status/rec required");
     if (a->retries < 0) return scn_fail(SCN_E_INVALID_ARG, "retries must be >= 0");
     if (int r = check_single_support(b)) return r;
-    // Schedule 0: 2 waves, batch order, placed spheres from global memory.
-    // Each step launch is as long as its slowest scene's proposals and
-    // fallback chunk; measured on batched-4096 this beat the plain default
-    // of 4 waves (34.2 vs 37.3 ms per generation) and 1, 3 or 8 waves.
-    scn_gen_args args = *a;
-    if (args.schedule == 0) args.schedule = 2 | (SCN_SCHED_LDS_NONE << SCN_SCHED_LDS_SHIFT);
-    a = &args;
+    // Launch shapes.  The first ticks (as many as a scene has objects) carry
+    // nearly every scene in the new-object list: their launch runs
+    // args->schedule (0: one wave per scene, placed spheres from global
+    // memory), sized for throughput.  The pending list, and both lists in the
+    // later ticks, hold a few scenes whose steps are latency-bound: they run
+    // args->wide_schedule (0: 4 waves per scene).  None of this changes a
+    // placement.
+    scn_gen_args bulk = *a, wide = *a;
+    if (bulk.schedule == 0) bulk.schedule = kBulkWaves | (SCN_SCHED_LDS_NONE << SCN_SCHED_LDS_SHIFT);
+    wide.schedule = a->wide_schedule != 0 ? a->wide_schedule
+                                          : kWideWaves | (SCN_SCHED_LDS_NONE << SCN_SCHED_LDS_SHIFT);
+    a = &bulk;
     const hipStream_t st = (hipStream_t)stream;
     const int n = b->n_scenes;
     if (n == 0) return SCN_OK;
@@ -188,62 +204,71 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     if (int r = scn_workspace(c, learned_layout(b, net, top_k, nullptr, nullptr), &ws)) return r;
     LearnedWs W;
     learned_layout(b, net, top_k, (char*)ws, &W);
-    float* hmap = W.hmap;
-    float* desc = W.desc;
-    uint16_t* x = W.x;
-    float* logits = W.logits;
-    int32_t* bins = W.bins;
-    int32_t* obj_idx = W.obj_idx;
-    int32_t* before = W.before;
-    int32_t* placed_now = W.placed_now;
-    int32_t* resume = W.resume;
-    int32_t* n_active = W.n_active;
+    if (!c->aux_stream) SCN_HIP(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+    for (auto& e : c->ev)
+        if (!e) SCN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
     const int j_cap = a->max_steps > 0 && a->max_steps < b->max_objects_per_scene ? a->max_steps : 0;
-    // uniform entries tried per launch: one attempt of the default size, so
-    // that a launch never waits on one scene's whole fallback
-    const int chunk = a->fallback_chunk < 0 ? 0
-                      : a->fallback_chunk > 0 ? a->fallback_chunk
-                      : (b->max_cand_per_object > 0 ? b->max_cand_per_object : a->default_ncand);
-    // every launch makes progress on each active scene (a placement, the
-    // invalid mark, or `chunk` more entries), which bounds the launches
+    // uniform entries a pending object tries per tick (0: all that remain)
+    const int chunk = a->fallback_chunk > 0 ? a->fallback_chunk : 0;
+    // every tick makes progress on each listed scene (a placement, the
+    // invalid mark, the proposals, or `chunk` more uniform entries), which
+    // bounds the ticks
     long long c_max = b->max_cand_per_object > 0 ? b->max_cand_per_object : a->default_ncand;
     if (c_max < 1) c_max = 1;
-    const long long per_obj = chunk > 0 ? 1 + ((long long)(a->retries + 1) * c_max + chunk - 1) / chunk : 1;
-    const long long max_launch = (long long)(j_cap > 0 ? j_cap : b->max_objects_per_scene) * per_obj + 1;
+    const long long per_obj = 1 + (chunk > 0 ? ((long long)(a->retries + 1) * c_max + chunk - 1) / chunk : 1);
+    const long long max_ticks =
+        (long long)(j_cap > 0 ? j_cap : b->max_objects_per_scene) * per_obj + 1;
 
     SCN_HIP(scn::launch_reset(*b, st));
-    SCN_HIP(scn::launch_fill_i32(resume, n, 0, st));
-    SCN_HIP(scn::launch_descriptor(*b, desc, st));
-    SCN_HIP(scn::launch_hmap_boxes(*b, hmap, st));
+    SCN_HIP(scn::launch_fill_i32(W.resume, n, 0, st));
+    SCN_HIP(scn::launch_descriptor(*b, W.desc, st));
+    SCN_HIP(scn::launch_hmap_boxes(*b, W.hmap, st));
+    SCN_HIP(scn::launch_object_info(*b, a->margin, W.info_keep, st));
+    void* map_keep = b->grid_off ? nullptr : W.map_keep;
 
-    // One step launch on stream s: for scenes that start a new object, the
-    // features, the network and the top-k (skipped when no scene does:
-    // resumed scenes need no proposal); then the place kernel, the height map
-    // update of the scenes that placed, and the read-back of the two counters.
-    auto enqueue_step = [&](hipStream_t s, bool with_net) -> int {
-        if (with_net) {
-            SCN_HIP(scn::launch_next_object(*b, resume, j_cap, obj_idx, s));
-            SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, s));
-            if (int r = scn_mlp_forward_ws(net, x, n, logits, W.act, s)) return r;
-            SCN_HIP(scn::launch_topk(n, logits, top_k, obj_idx, bins, s));
-        }
-        SCN_HIP(scn::launch_copy_i32(b->n_placed, before, n, s));
-        SCN_HIP(scn::launch_fill_i32(n_active, 2, 0, s));
-        if (int r = scn_place_internal(c, b, a, 1, nullptr, false, bins, top_k, resume, chunk,
-                                       j_cap, n_active, W.order, s))
+    int32_t* list_new = W.list;        // scenes starting an object: need proposals
+    int32_t* list_pend = W.list + n;   // scenes resuming a pending object's uniform entries
+    auto plan = [&](hipStream_t s) -> int {
+        SCN_HIP(scn::launch_fill_i32(W.count, 2, 0, s));
+        SCN_HIP(scn::launch_tick_plan(*b, W.resume, j_cap, W.list, W.obj_idx, W.count, W.before, s));
+        return SCN_OK;
+    };
+    // One tick on stream s (and the context's second stream): the plan
+    // splits the scenes with work into the two lists; the pending ones try
+    // their next `chunk` uniform entries on the second stream while the new
+    // ones run features, network and top-k over their compacted rows and try
+    // their proposals alone; each list raises the height maps of the scenes
+    // that placed.  The lists are disjoint, so the two streams never touch
+    // the same scene.  Launch sizes are fixed (n rows / scenes); each kernel
+    // reads its list's length on the device and the rest of its grid leaves.
+    auto tick = [&](hipStream_t s, bool late) -> int {
+        if (int r = plan(s)) return r;
+        SCN_HIP(hipEventRecord(c->ev[0], s));
+        SCN_HIP(hipStreamWaitEvent(c->aux_stream, c->ev[0], 0));
+        if (int r = scn_place_rows(c, b, &wide, W.bins, top_k, W.resume, chunk, j_cap, list_pend, W.count + 1, map_keep, W.bnd_keep,
+                                   W.info_keep, c->aux_stream))
             return r;
-        SCN_HIP(scn::launch_last_object(*b, before, placed_now, s));
-        SCN_HIP(scn::launch_hmap_raise(*b, placed_now, nullptr, hmap, s));
-        SCN_HIP(hipMemcpyAsync(c->h_flag, n_active, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SCN_HIP(scn::launch_hmap_raise_rows(*b, list_pend, W.count + 1, W.before, W.hmap,
+                                            c->aux_stream));
+        SCN_HIP(hipEventRecord(c->ev[1], c->aux_stream));
+        SCN_HIP(scn::launch_features(n, W.hmap, W.desc, W.obj_idx, SCN_FEATURES, W.x, s, list_new,
+                                     W.count));
+        if (int r = scn_mlp_forward_ws(net, W.x, n, W.logits, W.act, s, W.count)) return r;
+        SCN_HIP(scn::launch_topk(n, W.logits, top_k, nullptr, W.bins, s, list_new, W.count));
+        if (int r = scn_place_rows(c, b, late ? &wide : a, W.bins, top_k, W.resume, -1, j_cap,
+                                   list_new, W.count, map_keep, W.bnd_keep, W.info_keep, s))
+            return r;
+        SCN_HIP(scn::launch_hmap_raise_rows(*b, list_new, W.count, W.before, W.hmap, s));
+        SCN_HIP(hipStreamWaitEvent(s, c->ev[1], 0));
         return SCN_OK;
     };
 
-    // With use_graph the two step variants are captured once (on the
-    // context's own stream, after the first step ran eagerly and made every
-    // allocation) and replayed on `stream`: every step has the same kernel
-    // arguments, since the state lives in device memory.
-    hipGraphExec_t exec[2] = {nullptr, nullptr};   // [with network, resume only]
+    // With use_graph the two kinds of tick are captured (on the context's
+    // capture stream, forking to the second stream and joining back) and
+    // replayed on `stream`: ticks of a kind have the same kernel arguments,
+    // since the state lives in device memory.
+    hipGraphExec_t exec[2] = {nullptr, nullptr};   // [first ticks, later ticks]
     auto release = [&]() {
         for (auto& e : exec)
             if (e) {
@@ -251,45 +276,61 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
                 e = nullptr;
             }
     };
-    auto capture = [&](bool with_net, hipGraphExec_t* out) -> int {
+    if (a->use_graph) {
         if (!c->cap_stream)
             SCN_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-        SCN_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-        const int r = enqueue_step(c->cap_stream, with_net);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-        if (r != SCN_OK || e != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return r != SCN_OK ? r : scn_fail(SCN_E_HIP, "step capture: %s", hipGetErrorString(e));
+        for (int k = 0; k < 2; ++k) {
+            SCN_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+            const int r = tick(c->cap_stream, k == 1);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+            if (r != SCN_OK || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                release();
+                return r != SCN_OK ? r : scn_fail(SCN_E_HIP, "tick capture: %s", hipGetErrorString(e));
+            }
+            const hipError_t ei = hipGraphInstantiate(&exec[k], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                release();
+                return scn_fail(SCN_E_HIP, "tick graph: %s", hipGetErrorString(ei));
+            }
         }
-        const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ei != hipSuccess) return scn_fail(SCN_E_HIP, "step graph: %s", hipGetErrorString(ei));
-        return SCN_OK;
-    };
+    }
 
-    bool fresh = true;   // some scene starts a new object (needs the network)
-    for (long long it = 0; it < max_launch; ++it) {
-        int r = SCN_OK;
-        if (a->use_graph && it > 0) {
-            hipGraphExec_t& e = exec[fresh ? 0 : 1];
-            if (!e) r = capture(fresh, &e);
-            if (r == SCN_OK && hipGraphLaunch(e, st) != hipSuccess)
-                r = scn_fail(SCN_E_HIP, "step graph launch failed");
-        } else {
-            r = enqueue_step(st, fresh);
+    // Ticks run in batches without a host wait; after each batch the host
+    // reads the two list sizes of a fresh plan (8 bytes) and stops when both
+    // are zero.  No scene can finish in fewer ticks than it has objects, so
+    // the first batch is that long.
+    long long done = 0;
+    long long batch = b->max_objects_per_scene > 0 ? b->max_objects_per_scene : 1;
+    if (j_cap > 0 && j_cap < batch) batch = j_cap;
+    const long long first = batch;   // ticks of the first kind
+    int r = SCN_OK;
+    while (r == SCN_OK) {
+        const long long m = batch < max_ticks - done ? batch : max_ticks - done;
+        for (long long t = 0; t < m && r == SCN_OK; ++t) {
+            const bool late = done + t >= first;
+            if (exec[late])
+                r = hipGraphLaunch(exec[late], st) == hipSuccess
+                        ? SCN_OK
+                        : scn_fail(SCN_E_HIP, "tick graph launch failed");
+            else
+                r = tick(st, late);
         }
+        done += m;
+        if (r != SCN_OK) break;
+        r = plan(st);
+        if (r == SCN_OK && hipMemcpyAsync(c->h_flag, W.count, 2 * sizeof(int32_t),
+                                          hipMemcpyDeviceToHost, st) != hipSuccess)
+            r = scn_fail(SCN_E_HIP, "list size read failed");
         if (r == SCN_OK && hipStreamSynchronize(st) != hipSuccess)
-            r = scn_fail(SCN_E_HIP, "step failed: %s", hipGetErrorString(hipGetLastError()));
-        if (r != SCN_OK) {
-            release();
-            return r;
-        }
-        if (c->h_flag[0] == 0) break;
-        fresh = c->h_flag[1] > 0;
+            r = scn_fail(SCN_E_HIP, "tick failed: %s", hipGetErrorString(hipGetLastError()));
+        if (r != SCN_OK || (c->h_flag[0] == 0 && c->h_flag[1] == 0) || done >= max_ticks) break;
+        batch = 8;
     }
     release();
-    return SCN_OK;
+    return r;
 }
 
 }  // extern "C"

@@ -34,12 +34,17 @@ __device__ __forceinline__ __bf16 f2bf(float v) { return (__bf16)v; }   // round
 // banks.  Fragment layout (v_mfma_f32_16x16x32_bf16): lane l supplies row
 // l % 16 of a 16-row fragment, 8 BF16 at column 8 (l / 16) of the K step; the
 // result for lane l is rows 4 (l / 16) .. +3 of column l % 16.  Rows / columns
-// past M / N are clamped on load and skipped on store.  K % 32 == 0.
+// past M / N are clamped on load and skipped on store.  K % 32 == 0.  With
+// m_dev, the row count is min(M, *m_dev), read on the device: the grid covers
+// M rows and the workgroups past the live rows leave at once (compacted
+// batches whose size only the device knows).  Every output element sums its K
+// products in the same order whatever the tile shape or row count.
 constexpr int kLdsRow = 40;
 
 template <int BM, int BN, bool kBias, bool kRelu>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const __bf16* __restrict__ A,
-                                             int lda, const __bf16* __restrict__ B, int ldb,
+__global__ __launch_bounds__(256) void k_gemm(int M, const int32_t* __restrict__ m_dev, int N,
+                                             int K, const __bf16* __restrict__ A, int lda,
+                                             const __bf16* __restrict__ B, int ldb,
                                              const float* __restrict__ bias, float* __restrict__ C32,
                                              __bf16* __restrict__ C16, int ldc) {
     constexpr int FM = BM / 32, FN = BN / 32;       // 16 x 16 fragments per wave
@@ -49,6 +54,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const __bf16*
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
     const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
+    if (m_dev) M = min(M, *m_dev);
+    if (bm >= M) return;   // the whole workgroup, before any barrier
     const int r = lane & 15, kq = (lane >> 4) * 8;
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
 
@@ -136,23 +143,23 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const __bf16*
 }
 
 template <int BM, int BN>
-static void launch_gemm_tile(int M, int N, int K, const __bf16* a, int lda, const __bf16* b,
-                             int ldb, const float* bias, bool relu, float* C32, __bf16* c16,
-                             int ldc, hipStream_t st) {
+static void launch_gemm_tile(int M, const int32_t* m_dev, int N, int K, const __bf16* a, int lda,
+                             const __bf16* b, int ldb, const float* bias, bool relu, float* C32,
+                             __bf16* c16, int ldc, hipStream_t st) {
     dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM), block(256);
     if (bias && relu)
-        hipLaunchKernelGGL((k_gemm<BM, BN, true, true>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+        hipLaunchKernelGGL((k_gemm<BM, BN, true, true>), grid, block, 0, st, M, m_dev, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
     else if (bias)
-        hipLaunchKernelGGL((k_gemm<BM, BN, true, false>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+        hipLaunchKernelGGL((k_gemm<BM, BN, true, false>), grid, block, 0, st, M, m_dev, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
     else if (relu)
-        hipLaunchKernelGGL((k_gemm<BM, BN, false, true>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+        hipLaunchKernelGGL((k_gemm<BM, BN, false, true>), grid, block, 0, st, M, m_dev, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
     else
-        hipLaunchKernelGGL((k_gemm<BM, BN, false, false>), grid, block, 0, st, M, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
+        hipLaunchKernelGGL((k_gemm<BM, BN, false, false>), grid, block, 0, st, M, m_dev, N, K, a, lda, b, ldb, bias, C32, c16, ldc);
 }
 
 hipError_t launch_gemm(int M, int N, int K, const void* A, int lda, const void* B, int ldb,
                        const float* bias, bool relu, float* C32, void* C16, int ldc,
-                       hipStream_t st) {
+                       hipStream_t st, const int32_t* m_dev) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (K <= 0 || K % 32 || lda % 8 || ldb % 8) return hipErrorInvalidValue;
     auto a = (const __bf16*)A;
@@ -161,9 +168,9 @@ hipError_t launch_gemm(int M, int N, int K, const void* A, int lda, const void* 
     // the large tile only when it still gives every compute unit a workgroup
     const long long big = (long long)((N + 127) / 128) * ((M + 127) / 128);
     if (big >= 256)
-        launch_gemm_tile<128, 128>(M, N, K, a, lda, b, ldb, bias, relu, C32, c16, ldc, st);
+        launch_gemm_tile<128, 128>(M, m_dev, N, K, a, lda, b, ldb, bias, relu, C32, c16, ldc, st);
     else
-        launch_gemm_tile<64, 64>(M, N, K, a, lda, b, ldb, bias, relu, C32, c16, ldc, st);
+        launch_gemm_tile<64, 64>(M, m_dev, N, K, a, lda, b, ldb, bias, relu, C32, c16, ldc, st);
     return hipGetLastError();
 }
 

@@ -46,13 +46,14 @@ struct Arena {
 // Forward pass; activations of layers 1..3 (BF16, [M][dims[l]]) go to act[1..3],
 // the FP32 logits to `logits`.
 int forward(const scn_mlp* n, const uint16_t* x, int M, uint16_t* const* act, float* logits,
-            hipStream_t st) {
+            hipStream_t st, const int32_t* m_dev = nullptr) {
     const void* in = x;
     for (int l = 0; l < SCN_MLP_LAYERS; ++l) {
         const int K = n->dims[l], N = n->dims[l + 1];
         const bool last = l == SCN_MLP_LAYERS - 1;
         SCN_HIP(scn::launch_gemm(M, N, K, in, K, n->wb[l], K, n->b[l], !last,
-                                 last ? logits : nullptr, last ? nullptr : act[l + 1], N, st));
+                                 last ? logits : nullptr, last ? nullptr : act[l + 1], N, st,
+                                 m_dev));
         in = act[l + 1];
     }
     return SCN_OK;
@@ -138,12 +139,12 @@ size_t scn::ws_mlp_train_bytes(const scn_mlp* n, int rows) {
 }
 
 int scn_mlp_forward_ws(const scn_mlp* n, const uint16_t* x, int M, float* logits, void* act_ws,
-                       hipStream_t st) {
+                       hipStream_t st, const int32_t* m_dev) {
     if (M <= 0) return SCN_OK;
     Arena a{(char*)act_ws, 0};
     uint16_t* act[SCN_MLP_LAYERS] = {nullptr};
     for (int l = 1; l < SCN_MLP_LAYERS; ++l) act[l] = a.take<uint16_t>((size_t)M * max_hidden(n));
-    return forward(n, x, M, act, logits, st);
+    return forward(n, x, M, act, logits, st, m_dev);
 }
 
 extern "C" {

@@ -450,6 +450,36 @@ __device__ __forceinline__ unsigned long long reachable_boxes(const ObjConsts& K
     return __ballot(rel);
 }
 
+// The 4 constants the place kernel keeps per object to place (written by
+// lane 0 to I[0..3]): bounding centre and radius, the two probes, and the
+// lift, flags (second probe; non-finite template or support) and the mask of
+// the scene's first 64 boxes some candidate can reach.  One wave per object.
+template <int SPL, bool kProbe2>
+__device__ __forceinline__ void object_info(const float4* __restrict__ tmpl,
+                                            const int32_t* __restrict__ sph_off,
+                                            const int32_t* __restrict__ obj_sup,
+                                            const float* __restrict__ sup,
+                                            const float* __restrict__ box, int o, int b0,
+                                            int nbox_mask, float margin, int lane, float4* I) {
+    const int sb = sph_off[o];
+    const ObjConsts K = object_consts<SPL, kProbe2>(tmpl, sb, sph_off[o + 1] - sb, lane);
+    const Support U = load_support(sup, obj_sup[o]);
+    // a non-finite template sphere or support entry: every candidate of the
+    // object collides
+    bool fin_ok = lane < 16 ? __builtin_isfinite(sup[16 * obj_sup[o] + lane]) : true;
+    for (int k = sb + lane; k < sph_off[o + 1]; k += kWave) fin_ok &= finite4(tmpl[k]);
+    const bool obj_bad = __ballot(!fin_ok) != 0;
+    const unsigned long long rel = reachable_boxes(K, U, K.rho + margin, box, b0, nbox_mask, lane);
+    if (lane == 0) {
+        I[0] = make_float4(K.bc[0], K.bc[1], K.bc[2], K.rho);
+        I[1] = K.probe;
+        I[2] = K.probe2;
+        I[3] = make_float4(K.lift, __int_as_float((K.two ? 1 : 0) | (obj_bad ? 2 : 0)),
+                           __int_as_float((int)(unsigned)rel),
+                           __int_as_float((int)(unsigned)(rel >> 32)));
+    }
+}
+
 // kLds = true : the scene's placed spheres live in LDS (cap_sph of them);
 //               with `split`, scenes with more spheres are left to the
 //               other launch, otherwise they are a capacity error.
@@ -469,7 +499,8 @@ __device__ __forceinline__ unsigned long long reachable_boxes(const ObjConsts& K
     const int32_t* __restrict__ box_off, const float* __restrict__ box, \
     float4* __restrict__ placed, int32_t* __restrict__ n_placed, int8_t* __restrict__ status, \
     scn_pose_rec* __restrict__ rec, int32_t* __restrict__ chosen, \
-    unsigned long long* __restrict__ counters, const int32_t* __restrict__ order, uint64_t seed, \
+    unsigned long long* __restrict__ counters, const int32_t* __restrict__ order, \
+    const int32_t* __restrict__ n_order, uint64_t seed, \
     float margin, int retries, int default_ncand, int max_steps, int cap_sph, int cap_obj, \
     int split, int split_sph, const int32_t* __restrict__ prop_bins, int prop_k, \
     int32_t* __restrict__ resume, int chunk, int j_cap, int32_t* __restrict__ n_active, \
@@ -477,11 +508,12 @@ __device__ __forceinline__ unsigned long long reachable_boxes(const ObjConsts& K
     const int32_t* __restrict__ grid_src, const int64_t* __restrict__ grid_val_off, \
     const float* __restrict__ grid_val, const int32_t* __restrict__ obj_rel, \
     const float* __restrict__ rel, const float* __restrict__ obj_ratio, \
-    const float* __restrict__ robot, const float* __restrict__ obj_reach, scn_reach_map rmap
+    const float* __restrict__ robot, const float* __restrict__ obj_reach, scn_reach_map rmap, \
+    int8_t* __restrict__ map_keep, float4* __restrict__ bnd_keep, const float4* __restrict__ info_keep
 #define SCN_PLACE_ARGS \
-    obj_off, sph_off, tmpl, obj_sup, obj_ncand, sup, box_off, box, placed, n_placed, status, rec, chosen, counters, order, seed, margin, retries, default_ncand, max_steps, cap_sph, cap_obj, split, split_sph, prop_bins, prop_k, resume, chunk, j_cap, n_active, \
+    obj_off, sph_off, tmpl, obj_sup, obj_ncand, sup, box_off, box, placed, n_placed, status, rec, chosen, counters, order, n_order, seed, margin, retries, default_ncand, max_steps, cap_sph, cap_obj, split, split_sph, prop_bins, prop_k, resume, chunk, j_cap, n_active, \
     grid_off, grid, grid_src, grid_val_off, grid_val, obj_rel, rel, obj_ratio, robot, obj_reach, \
-    rmap
+    rmap, map_keep, bnd_keep, info_keep
 
 template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons>
 __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
@@ -505,6 +537,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     __shared__ DepthMap s_dm;   // read where used (volatile), not held in registers
     __shared__ RelState s_rel;  // the current object's spatial relation
 
+    // with n_order, only the first *n_order entries of `order` are scenes of
+    // this launch (a list compacted on the device); the other workgroups leave
+    if (n_order && (int)blockIdx.x >= *n_order) return;
     const int s = order ? order[blockIdx.x] : (int)blockIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform_int(threadIdx.x >> 6);
@@ -561,7 +596,10 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         q.w += margin;
         lsph[i] = q;
     }
-    for (int ob = wave; ob < j; ob += W) {
+    // (with bnd_keep the bounding spheres recorded when each was placed)
+    if (bnd_keep)
+        for (int ob = threadIdx.x; ob < j; ob += blockDim.x) lbnd[ob] = bnd_keep[o0 + ob];
+    for (int ob = bnd_keep ? j : wave; ob < j; ob += W) {
         const int a0 = sph_off[o0 + ob] - first, a1 = sph_off[o0 + ob + 1] - first;
         float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
         for (int k = a0 + lane; k < a1; k += kWave) {
@@ -599,10 +637,16 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 if (threadIdx.x == 0) s_dm = dm;
                 const int words = (dm.nx * dm.ny * dm.nz + 3) >> 2;
                 int* mw = reinterpret_cast<int*>(lmap);
-                for (int i = threadIdx.x; i < words; i += blockDim.x) mw[i] = (int)0x80808080u;
-                __syncthreads();
                 const int n_old = sph_off[o0 + j] - first;
-                for (int i = threadIdx.x; i < n_old; i += blockDim.x) {
+                // with map_keep, the map the launch that placed the scene's
+                // last object stored (every placing launch stores it)
+                const bool kept = map_keep && j > 0;
+                const int* src = kept ? reinterpret_cast<const int*>(map_keep + (size_t)s * kMapBytes)
+                                      : nullptr;
+                for (int i = threadIdx.x; i < words; i += blockDim.x)
+                    mw[i] = kept ? src[i] : (int)0x80808080u;
+                __syncthreads();
+                for (int i = kept ? n_old : (int)threadIdx.x; i < n_old; i += blockDim.x) {
                     const float4 q = placed[first + i];
                     const float dx = q.x - U0.t[0], dy = q.y - U0.t[1], dz = q.z - U0.t[2];
                     map_insert(lmap, dm, fmaf(U0.R[0], dx, fmaf(U0.R[3], dy, U0.R[6] * dz)),
@@ -629,25 +673,15 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     // objects overlap here instead of stalling each object's start.
     // A second probe is not used in grid batches: their placements rarely
     // collide, and its registers would cost occupancy.
-    for (int jj = j + wave; jj < j_end; jj += W) {
-        const int o = o0 + jj, sb = sph_off[o];
-        const ObjConsts K = object_consts<SPL, !kGrids>(tmpl, sb, sph_off[o + 1] - sb, lane);
-        const Support U = load_support(sup, obj_sup[o]);
-        // a non-finite template sphere or support entry: every candidate of
-        // the object collides
-        bool fin_ok = lane < 16 ? __builtin_isfinite(sup[16 * obj_sup[o] + lane]) : true;
-        for (int k = sb + lane; k < sph_off[o + 1]; k += kWave) fin_ok &= finite4(tmpl[k]);
-        const bool obj_bad = __ballot(!fin_ok) != 0;
-        const unsigned long long rel = reachable_boxes(K, U, K.rho + margin, box, b0, nbox_mask, lane);
-        if (lane == 0) {
-            float4* I = linfo + 4 * jj;
-            I[0] = make_float4(K.bc[0], K.bc[1], K.bc[2], K.rho);
-            I[1] = K.probe;
-            I[2] = K.probe2;
-            I[3] = make_float4(K.lift, __int_as_float((K.two ? 1 : 0) | (obj_bad ? 2 : 0)),
-                               __int_as_float((int)(unsigned)rel),
-                               __int_as_float((int)(unsigned)(rel >> 32)));
-        }
+    // With info_keep (computed once per generation by k_object_info) they
+    // are only copied.
+    if (info_keep) {
+        for (int i = threadIdx.x; i < 4 * (j_end - j); i += blockDim.x)
+            linfo[4 * j + i] = info_keep[4 * (size_t)(o0 + j) + i];
+    } else {
+        for (int jj = j + wave; jj < j_end; jj += W)
+            object_info<SPL, !kGrids>(tmpl, sph_off, obj_sup, sup, box, o0 + jj, b0, nbox_mask,
+                                      margin, lane, linfo + 4 * jj);
     }
     // the scene's boxes all turn about z only (then, with a support that does
     // too, the entry loop runs its planar form); the barrier also publishes
@@ -666,8 +700,12 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     if constexpr (kGrids)
         for (int gi = g0 + (int)threadIdx.x; gi < g1; gi += blockDim.x)
             bad_in |= !all_finite(grid + 24 * gi, 19);
-    for (int i = threadIdx.x; i < sph_off[o0 + j] - first; i += blockDim.x)
-        bad_in |= !finite4(placed[first + i]);
+    // (with bnd_keep every placed sphere comes from an earlier launch of the
+    // same generation, which placed it only from a finite template, support
+    // and pose)
+    if (!bnd_keep)
+        for (int i = threadIdx.x; i < sph_off[o0 + j] - first; i += blockDim.x)
+            bad_in |= !finite4(placed[first + i]);
     const bool boxes_yaw = !__syncthreads_or(tilted);
     const bool scene_bad = __syncthreads_or(bad_in) != 0;
 
@@ -766,11 +804,12 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         const int total = pk + (C > 0 ? (retries + 1) * C : 0);   // entries of the list
         // entries [g_lo, g_hi) of the list are tried in this launch: with a
         // chunk, the proposals plus `chunk` uniform entries, then `chunk` more
-        // per launch; earlier launches found none of the entries before g_lo
-        // valid, so the lowest valid entry of [g_lo, g_hi) is the first valid
-        // one of the whole list
+        // per launch (chunk < 0: the proposals alone, then the uniform entries
+        // from a later launch); earlier launches found none of the entries
+        // before g_lo valid, so the lowest valid entry of [g_lo, g_hi) is the
+        // first valid one of the whole list
         const int g_lo = j == j_start ? min(resume0, total) : 0;
-        const int g_hi = chunk > 0 ? min(total, max(g_lo, pk) + chunk) : total;
+        const int g_hi = chunk != 0 ? min(total, max(g_lo, pk) + max(chunk, 0)) : total;
         const int nob_mask = min(j, kWave * kObjWords);     // objects covered by the masks
 
         if (threadIdx.x == 0) s_best = INT_MAX;
@@ -1152,13 +1191,15 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                     to_world(U, P, bc[0], bc[1], bc[2], gx, gy, gz);
                 }
                 lbnd[j] = make_float4(gx, gy, gz, rho);
+                if (bnd_keep) bnd_keep[o] = make_float4(gx, gy, gz, rho);
                 rec[o] = scn_pose_rec{P.x, P.y, P.z, P.yaw, fa, fi};
             }
             ++n_done;
         }
         // the new object's spheres into the depth map (voxels split over the
-        // waves); a later launch rebuilds the map from the placed spheres
-        if (kMap && use_map && j + 1 < j_end) {
+        // waves); a later launch rebuilds the map from the placed spheres, or
+        // with map_keep loads the one stored below
+        if (kMap && use_map && (j + 1 < j_end || map_keep)) {
             const DepthMap dm = map_params(&s_dm);
 #pragma unroll
             for (int q = 0; q < SPL; ++q)
@@ -1169,6 +1210,17 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         }
         last = fi;
         __syncthreads();
+    }
+    // the depth map of a scene that placed in this launch back to map_keep
+    // (the barrier ending the last placement ordered every insert before)
+    if constexpr (kMap) {
+        if (map_keep && use_map && j > j_start) {
+            const DepthMap dm = map_params(&s_dm);
+            const int words = (dm.nx * dm.ny * dm.nz + 3) >> 2;
+            int* dst = reinterpret_cast<int*>(map_keep + (size_t)s * kMapBytes);
+            const int* mw = reinterpret_cast<const int*>(lmap);
+            for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = mw[i];
+        }
     }
     if (threadIdx.x == 0) {
         n_placed[s] = j;
@@ -1247,12 +1299,13 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
     hipLaunchKernelGGL(kern, dim3(b.n_scenes), dim3(kWave * plan.waves), bytes, st, b.obj_off,
                        b.sph_off, (const float4*)b.tmpl, b.obj_sup, b.obj_ncand, b.sup,
                        b.box_off, b.box, (float4*)b.placed, b.n_placed, b.status, b.rec, chosen,
-                       ctr, plan.order, a.seed, a.margin, a.retries, a.default_ncand,
+                       ctr, plan.order, plan.n_order, a.seed, a.margin, a.retries, a.default_ncand,
                        plan.max_steps, cap_sph, plan.cap_obj, split, plan.split_sph,
                        plan.prop_bins, plan.prop_k, plan.resume, plan.chunk, plan.j_cap,
                        plan.n_active, b.grid_off, b.grid, b.grid_src,
                        b.grid_val_off, b.grid_val, b.obj_rel, b.rel, b.obj_ratio, b.robot,
-                       b.obj_reach, b.reach);
+                       b.obj_reach, b.reach, (int8_t*)plan.map_keep, (float4*)plan.bnd_keep,
+                       (const float4*)plan.info_keep);
     return hipGetLastError();
 }
 
@@ -1273,6 +1326,40 @@ static hipError_t launch_place_spl(const scn_batch& b, const scn_gen_args& a,
         }
         default: return hipErrorInvalidValue;
     }
+}
+
+// Every object's 4 place-kernel constants (object_info) into info, once per
+// generation: one workgroup of 4 waves per scene, one wave per object.
+template <int SPL, bool kProbe2>
+__global__ __launch_bounds__(256) void k_object_info(
+    int n, const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
+    const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
+    const float* __restrict__ sup, const int32_t* __restrict__ box_off,
+    const float* __restrict__ box, float margin, float4* __restrict__ info) {
+    const int s = blockIdx.x;
+    if (s >= n) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform_int(threadIdx.x >> 6), W = blockDim.x >> 6;
+    const int b0 = box_off[s], nbox_mask = min(box_off[s + 1] - b0, kWave);
+    for (int o = obj_off[s] + wave; o < obj_off[s + 1]; o += W)
+        object_info<SPL, kProbe2>(tmpl, sph_off, obj_sup, sup, box, o, b0, nbox_mask, margin, lane,
+                                  info + 4 * (size_t)o);
+}
+
+hipError_t launch_object_info(const scn_batch& b, float margin, void* info, hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    const int S = b.max_spheres_per_object;
+    const dim3 grid(b.n_scenes), block(256);
+    auto args = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, 0, st, b.n_scenes, b.obj_off, b.sph_off,
+                           (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box, margin,
+                           (float4*)info);
+    };
+    const bool p2 = b.grid_off == nullptr;   // the second probe serves grid-free batches
+    if (S <= 64) p2 ? args(k_object_info<1, true>) : args(k_object_info<1, false>);
+    else if (S <= 128) p2 ? args(k_object_info<2, true>) : args(k_object_info<2, false>);
+    else p2 ? args(k_object_info<4, true>) : args(k_object_info<4, false>);
+    return hipGetLastError();
 }
 
 hipError_t launch_place(const scn_batch& b, const scn_gen_args& a, const PlacePlan& plan,

@@ -67,7 +67,8 @@ class _GenArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("margin", C.c_float), ("retries", C.c_int32),
                 ("default_ncand", C.c_int32), ("max_steps", C.c_int32),
                 ("schedule", C.c_int32), ("use_graph", C.c_int32),
-                ("fallback_chunk", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("fallback_chunk", C.c_int32), ("wide_schedule", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Counters(C.Structure):
@@ -264,6 +265,7 @@ class GenArgs:
     schedule: int = 0
     use_graph: int = 0
     fallback_chunk: int = 0
+    wide_schedule: int = 0
 
     def c(self) -> _GenArgs:
         a = _GenArgs()
@@ -271,6 +273,7 @@ class GenArgs:
         a.default_ncand, a.max_steps = int(self.default_ncand), int(self.max_steps)
         a.schedule, a.use_graph = int(self.schedule), int(self.use_graph)
         a.fallback_chunk = int(self.fallback_chunk)
+        a.wide_schedule = int(self.wide_schedule)
         return a
 
 
