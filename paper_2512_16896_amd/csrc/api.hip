@@ -431,7 +431,7 @@ int scn_place_step(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int32_t* cho
 __attribute__((visibility("hidden"))) int scn_place_rows(
     scn_ctx* c, scn_batch* b, const scn_gen_args* a, const int32_t* prop_bins, int prop_k,
     int32_t* resume, int chunk, int j_cap, const int32_t* rows, const int32_t* n_rows,
-    void* map_keep, void* bnd_keep, const void* info_keep, hipStream_t st) {
+    void* map_keep, void* bnd_keep, const void* info_keep, float* hmap, hipStream_t st) {
     // the launch order is the list's: no longest-first order is computed
     scn_gen_args a1 = *a;
     if (a1.schedule != 0) a1.schedule &= ~SCN_SCHED_LONGEST_FIRST;
@@ -450,6 +450,7 @@ __attribute__((visibility("hidden"))) int scn_place_rows(
     plan.map_keep = map_keep;
     plan.bnd_keep = bnd_keep;
     plan.info_keep = info_keep;
+    plan.hmap = hmap;
     SCN_HIP(scn::launch_place(*b, *a, plan, nullptr, c->d_counters, st));
     return SCN_OK;
 }

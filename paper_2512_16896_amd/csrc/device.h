@@ -280,4 +280,62 @@ __device__ __forceinline__ float uniform_f(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// ---------------------------------------------------------------------------
+// Height map of scene s over its first object's support (the learned
+// proposal's state feature): cell (ix, iy), ix along x in [0,64), iy along y,
+// centre (-hx + (ix + 1/2) 2hx/64, -hy + ...); value = max(0, box tops, sphere
+// tops) above the support plane, metres.  A box covers a cell when the cell
+// centre at the box centre's height lies in the box's x/y extent (box frame);
+// its top is the box's highest point.  A sphere (support-frame centre p,
+// radius r) covers a cell when the cell centre is within r of p in x/y; its
+// top there is p_z + sqrt(r^2 - d^2).
+struct SupportFrame {
+    float R[9], t[3], hx, hy;
+};
+__device__ __forceinline__ SupportFrame scene_support(const int32_t* __restrict__ obj_off,
+                                                      const int32_t* __restrict__ obj_sup,
+                                                      const float* __restrict__ sup, int s) {
+    SupportFrame F;
+    const int o = obj_off[s] < obj_off[s + 1] ? obj_off[s] : -1;
+    const float* p = sup + 16 * (o >= 0 ? obj_sup[o] : 0);
+    for (int i = 0; i < 9; ++i) F.R[i] = p[i];
+    F.t[0] = p[9]; F.t[1] = p[10]; F.t[2] = p[11];
+    F.hx = p[12]; F.hy = p[13];
+    return F;
+}
+// world point -> support frame: R^T (p - t)
+__device__ __forceinline__ void to_support(const SupportFrame& F, float x, float y, float z,
+                                           float& sx, float& sy, float& sz) {
+    const float dx = x - F.t[0], dy = y - F.t[1], dz = z - F.t[2];
+    sx = F.R[0] * dx + F.R[3] * dy + F.R[6] * dz;
+    sy = F.R[1] * dx + F.R[4] * dy + F.R[7] * dz;
+    sz = F.R[2] * dx + F.R[5] * dy + F.R[8] * dz;
+}
+// Raise a scene's height map (64 x 64 floats at hm) by one world sphere:
+// a monotone max through integer atomics on non-negative floats, so the
+// result does not depend on the order of the spheres or of the callers.
+__device__ __forceinline__ void hmap_raise_sphere(const SupportFrame& F, float* __restrict__ hm,
+                                                  float x, float y, float z, float r) {
+    const float cw = 2.f * F.hx / 64.f, ch = 2.f * F.hy / 64.f;
+    int* H = (int*)hm;
+    float px, py, pz;
+    to_support(F, x, y, z, px, py, pz);
+    // cells whose centre can lie within r of (px, py)
+    const int ix0 = max(0, (int)floorf((px - r + F.hx) / cw - 0.5f));
+    const int ix1 = min(63, (int)ceilf((px + r + F.hx) / cw - 0.5f));
+    const int iy0 = max(0, (int)floorf((py - r + F.hy) / ch - 0.5f));
+    const int iy1 = min(63, (int)ceilf((py + r + F.hy) / ch - 0.5f));
+    for (int ix = ix0; ix <= ix1; ++ix) {
+        const float cx = -F.hx + (ix + 0.5f) * cw;
+        for (int iy = iy0; iy <= iy1; ++iy) {
+            const float cy = -F.hy + (iy + 0.5f) * ch;
+            const float d2 = (cx - px) * (cx - px) + (cy - py) * (cy - py);
+            if (d2 < r * r) {
+                const float top = pz + sqrtf(r * r - d2);
+                if (top > 0.f) atomicMax(H + ix * 64 + iy, __float_as_int(top));
+            }
+        }
+    }
+}
+
 }  // namespace scn

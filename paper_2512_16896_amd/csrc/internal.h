@@ -114,6 +114,7 @@ struct PlacePlan {
     void* map_keep = nullptr;
     void* bnd_keep = nullptr;
     const void* info_keep = nullptr;
+    float* hmap = nullptr;   // learned proposal: height maps raised at each commit
 };
 
 // learned-proposal kernels (learned.hip)
@@ -127,10 +128,8 @@ hipError_t launch_features(int n, const float* hmap, const float* desc, const in
 hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active, int32_t* bins,
                        hipStream_t st, const int32_t* rows = nullptr,
                        const int32_t* m_dev = nullptr);
-hipError_t launch_hmap_raise_rows(const scn_batch& b, const int32_t* rows, const int32_t* m_dev,
-                                  const int32_t* before, float* hmap, hipStream_t st);
 hipError_t launch_tick_plan(const scn_batch& b, const int32_t* resume, int j_cap, int32_t* list,
-                            int32_t* obj_idx, int32_t* count, int32_t* before, hipStream_t st);
+                            int32_t* obj_idx, int32_t* count, hipStream_t st);
 hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,
                           int round, float margin, int32_t* bins, float* accept,
                           int64_t* counters, hipStream_t st);

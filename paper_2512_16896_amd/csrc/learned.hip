@@ -109,29 +109,6 @@ hipError_t launch_descriptor(const scn_batch& b, float* desc, hipStream_t st) {
 // the box's x/y extent (box frame); its top is the box's highest point.
 // A sphere (support-frame centre p, radius r) covers a cell when the cell
 // centre is within r of p in x/y; its top there is p_z + sqrt(r^2 - d^2).
-struct SupportFrame {
-    float R[9], t[3], hx, hy;
-};
-__device__ __forceinline__ SupportFrame scene_support(const int32_t* __restrict__ obj_off,
-                                                      const int32_t* __restrict__ obj_sup,
-                                                      const float* __restrict__ sup, int s) {
-    SupportFrame F;
-    const int o = obj_off[s] < obj_off[s + 1] ? obj_off[s] : -1;
-    const float* p = sup + 16 * (o >= 0 ? obj_sup[o] : 0);
-    for (int i = 0; i < 9; ++i) F.R[i] = p[i];
-    F.t[0] = p[9]; F.t[1] = p[10]; F.t[2] = p[11];
-    F.hx = p[12]; F.hy = p[13];
-    return F;
-}
-// world point -> support frame: R^T (p - t)
-__device__ __forceinline__ void to_support(const SupportFrame& F, float x, float y, float z,
-                                           float& sx, float& sy, float& sz) {
-    const float dx = x - F.t[0], dy = y - F.t[1], dz = z - F.t[2];
-    sx = F.R[0] * dx + F.R[3] * dy + F.R[6] * dz;
-    sy = F.R[1] * dx + F.R[4] * dy + F.R[7] * dz;
-    sz = F.R[2] * dx + F.R[5] * dy + F.R[8] * dz;
-}
-
 __global__ __launch_bounds__(256) void k_hmap_boxes(
     int n, const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
     const float* __restrict__ sup, const int32_t* __restrict__ box_off,
@@ -178,29 +155,9 @@ __device__ void raise_scene(int s, int k0, int k1, const int32_t* __restrict__ o
                             const int32_t* __restrict__ obj_sup, const float* __restrict__ sup,
                             const float4* __restrict__ placed, float* __restrict__ hmap) {
     const SupportFrame F = scene_support(obj_off, obj_sup, sup, s);
-    const float cw = 2.f * F.hx / 64.f, ch = 2.f * F.hy / 64.f;
-    int* H = (int*)(hmap + (size_t)s * 4096);
     for (int k = k0 + threadIdx.x; k < k1; k += kWave) {
         const float4 q = placed[k];
-        float px, py, pz;
-        to_support(F, q.x, q.y, q.z, px, py, pz);
-        const float r = q.w;
-        // cells whose centre can lie within r of (px, py)
-        const int ix0 = max(0, (int)floorf((px - r + F.hx) / cw - 0.5f));
-        const int ix1 = min(63, (int)ceilf((px + r + F.hx) / cw - 0.5f));
-        const int iy0 = max(0, (int)floorf((py - r + F.hy) / ch - 0.5f));
-        const int iy1 = min(63, (int)ceilf((py + r + F.hy) / ch - 0.5f));
-        for (int ix = ix0; ix <= ix1; ++ix) {
-            const float cx = -F.hx + (ix + 0.5f) * cw;
-            for (int iy = iy0; iy <= iy1; ++iy) {
-                const float cy = -F.hy + (iy + 0.5f) * ch;
-                const float d2 = (cx - px) * (cx - px) + (cy - py) * (cy - py);
-                if (d2 < r * r) {
-                    const float top = pz + sqrtf(r * r - d2);
-                    if (top > 0.f) atomicMax(H + ix * 64 + iy, __float_as_int(top));
-                }
-            }
-        }
+        hmap_raise_sphere(F, hmap + (size_t)s * 4096, q.x, q.y, q.z, q.w);
     }
 }
 
@@ -227,39 +184,12 @@ __global__ __launch_bounds__(64) void k_hmap_raise(
     raise_scene(s, k0, k1, obj_off, obj_sup, sup, placed, hmap);
 }
 
-// The same for the scenes rows[0 .. *m_dev) of a compacted list: a scene
-// whose n_placed grew past before[s] in the step just run is raised by the
-// object it placed (obj_off[s] + n_placed[s] - 1).
-__global__ __launch_bounds__(64) void k_hmap_raise_rows(
-    int n, const int32_t* __restrict__ rows, const int32_t* __restrict__ m_dev,
-    const int32_t* __restrict__ before, const int32_t* __restrict__ n_placed,
-    const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
-    const float* __restrict__ sup, const int32_t* __restrict__ sph_off,
-    const float4* __restrict__ placed, float* __restrict__ hmap) {
-    const int r = blockIdx.x;
-    if (r >= n || r >= *m_dev) return;
-    const int s = rows[r];
-    const int j = n_placed[s];
-    if (j <= before[s] || j > obj_off[s + 1] - obj_off[s]) return;
-    const int o = obj_off[s] + j - 1;
-    raise_scene(s, sph_off[o], sph_off[o + 1], obj_off, obj_sup, sup, placed, hmap);
-}
-
-hipError_t launch_hmap_raise_rows(const scn_batch& b, const int32_t* rows, const int32_t* m_dev,
-                                  const int32_t* before, float* hmap, hipStream_t st) {
-    if (b.n_scenes == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hmap_raise_rows, dim3(b.n_scenes), dim3(64), 0, st, b.n_scenes, rows,
-                       m_dev, before, b.n_placed, b.obj_off, b.obj_sup, b.sup, b.sph_off,
-                       (const float4*)b.placed, hmap);
-    return hipGetLastError();
-}
-
 // The learned pipeline's plan of one tick: the active scenes below the
 // objects cap that still have an object to place, split into those that start
 // a new object (resume[s] == 0: they need proposals; list[0 ..), with the
 // object in obj_idx by row) and those resuming the uniform entries of a
 // pending one (list[n ..)).  count[0] and count[1] (zeroed by the caller)
-// receive the two sizes; before[s] = n_placed[s] for every listed scene.
+// receive the two sizes.
 // Appends are aggregated per wave, so the order within each list is not the
 // scene order; each scene's step does not depend on it.
 __global__ __launch_bounds__(256) void k_tick_plan(int n, const int32_t* __restrict__ obj_off,
@@ -268,8 +198,7 @@ __global__ __launch_bounds__(256) void k_tick_plan(int n, const int32_t* __restr
                                                    const int32_t* __restrict__ resume, int j_cap,
                                                    int32_t* __restrict__ list,
                                                    int32_t* __restrict__ obj_idx,
-                                                   int32_t* __restrict__ count,
-                                                   int32_t* __restrict__ before) {
+                                                   int32_t* __restrict__ count) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & (kWave - 1);
     bool fresh = false, pending = false;
@@ -279,7 +208,6 @@ __global__ __launch_bounds__(256) void k_tick_plan(int n, const int32_t* __restr
         if (j < obj_off[s + 1] - obj_off[s] && (j_cap <= 0 || j < j_cap)) {
             fresh = resume[s] == 0;
             pending = !fresh;
-            before[s] = j;
         }
     }
     const unsigned long long lower = lane ? (~0ull >> (kWave - lane)) : 0ull;
@@ -300,11 +228,10 @@ __global__ __launch_bounds__(256) void k_tick_plan(int n, const int32_t* __restr
 }
 
 hipError_t launch_tick_plan(const scn_batch& b, const int32_t* resume, int j_cap, int32_t* list,
-                            int32_t* obj_idx, int32_t* count, int32_t* before, hipStream_t st) {
+                            int32_t* obj_idx, int32_t* count, hipStream_t st) {
     if (b.n_scenes == 0) return hipSuccess;
     hipLaunchKernelGGL(k_tick_plan, dim3((b.n_scenes + 255) / 256), dim3(256), 0, st, b.n_scenes,
-                       b.obj_off, b.n_placed, b.status, resume, j_cap, list, obj_idx, count,
-                       before);
+                       b.obj_off, b.n_placed, b.status, resume, j_cap, list, obj_idx, count);
     return hipGetLastError();
 }
 

@@ -114,7 +114,7 @@ int scn_harvest_labels(scn_ctx* c, const scn_batch* b, const int32_t* n_state, i
 __attribute__((visibility("hidden"))) int scn_place_rows(
     scn_ctx* c, scn_batch* b, const scn_gen_args* a, const int32_t* prop_bins, int prop_k,
     int32_t* resume, int chunk, int j_cap, const int32_t* rows, const int32_t* n_rows,
-    void* map_keep, void* bnd_keep, const void* info_keep, hipStream_t st);
+    void* map_keep, void* bnd_keep, const void* info_keep, float* hmap, hipStream_t st);
 
 }  // extern "C"
 
@@ -128,7 +128,7 @@ struct LearnedWs {
     uint16_t* x;
     float* logits;
     int32_t* bins;
-    int32_t *obj_idx, *before, *list, *count, *resume;
+    int32_t *obj_idx, *list, *count, *resume;
     void *map_keep, *bnd_keep, *info_keep;   // state the step launches keep (PlacePlan)
 };
 size_t learned_layout(const scn_batch* b, const scn_mlp* net, int top_k, char* base,
@@ -148,7 +148,6 @@ size_t learned_layout(const scn_batch* b, const scn_mlp* net, int top_k, char* b
     t.logits = (float*)take(n * SCN_BINS * 4);
     t.bins = (int32_t*)take(n * (size_t)top_k * 4);
     t.obj_idx = (int32_t*)take(n * 4);
-    t.before = (int32_t*)take(n * 4);
     t.list = (int32_t*)take(2 * n * 4);
     t.count = (int32_t*)take(8);
     t.resume = (int32_t*)take(n * 4);
@@ -231,35 +230,34 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     int32_t* list_pend = W.list + n;   // scenes resuming a pending object's uniform entries
     auto plan = [&](hipStream_t s) -> int {
         SCN_HIP(scn::launch_fill_i32(W.count, 2, 0, s));
-        SCN_HIP(scn::launch_tick_plan(*b, W.resume, j_cap, W.list, W.obj_idx, W.count, W.before, s));
+        SCN_HIP(scn::launch_tick_plan(*b, W.resume, j_cap, W.list, W.obj_idx, W.count, s));
         return SCN_OK;
     };
     // One tick on stream s (and the context's second stream): the plan
     // splits the scenes with work into the two lists; the pending ones try
     // their next `chunk` uniform entries on the second stream while the new
     // ones run features, network and top-k over their compacted rows and try
-    // their proposals alone; each list raises the height maps of the scenes
-    // that placed.  The lists are disjoint, so the two streams never touch
+    // their proposals alone; a placing step raises its scene's height map at
+    // the commit.  The lists are disjoint, so the two streams never touch
     // the same scene.  Launch sizes are fixed (n rows / scenes); each kernel
     // reads its list's length on the device and the rest of its grid leaves.
     auto tick = [&](hipStream_t s, bool late) -> int {
         if (int r = plan(s)) return r;
         SCN_HIP(hipEventRecord(c->ev[0], s));
         SCN_HIP(hipStreamWaitEvent(c->aux_stream, c->ev[0], 0));
-        if (int r = scn_place_rows(c, b, &wide, W.bins, top_k, W.resume, chunk, j_cap, list_pend, W.count + 1, map_keep, W.bnd_keep,
-                                   W.info_keep, c->aux_stream))
+        if (int r = scn_place_rows(c, b, &wide, W.bins, top_k, W.resume, chunk, j_cap, list_pend,
+                                   W.count + 1, map_keep, W.bnd_keep, W.info_keep, W.hmap,
+                                   c->aux_stream))
             return r;
-        SCN_HIP(scn::launch_hmap_raise_rows(*b, list_pend, W.count + 1, W.before, W.hmap,
-                                            c->aux_stream));
         SCN_HIP(hipEventRecord(c->ev[1], c->aux_stream));
         SCN_HIP(scn::launch_features(n, W.hmap, W.desc, W.obj_idx, SCN_FEATURES, W.x, s, list_new,
                                      W.count));
         if (int r = scn_mlp_forward_ws(net, W.x, n, W.logits, W.act, s, W.count)) return r;
         SCN_HIP(scn::launch_topk(n, W.logits, top_k, nullptr, W.bins, s, list_new, W.count));
         if (int r = scn_place_rows(c, b, late ? &wide : a, W.bins, top_k, W.resume, -1, j_cap,
-                                   list_new, W.count, map_keep, W.bnd_keep, W.info_keep, s))
+                                   list_new, W.count, map_keep, W.bnd_keep, W.info_keep,
+                                   W.hmap, s))
             return r;
-        SCN_HIP(scn::launch_hmap_raise_rows(*b, list_new, W.count, W.before, W.hmap, s));
         SCN_HIP(hipStreamWaitEvent(s, c->ev[1], 0));
         return SCN_OK;
     };

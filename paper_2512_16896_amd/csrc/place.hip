@@ -509,11 +509,12 @@ __device__ __forceinline__ void object_info(const float4* __restrict__ tmpl,
     const float* __restrict__ grid_val, const int32_t* __restrict__ obj_rel, \
     const float* __restrict__ rel, const float* __restrict__ obj_ratio, \
     const float* __restrict__ robot, const float* __restrict__ obj_reach, scn_reach_map rmap, \
-    int8_t* __restrict__ map_keep, float4* __restrict__ bnd_keep, const float4* __restrict__ info_keep
+    int8_t* __restrict__ map_keep, float4* __restrict__ bnd_keep, const float4* __restrict__ info_keep, \
+    float* __restrict__ hmap
 #define SCN_PLACE_ARGS \
     obj_off, sph_off, tmpl, obj_sup, obj_ncand, sup, box_off, box, placed, n_placed, status, rec, chosen, counters, order, n_order, seed, margin, retries, default_ncand, max_steps, cap_sph, cap_obj, split, split_sph, prop_bins, prop_k, resume, chunk, j_cap, n_active, \
     grid_off, grid, grid_src, grid_val_off, grid_val, obj_rel, rel, obj_ratio, robot, obj_reach, \
-    rmap, map_keep, bnd_keep, info_keep
+    rmap, map_keep, bnd_keep, info_keep, hmap
 
 template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons>
 __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
@@ -1182,6 +1183,18 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                     if constexpr (kLds) lsph[sb - first + k] = make_float4(px, py, pz, cr[q] + margin);
                 }
             }
+            // the learned proposal's height map of the scene, raised by the
+            // committed spheres (the same arithmetic as k_hmap_raise)
+            if (hmap) {
+                const SupportFrame F = scene_support(obj_off, obj_sup, sup, s);
+#pragma unroll
+                for (int q = 0; q < SPL; ++q) {
+                    if (act[q]) {
+                        const float4 w = placed[sb + lane + kWave * q];
+                        hmap_raise_sphere(F, hmap + (size_t)s * 4096, w.x, w.y, w.z, w.w);
+                    }
+                }
+            }
             if (lane == 0) {
                 float gx, gy, gz;
                 if constexpr (kYaw) {
@@ -1305,7 +1318,7 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                        plan.n_active, b.grid_off, b.grid, b.grid_src,
                        b.grid_val_off, b.grid_val, b.obj_rel, b.rel, b.obj_ratio, b.robot,
                        b.obj_reach, b.reach, (int8_t*)plan.map_keep, (float4*)plan.bnd_keep,
-                       (const float4*)plan.info_keep);
+                       (const float4*)plan.info_keep, plan.hmap);
     return hipGetLastError();
 }
 
