@@ -43,7 +43,7 @@ class _Batch(C.Structure):
                 ("grid_val", C.c_void_p), ("scene_id", C.c_void_p),
                 ("obj_rel", C.c_void_p), ("rel", C.c_void_p), ("obj_ratio", C.c_void_p),
                 ("robot", C.c_void_p), ("obj_reach", C.c_void_p), ("reach_map", C.c_void_p),
-                ("reach_geom", C.c_void_p)]
+                ("reach_geom", C.c_void_p), ("obj_pose_off", C.c_void_p), ("stable", C.c_void_p)]
 
 
 class _GenArgs(C.Structure):
@@ -55,7 +55,7 @@ class _GenArgs(C.Structure):
 class _GenOut(C.Structure):
     _fields_ = [("status", C.c_void_p), ("n_placed", C.c_void_p),
                 ("rec_attempt", C.c_void_p), ("rec_idx", C.c_void_p),
-                ("rec_pose", C.c_void_p), ("rec_banded", C.c_void_p),
+                ("rec_pose", C.c_void_p), ("rec_stable", C.c_void_p), ("rec_banded", C.c_void_p),
                 ("rec_clear", C.c_void_p), ("placed", C.c_void_p), ("n_cand", C.c_void_p)]
 
 
@@ -73,8 +73,8 @@ def lib():
         L.orc_grid_sample.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
         L.orc_grid_sample.restype = C.c_double
         L.orc_sample_poses.argtypes = [C.POINTER(_Batch), C.c_void_p, C.c_void_p, C.c_uint64,
-                                       C.c_int] + [C.c_void_p] * 4
-        L.orc_check.argtypes = [C.POINTER(_Batch)] + [C.c_void_p] * 9
+                                       C.c_int] + [C.c_void_p] * 5
+        L.orc_check.argtypes = [C.POINTER(_Batch)] + [C.c_void_p] * 10
         L.orc_generate.argtypes = [C.POINTER(_Batch), C.POINTER(_GenArgs), C.POINTER(_GenOut)]
         L.orc_fk_links.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_uint64, C.c_int, C.c_void_p, C.c_void_p]
@@ -125,6 +125,10 @@ class _Keep:
             self.obj_reach = np.ascontiguousarray(b.obj_reach, np.float64)
             self.reach_map = np.ascontiguousarray(b.reach_map, np.uint8)
             self.reach_geom = np.ascontiguousarray(b.reach_geom, np.float64)
+        self.obj_pose_off = self.stable = None
+        if getattr(b, "obj_pose_off", None) is not None:
+            self.obj_pose_off = np.ascontiguousarray(b.obj_pose_off, np.int32)
+            self.stable = np.ascontiguousarray(b.stable, np.float64).reshape(-1, 12)
         self.cb = _Batch(int(len(self.obj_off) - 1), _p(self.obj_off), _p(self.sph_off),
                          _p(self.tmpl), _p(self.obj_sup), _p(self.obj_ncand), _p(self.sup),
                          _p(self.box_off), _p(self.box), _p(self.grid_off), _p(self.grid),
@@ -132,7 +136,7 @@ class _Keep:
                          C.cast(self.grid_ptrs, C.c_void_p) if self.grid_ptrs is not None else None,
                          _p(self.scene_id), _p(self.obj_rel), _p(self.rel), _p(self.obj_ratio),
                          _p(self.robot), _p(self.obj_reach), _p(self.reach_map),
-                         _p(self.reach_geom))
+                         _p(self.reach_geom), _p(self.obj_pose_off), _p(self.stable))
 
 
 # ---------------------------------------------------------------------------
@@ -172,29 +176,35 @@ def grid_sample(vals, origin, h, pg) -> float:
     return float(lib().orc_grid_sample(_p(v), _p(dims), _p(o), float(h), _p(pg)))
 
 
-def sample_poses(b, obj_idx, cand_off, seed: int, attempt: int, scene_id=None):
+def sample_poses(b, obj_idx, cand_off, seed: int, attempt: int, scene_id=None,
+                 with_stable: bool = False):
+    """Candidate poses (x, y, z, yaw) in the support frame; with_stable also
+    returns each candidate's stable-pose row (-1: none)."""
     K = _Keep(b, scene_id)
     oi = np.ascontiguousarray(obj_idx, np.int32)
     co = np.ascontiguousarray(cand_off, np.int32)
     tot = int(co[-1])
     out = [np.zeros(tot, np.float64) for _ in range(4)]
+    kk = np.zeros(tot, np.int32)
     lib().orc_sample_poses(C.byref(K.cb), _p(oi), _p(co), C.c_uint64(seed), int(attempt),
-                           *[_p(a) for a in out])
-    return out
+                           *[_p(a) for a in out], _p(kk))
+    return out + [kk] if with_stable else out
 
 
 def check(b, obj_idx, cand_off, n_placed, placed, poses, scene_id=None) -> np.ndarray:
     """Clearance of each candidate pose (support frame) of object obj_idx[s]
-    against scene s's boxes/grids and its first n_placed[s] objects."""
+    against scene s's boxes/grids and its first n_placed[s] objects.  poses:
+    (x, y, z, yaw) or (x, y, z, yaw, stable row)."""
     K = _Keep(b, scene_id)
     oi = np.ascontiguousarray(obj_idx, np.int32)
     co = np.ascontiguousarray(cand_off, np.int32)
     npl = np.ascontiguousarray(n_placed, np.int32)
     pl = np.ascontiguousarray(placed, np.float64).reshape(-1, 4)
-    ps = [np.ascontiguousarray(a, np.float64) for a in poses]
+    ps = [np.ascontiguousarray(a, np.float64) for a in poses[:4]]
+    kk = np.ascontiguousarray(poses[4], np.int32) if len(poses) > 4 else None
     clr = np.zeros(int(co[-1]), np.float64)
     lib().orc_check(C.byref(K.cb), _p(oi), _p(co), _p(npl), _p(pl), *[_p(a) for a in ps],
-                    _p(clr))
+                    _p(kk), _p(clr))
     return clr
 
 
@@ -212,11 +222,13 @@ def generate(b, seed: int, margin: float = 0.005, retries: int = 10, default_nca
     n, n_obj, n_sph = K.cb.n_scenes, len(K.sph_off) - 1, K.tmpl.shape[0]
     out = dict(status=np.zeros(n, np.int8), n_placed=np.zeros(n, np.int32),
                rec_attempt=np.zeros(n_obj, np.int32), rec_idx=np.zeros(n_obj, np.int32),
-               rec_pose=np.zeros((n_obj, 4), np.float64), rec_banded=np.zeros(n_obj, np.int8),
+               rec_pose=np.zeros((n_obj, 4), np.float64), rec_stable=np.zeros(n_obj, np.int32),
+               rec_banded=np.zeros(n_obj, np.int8),
                rec_clear=np.zeros(n_obj, np.float64),
                placed=np.full((n_sph, 4), np.nan, np.float64), n_cand=np.zeros(n, np.int64))
     go = _GenOut(*[_p(out[k]) for k in ("status", "n_placed", "rec_attempt", "rec_idx",
-                                         "rec_pose", "rec_banded", "rec_clear", "placed",
+                                         "rec_pose", "rec_stable", "rec_banded", "rec_clear",
+                                         "placed",
                                          "n_cand")])
     ga = _GenArgs(int(seed), float(margin), int(retries), int(default_ncand), float(band),
                   int(max_steps), int(bool(early_exit)), float(band_region))

@@ -89,7 +89,12 @@ def generate(b, seed: int, margin=0.005, retries=10, scene_id=None):
             tmpl = np.asarray(b.tmpl[b.sph_off[o]:b.sph_off[o + 1]], np.float64)
             sup = np.asarray(b.sup[b.obj_sup[o]], np.float64)
             C = int(b.obj_ncand[o])
-            lift = float(np.max(tmpl[:, 3] - tmpl[:, 2]))
+            # stable poses: the template turned into each row's resting frame
+            rows = None
+            if getattr(b, "obj_pose_off", None) is not None:
+                r0, r1 = int(b.obj_pose_off[o]), int(b.obj_pose_off[o + 1])
+                if r1 > r0:
+                    rows = np.asarray(b.stable[r0:r1], np.float64)
             pick = None
             for a in range(retries + 1):
                 ctr = np.stack([np.arange(C), np.full(C, a), np.full(C, step), np.full(C, sid)], 1)
@@ -98,14 +103,21 @@ def generate(b, seed: int, margin=0.005, retries=10, scene_id=None):
                 xs = (sup[12] - sup[14]) * (2 * u[:, 0] - 1)
                 ys = (sup[13] - sup[14]) * (2 * u[:, 1] - 1)
                 yaws = 2 * math.pi * u[:, 2]
-                ok = np.array([clearance(world_spheres(tmpl, sup, (xs[i], ys[i], sup[15] + lift,
-                                                                     yaws[i])), boxes, placed)
+                if rows is None:
+                    rest = [tmpl] * C
+                else:
+                    ks = np.minimum(np.searchsorted(rows[:, 9], u[:, 3], side="left"), len(rows) - 1)
+                    rest = [np.concatenate([tmpl[:, :3] @ rows[k, :9].reshape(3, 3).T, tmpl[:, 3:]], 1)
+                            for k in ks]
+                lifts = [float(np.max(t[:, 3] - t[:, 2])) for t in rest]
+                ok = np.array([clearance(world_spheres(rest[i], sup, (xs[i], ys[i], sup[15] + lifts[i],
+                                                                        yaws[i])), boxes, placed)
                                >= margin for i in range(C)])
                 if ok.any():
                     i = int(np.argmax(ok))
                     pick = (a, i)
                     placed = np.concatenate(
-                        [placed, world_spheres(tmpl, sup, (xs[i], ys[i], sup[15] + lift, yaws[i]))])
+                        [placed, world_spheres(rest[i], sup, (xs[i], ys[i], sup[15] + lifts[i], yaws[i]))])
                     break
             if pick is None:
                 status = 2

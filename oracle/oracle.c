@@ -12,7 +12,9 @@
  *   - Candidate positions are 2-D points sampled on the support polygon plus a
  *     z offset (Sec. III "Position sampling"), sampled in the canonical support
  *     frame and moved by the support's world pose (Sec. IV-C, last paragraph).
- *   - Orientation: random rotation about z (Sec. III "Main algorithm").
+ *   - Orientation: random rotation about z, or a stable pose of the object
+ *     drawn from its table (weights) followed by the random rotation about z
+ *     (Sec. III "Main algorithm": pre-defined rules or stable poses).
  *   - Batched form: N independent scenes, one pose per (scene, object)
  *     (Sec. IV-B); retries only for the scenes that failed (Sec. IV-D).
  *   - 10 retries per object; a scene whose object exhausts them is invalid
@@ -92,6 +94,9 @@ typedef struct {
     const double  *obj_reach; /* [n_obj] approach angle of the reachability check, < 0 none */
     const uint8_t *reach_map; /* 4-D map, 1 = reachable (see reachable())             */
     const double  *reach_geom;/* lo[4], h[4], dims[4] of the map axes (z*, theta, x*, y*) */
+    const int32_t *obj_pose_off; /* [n_obj+1] stable-pose rows of an object (NULL: none) */
+    const double  *stable;    /* [n_rows][12] R[9] (object frame -> resting frame),
+                                 cumulative weight (last row of an object 1), 2 unused */
 } orc_batch;
 
 typedef struct {
@@ -108,18 +113,45 @@ typedef struct {
                                marks the decision as banded (FP32 may decide it either way) */
 } orc_gen_args;
 
-/* Pose of a candidate in its support frame: position (x,y,z), yaw about z. */
-typedef struct { double x, y, z, yaw; } orc_pose;
+/* Pose of a candidate in its support frame: position (x,y,z), yaw about z,
+ * and the stable-pose row k applied before the yaw (-1: none).              */
+typedef struct { double x, y, z, yaw; int k; } orc_pose;
 
-static double zrest_of(const orc_batch *b, int o)
+/* Template sphere c (object frame) turned into the resting frame of stable
+ * pose row k (unchanged for k < 0): R_k c.                                   */
+static void rest_point(const orc_batch *b, int k, const double *c, double out[3])
 {
-    /* lowest point of the sphere set in the object frame, as a lift */
+    if (k < 0) { out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; return; }
+    const double *R = b->stable + 12 * k;
+    for (int r = 0; r < 3; ++r) out[r] = R[3 * r] * c[0] + R[3 * r + 1] * c[1] + R[3 * r + 2] * c[2];
+}
+
+/* Lift that rests the lowest point of the sphere set on the support plane:
+ * max over spheres of (r - z), z in the resting frame of row k.             */
+static double zrest_of(const orc_batch *b, int o, int k)
+{
     double lift = -INFINITY;
-    for (int k = b->sph_off[o]; k < b->sph_off[o + 1]; ++k) {
-        double v = b->tmpl[4 * k + 3] - b->tmpl[4 * k + 2];
+    for (int m = b->sph_off[o]; m < b->sph_off[o + 1]; ++m) {
+        double q[3];
+        rest_point(b, k, b->tmpl + 4 * m, q);
+        double v = b->tmpl[4 * m + 3] - q[2];
         if (v > lift) lift = v;
     }
     return lift;
+}
+
+/* Stable pose of a candidate from its fourth Philox word: the first row of
+ * the object's table whose cumulative weight reaches u = u01(w3), i.e. row
+ * r0 + m with probability cum_m - cum_{m-1}; -1 when the object has none. */
+static int stable_row(const orc_batch *b, int o, uint32_t w3)
+{
+    if (!b->obj_pose_off) return -1;
+    int r0 = b->obj_pose_off[o], r1 = b->obj_pose_off[o + 1];
+    if (r1 <= r0) return -1;
+    double u = orc_u01(w3);
+    for (int r = r0; r < r1 - 1; ++r)
+        if (u <= b->stable[12 * r + 9]) return r;
+    return r1 - 1;
 }
 
 /* ratio_on_support (Sec. IV-F): the support is eroded by ratio x half the
@@ -162,7 +194,8 @@ static orc_pose sample_pose(const orc_batch *b, uint64_t seed, int s, int step, 
     p.x = ax * (2.0 * orc_u01(w[0]) - 1.0);
     p.y = ay * (2.0 * orc_u01(w[1]) - 1.0);
     p.yaw = 2.0 * M_PI * orc_u01(w[2]);
-    p.z = u[15] + zrest_of(b, o);
+    p.k = stable_row(b, o, w[3]);
+    p.z = u[15] + zrest_of(b, o, p.k);
     return p;
 }
 
@@ -250,28 +283,26 @@ yaw:
     return r;
 }
 
-/* World position of an object-frame point c under pose p (as world_sphere). */
+/* World position of an object-frame point c under pose p on support u:
+ *   world = R_u * (Rz(yaw) * R_k * c + (x,y,z)) + t_u   (R_k = I without a
+ * stable pose)                                                              */
 static void world_point(const orc_batch *b, int o, const double c[4], orc_pose p, double out[4])
 {
     const double *u = b->sup + 16 * b->obj_sup[o];
+    double q[3];
+    rest_point(b, p.k, c, q);
     double cs = cos(p.yaw), sn = sin(p.yaw);
-    double l[3] = {cs * c[0] - sn * c[1] + p.x, sn * c[0] + cs * c[1] + p.y, c[2] + p.z};
+    double l[3] = {cs * q[0] - sn * q[1] + p.x, sn * q[0] + cs * q[1] + p.y, q[2] + p.z};
     for (int r = 0; r < 3; ++r)
         out[r] = u[3 * r + 0] * l[0] + u[3 * r + 1] * l[1] + u[3 * r + 2] * l[2] + u[9 + r];
     out[3] = 0.0;
 }
 
-/* World sphere k of object o at pose p on support u:
- *   world = R_u * (Rz(yaw) * c_k + (x,y,z)) + t_u                             */
+/* World sphere k of object o at pose p (the same transform; radius kept).  */
 static void world_sphere(const orc_batch *b, int o, int k, orc_pose p, double out[4])
 {
-    const double *u = b->sup + 16 * b->obj_sup[o];
-    const double *c = b->tmpl + 4 * k;
-    double cs = cos(p.yaw), sn = sin(p.yaw);
-    double l[3] = {cs * c[0] - sn * c[1] + p.x, sn * c[0] + cs * c[1] + p.y, c[2] + p.z};
-    for (int r = 0; r < 3; ++r)
-        out[r] = u[3 * r + 0] * l[0] + u[3 * r + 1] * l[1] + u[3 * r + 2] * l[2] + u[9 + r];
-    out[3] = c[3];
+    world_point(b, o, b->tmpl + 4 * k, p, out);
+    out[3] = b->tmpl[4 * k + 3];
 }
 
 /* Exact signed distance from point p to an oriented box (R: box->world
@@ -456,7 +487,8 @@ void orc_sample_relation(const double rel[16], const double *anchors, double ax,
 /* obj_idx[s]: object to sample for scene s (-1: none); cand_off: CSR of the
  * candidates of each scene in the output arrays.                            */
 void orc_sample_poses(const orc_batch *b, const int32_t *obj_idx, const int32_t *cand_off,
-                      uint64_t seed, int attempt, double *x, double *y, double *z, double *yaw)
+                      uint64_t seed, int attempt, double *x, double *y, double *z, double *yaw,
+                      int32_t *kk)
 {
     for (int s = 0; s < b->n_scenes; ++s) {
         int o = obj_idx[s];
@@ -466,6 +498,7 @@ void orc_sample_poses(const orc_batch *b, const int32_t *obj_idx, const int32_t 
             orc_pose p = sample_pose(b, seed, s, step, o, attempt, i);
             int t = cand_off[s] + i;
             x[t] = p.x; y[t] = p.y; z[t] = p.z; yaw[t] = p.yaw;
+            if (kk) kk[t] = p.k;
         }
     }
 }
@@ -475,7 +508,7 @@ void orc_sample_poses(const orc_batch *b, const int32_t *obj_idx, const int32_t 
  * whose world spheres are in `placed` (parallel to the template table).     */
 void orc_check(const orc_batch *b, const int32_t *obj_idx, const int32_t *cand_off,
                const int32_t *n_placed, const double *placed, const double *x, const double *y,
-               const double *z, const double *yaw, double *clr)
+               const double *z, const double *yaw, const int32_t *kk, double *clr)
 {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int s = 0; s < b->n_scenes; ++s) {
@@ -486,7 +519,7 @@ void orc_check(const orc_batch *b, const int32_t *obj_idx, const int32_t *cand_o
         int first = b->sph_off[b->obj_off[s]];
         int n_pl = b->sph_off[b->obj_off[s] + n_placed[s]] - first;
         for (int t = cand_off[s]; t < cand_off[s + 1]; ++t) {
-            orc_pose p = {x[t], y[t], z[t], yaw[t]};
+            orc_pose p = {x[t], y[t], z[t], yaw[t], kk ? kk[t] : -1};
             for (int k = 0; k < ns; ++k) world_sphere(b, o, b->sph_off[o] + k, p, sph + 4 * k);
             clr[t] = clearance(b, s, sph, ns, placed + 4 * first, n_pl, -INFINITY);
         }
@@ -500,6 +533,7 @@ typedef struct {
     int32_t *rec_attempt;/* [n_obj] attempt that placed the object (-1 none)    */
     int32_t *rec_idx;    /* [n_obj] chosen candidate index (-1 none)            */
     double  *rec_pose;   /* [n_obj][4] x y z yaw in the support frame           */
+    int32_t *rec_stable; /* [n_obj] stable-pose row of the placement (-1 none)  */
     int8_t  *rec_banded; /* [n_obj] a candidate the decision depended on was banded */
     double  *rec_clear;  /* [n_obj] clearance of the chosen candidate           */
     double  *placed;     /* [n_sph][4] world spheres of placed objects          */
@@ -522,6 +556,7 @@ void orc_generate(const orc_batch *b, const orc_gen_args *g, orc_gen_out *out)
         for (int o = o0; o < o1; ++o) {
             out->rec_attempt[o] = -1; out->rec_idx[o] = -1; out->rec_banded[o] = 0;
             out->rec_clear[o] = NAN;
+            out->rec_stable[o] = -1;
             for (int c = 0; c < 4; ++c) out->rec_pose[4 * o + c] = NAN;
         }
         for (int o = o0; o < o1 && status == 0; ++o) {
@@ -532,7 +567,7 @@ void orc_generate(const orc_batch *b, const orc_gen_args *g, orc_gen_out *out)
             int n_pl = b->sph_off[o] - first;
             int chosen = -1, chosen_att = -1;
             double chosen_clr = NAN;
-            orc_pose chosen_pose = {0, 0, 0, 0};
+            orc_pose chosen_pose = {0, 0, 0, 0, -1};
             int8_t banded = 0;
             /* the object's relation: its anchors' recorded positions (earlier
              * objects of the scene, on the same support) */
@@ -599,6 +634,7 @@ void orc_generate(const orc_batch *b, const orc_gen_args *g, orc_gen_out *out)
             out->rec_pose[4 * o + 1] = chosen_pose.y;
             out->rec_pose[4 * o + 2] = chosen_pose.z;
             out->rec_pose[4 * o + 3] = chosen_pose.yaw;
+            out->rec_stable[o] = chosen_pose.k;
             for (int k = 0; k < ns; ++k)
                 world_sphere(b, o, b->sph_off[o] + k, chosen_pose, out->placed + 4 * (b->sph_off[o] + k));
             ++placed_obj;

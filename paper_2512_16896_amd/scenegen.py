@@ -64,6 +64,9 @@ class SceneBatch:
     obj_reach: Optional[np.ndarray] = None    # float32 [n_obj] approach angle, < 0 no check
     reach_map: Optional[np.ndarray] = None    # uint8 [nz, ntheta, nx, ny], 1 = reachable
     reach_geom: Optional[np.ndarray] = None   # float32 [12] lo[4], h[4], dims[4]
+    # stable poses (None when absent): rows [obj_pose_off[o], obj_pose_off[o+1])
+    obj_pose_off: Optional[np.ndarray] = None  # int32 [n_obj+1]
+    stable: Optional[np.ndarray] = None        # float32 [n_rows,12] R[9], cumulative weight, 0, 0
     name: str = ""
     params: dict = dataclasses.field(default_factory=dict)
 
@@ -556,6 +559,97 @@ def reach_scenes(n_scenes: int = 4096, seed: int = 0, n_obj: int = 8, n_sph: int
         params=dict(n_scenes=n_scenes, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand, seed=seed))
 
 
+def face_down_rotations() -> np.ndarray:
+    """The 6 rotations (object frame -> resting frame) that turn the outward
+    normal of one face of an axis-aligned box (+x, -x, +y, -y, +z, -z, in
+    this order) to -z: the box resting on that face."""
+    def rx(a):
+        c, s = np.cos(a), np.sin(a)
+        return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+
+    def ry(a):
+        c, s = np.cos(a), np.sin(a)
+        return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+    R = np.stack([ry(np.pi / 2), ry(-np.pi / 2), rx(-np.pi / 2), rx(np.pi / 2), rx(np.pi),
+                  np.eye(3)])
+    return np.round(R, 15)
+
+
+def haar_rotations(rng, n: int) -> np.ndarray:
+    """n rotations uniform on SO(3) (normalised Gaussian quaternions)."""
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
+
+
+def stable_rows(R: np.ndarray, weights) -> np.ndarray:
+    """Stable-pose table rows [K,12]: R[9], cumulative weight (last 1), 0, 0."""
+    w = np.asarray(weights, np.float64)
+    cum = np.cumsum(w / w.sum())
+    cum[-1] = 1.0
+    rows = np.zeros((len(w), 12), np.float32)
+    rows[:, :9] = np.asarray(R).reshape(-1, 9)
+    rows[:, 9] = cum
+    return rows
+
+
+def stable_scenes(n_scenes: int = 4096, seed: int = 0, n_obj: int = 12, n_sph: int = 32,
+                  n_cand: int = 256, n_box: int = 6, n_free: int = 12,
+                  side=(0.05, 0.20), rad=(0.01, 0.04)) -> SceneBatch:
+    """Objects with stable poses (Sec. III "Main algorithm": orientations from
+    rules or from stable poses): a 1.6 x 1.0 m support at a random world pose
+    with n_box cuboids; of every three objects one turns about z only, one
+    rests on a face of its sphere set's bounding box (6 rows, weight = the
+    face's area), one takes one of n_free rotations uniform on SO(3) (equal
+    weights), each followed by the random rotation about z."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x57AB]))
+    hx, hy = 0.8, 0.5
+    sup_R, sup_t = _support_poses(rng, n_scenes)
+    sup = _support_rows(sup_R, sup_t, hx, hy, 0.0, 0.0)
+    obj_off = np.arange(n_scenes + 1, dtype=np.int64) * n_obj
+    sph_off, tmpl = _templates(rng, n_scenes * n_obj, n_sph, side, rad)
+    perm = _footprint_order(obj_off, sph_off, tmpl)
+    sph_off, tmpl = _reorder_objects(perm, sph_off, tmpl)
+    box_off, box = _boxes(rng, n_scenes, n_box, hx, hy, 0.5, sup_R, sup_t, half=(0.05, 0.25))
+    n_o = n_scenes * n_obj
+    kind = np.arange(n_o) % 3
+    t = tmpl.astype(np.float64)
+    starts = sph_off[:-1].astype(np.int64)
+    ext = (np.maximum.reduceat(t[:, :3] + t[:, 3:4], starts, axis=0)
+           - np.minimum.reduceat(t[:, :3] - t[:, 3:4], starts, axis=0))
+    counts = np.where(kind == 0, 0, np.where(kind == 1, 6, n_free)).astype(np.int64)
+    pose_off = np.zeros(n_o + 1, np.int64)
+    pose_off[1:] = np.cumsum(counts)
+    rows = np.zeros((int(pose_off[-1]), 12), np.float32)
+    # face rows: weights are the face areas, cumulative per object
+    f = np.nonzero(kind == 1)[0]
+    e = ext[f]
+    area = np.stack([e[:, 1] * e[:, 2]] * 2 + [e[:, 0] * e[:, 2]] * 2 + [e[:, 0] * e[:, 1]] * 2, 1)
+    cum = np.cumsum(area / area.sum(1, keepdims=True), 1)
+    cum[:, -1] = 1.0
+    fr = pose_off[f][:, None] + np.arange(6)
+    rows[fr, :9] = face_down_rotations().reshape(6, 9)
+    rows[fr, 9] = cum
+    # free rows: uniform on SO(3), equal weights
+    g = np.nonzero(kind == 2)[0]
+    gr = (pose_off[g][:, None] + np.arange(n_free)).ravel()
+    rows[gr, :9] = haar_rotations(rng, len(gr)).reshape(-1, 9)
+    cg = np.arange(1, n_free + 1) / n_free
+    cg[-1] = 1.0
+    rows[gr, 9] = np.tile(cg, len(g))
+    return SceneBatch(
+        obj_off=obj_off.astype(np.int32), sph_off=sph_off.astype(np.int32),
+        tmpl=tmpl.astype(np.float32), obj_sup=np.repeat(np.arange(n_scenes), n_obj).astype(np.int32),
+        obj_ncand=np.full(n_o, n_cand, np.int32), sup=sup,
+        box_off=box_off.astype(np.int32), box=box, obj_pose_off=pose_off.astype(np.int32),
+        stable=rows, name=f"stable-{n_scenes}",
+        params=dict(n_scenes=n_scenes, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand, seed=seed))
+
+
 def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
     """The scenes `scenes` of a batch as a batch of their own, plus the
     original scene indices (which the random-number counters must keep)."""
@@ -588,6 +682,12 @@ def subset(b: SceneBatch, scenes) -> tuple[SceneBatch, np.ndarray]:
         out.robot = b.robot[scenes].copy()
         out.obj_reach = b.obj_reach[objs].copy()
         out.reach_map, out.reach_geom = b.reach_map, b.reach_geom
+    if b.obj_pose_off is not None:
+        cnt = (b.obj_pose_off[objs + 1] - b.obj_pose_off[objs]).astype(np.int64)
+        poff = np.zeros(len(objs) + 1, np.int64)
+        poff[1:] = np.cumsum(cnt)
+        out.obj_pose_off = poff.astype(np.int32)
+        out.stable = b.stable[_ranges(b.obj_pose_off[objs], cnt)].copy()
     if b.grid_off is not None:
         grids = _ranges(b.grid_off[scenes], b.grid_off[scenes + 1] - b.grid_off[scenes])
         goff = np.zeros(len(scenes) + 1, np.int64)
