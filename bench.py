@@ -75,6 +75,14 @@ WORKLOADS = {
                        make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                     fromlist=["x"]).reach_scenes(4096, seed=seed),
                        ncand=256, cpu_scenes=0),
+    "stable-4096": dict(desc="4096 tables (1.6x1.0 m, 6 cuboids); 12 objects x 32 spheres, of "
+                             "every three one turning about z only, one resting on a face of its "
+                             "bounding box (6 stable poses weighted by face area), one in one of "
+                             "12 rotations uniform on SO(3); 256 candidates per attempt; margin "
+                             "5 mm; 10 retries",
+                        make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                     fromlist=["x"]).stable_scenes(4096, seed=seed),
+                        ncand=256, cpu_scenes=0),
     "drawers-4096": dict(desc="4096 two-drawer cabinets at random world poses; drawers are "
                               "prismatic joints with travel U[0, 0.35] m drawn per scene by the "
                               "batched forward kinematics, which moves their walls (boxes) and "
@@ -546,6 +554,7 @@ def main():
         out["shelves_65536"] = extra_workload(ctx, "shelves-65536", 5, 1)
         out["drawers_4096"] = drawers_leg(ctx, 20, 3)
         out["relations_4096"] = extra_workload(ctx, "relations-4096", 20, 3)
+        out["stable_4096"] = extra_workload(ctx, "stable-4096", 20, 3)
         out["reach_4096"] = extra_workload(ctx, "reach-4096", 20, 3)
         out["reach_4096"]["reach_query"] = reach_query_leg(ctx)
     print(json.dumps(out), flush=True)

@@ -192,11 +192,38 @@ typedef struct scn_batch {
     const float *robot;
     const float *obj_reach;
     scn_reach_map reach;
+    /* Stable poses (Sec. III "Main algorithm": an orientation from an
+     * object's stable poses), optional (obj_pose_off NULL: none), read by the
+     * place calls and scn_sample_poses:
+     *   obj_pose_off [n_objects+1] rows of object o in `stable` (at most
+     *                SCN_MAX_STABLE per object; an object without rows turns
+     *                about z only)
+     *   stable    [n_rows][12] R[9] (row-major, object frame -> resting
+     *             frame), cumulative weight (increasing; the object's last row
+     *             1), 2 unused.
+     * A candidate of an object with rows takes row r0 + m, the first whose
+     * cumulative weight reaches u3 (the candidate's fourth Philox word as a
+     * unit value); its spheres are R_m c before the turn about z, and z rests
+     * the turned set's lowest point on the support: z = dz + max_k (r_k -
+     * (R_m c_k)_z).  ratio_on_support erodes by the unturned set's extents.
+     *   rec_stable [n_objects] (output, nullable) the row each placed object
+     *             took (-1: none).
+     * The learned-proposal calls refuse batches that have them, and grid
+     * batches do not take them (SCN_E_UNSUPPORTED).                          */
+    const int32_t *obj_pose_off;
+    const float *stable;
+    int32_t *rec_stable;
 } scn_batch;
 
-/* Candidate poses in the support frame, structure of arrays (device). */
+/* Largest number of stable-pose rows of one object. */
+#define SCN_MAX_STABLE 16
+
+/* Candidate poses in the support frame, structure of arrays (device).
+ * stable (nullable): the stable-pose row of each candidate (-1: none);
+ * written by scn_sample_poses for batches with stable poses.             */
 typedef struct {
     float *x, *y, *z, *yaw;
+    int32_t *stable;
 } scn_poses;
 
 typedef struct {
@@ -312,7 +339,8 @@ int scn_sample_poses(scn_ctx *ctx, const scn_batch *b, const int32_t *obj_idx,
  * world spheres in b->placed).  clearance[t] (nullable) = min over the
  * candidate's spheres and all obstacles of (signed distance - radii);
  * +inf without obstacles.  collide[t] (nullable, uint8) = clearance < margin.
- * Every pair is evaluated (no culling, no early exit).                      */
+ * Every pair is evaluated (no culling, no early exit).  Candidates turn
+ * about z only: poses.stable must be NULL (SCN_E_UNSUPPORTED otherwise).    */
 int scn_check_batch(scn_ctx *ctx, const scn_batch *b, const int32_t *obj_idx,
                     const int32_t *cand_off, int32_t total, int32_t max_cand_per_scene,
                     scn_poses poses, float margin, float *clearance, uint8_t *collide,

@@ -98,6 +98,8 @@ int check_batch(const scn_batch* b, bool need_state) {
     if (b->n_boxes > 0 && !b->box) return fail(SCN_E_INVALID_ARG, "box required");
     if (b->grid_off && (!b->grid || !b->grid_src || !b->grid_val_off || !b->grid_val))
         return fail(SCN_E_INVALID_ARG, "grid_off given without grid tables");
+    if (b->obj_pose_off && !b->stable)
+        return fail(SCN_E_INVALID_ARG, "obj_pose_off given without stable");
     if (b->max_spheres_per_object < 0 || b->max_spheres_per_scene < 0 ||
         b->max_objects_per_scene < 0)
         return fail(SCN_E_INVALID_ARG, "negative planning size");
@@ -294,6 +296,8 @@ int scn_check_batch(scn_ctx* c, const scn_batch* b, const int32_t* obj_idx,
         return fail(SCN_E_INVALID_ARG, "obj_idx/cand_off/n_placed/placed required");
     if (total > 0 && (!poses.x || !poses.y || !poses.z || !poses.yaw))
         return fail(SCN_E_INVALID_ARG, "pose arrays required");
+    if (poses.stable)
+        return fail(SCN_E_UNSUPPORTED, "the dense checker takes poses that turn about z only");
     if (!(margin >= 0.f)) return fail(SCN_E_INVALID_ARG, "margin must be >= 0");
     if ((int64_t)max_cand > 65535LL * 128) return fail(SCN_E_UNSUPPORTED, "max_cand too large");
     if (b->max_spheres_per_object > 256)
@@ -342,9 +346,10 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
         return fail(SCN_E_INVALID_ARG, "default_ncand must be > 0 when obj_ncand is NULL");
     const int S = b->max_spheres_per_object;
     if (S > 256) return fail(SCN_E_UNSUPPORTED, "max_spheres_per_object %d > 256", S);
-    if ((b->obj_rel || b->robot) && b->grid_off)
+    if ((b->obj_rel || b->robot || b->obj_pose_off) && b->grid_off)
         return fail(SCN_E_UNSUPPORTED,
-                    "spatial relations or reachability in voxel-grid batches are not supported");
+                    "spatial relations, reachability or stable poses in voxel-grid batches are "
+                    "not supported");
     if (b->obj_rel && !b->rel) return fail(SCN_E_INVALID_ARG, "obj_rel given without rel");
     if (b->robot) {
         if (!b->obj_reach || !b->reach.map)

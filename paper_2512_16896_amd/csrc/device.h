@@ -61,8 +61,10 @@ struct Pose { float x, y, z, c, s, yaw; };
 
 // Candidate i of attempt a for the object at position j of scene s.
 __device__ __forceinline__ Pose sample_pose(uint64_t seed, uint32_t s, uint32_t j, uint32_t a,
-                                            uint32_t i, float ax, float ay, float z) {
+                                            uint32_t i, float ax, float ay, float z,
+                                            uint32_t* w3 = nullptr) {
     U4 w = philox10(U4{i, a, j, s}, (uint32_t)seed, (uint32_t)(seed >> 32));
+    if (w3) *w3 = w.d;   // the fourth word: the stable-pose choice
     Pose p;
     p.x = ax * signed_unit(w.a);
     p.y = ay * signed_unit(w.b);
@@ -71,6 +73,28 @@ __device__ __forceinline__ Pose sample_pose(uint64_t seed, uint32_t s, uint32_t 
     sincospif(2.0f * u2, &p.s, &p.c);
     p.z = z;
     return p;
+}
+
+// Stable pose of a candidate of an object with table rows [r0, r1): the
+// first row whose cumulative weight (row entry 9) reaches u = unit01(w3)
+// (exact comparisons of exact values); -1 without rows.
+__device__ __forceinline__ int stable_pick(const int32_t* __restrict__ pose_off,
+                                           const float* __restrict__ stable, int o, uint32_t w3) {
+    if (!pose_off) return -1;
+    const int r0 = pose_off[o], r1 = pose_off[o + 1];
+    if (r1 <= r0) return -1;
+    const float u = unit01(w3);
+    int r = r0;
+    while (r < r1 - 1 && !(u <= stable[12 * r + 9])) ++r;
+    return r;
+}
+
+// c turned into a stable pose's resting frame: R c (R row-major).
+__device__ __forceinline__ void rest_point(const float* __restrict__ R, float cx, float cy, float cz,
+                                           float& x, float& y, float& z) {
+    x = fmaf(R[0], cx, fmaf(R[1], cy, R[2] * cz));
+    y = fmaf(R[3], cx, fmaf(R[4], cy, R[5] * cz));
+    z = fmaf(R[6], cx, fmaf(R[7], cy, R[8] * cz));
 }
 
 // Object-frame point -> world: R_u (Rz(yaw) c + (x,y,z)) + t_u.

@@ -15,7 +15,8 @@ namespace scn {
 
 // ---------------------------------------------------------------------------
 __global__ void k_reset(int n_scenes, int n_objects, int32_t* __restrict__ n_placed,
-                        int8_t* __restrict__ status, scn_pose_rec* __restrict__ rec) {
+                        int8_t* __restrict__ status, scn_pose_rec* __restrict__ rec,
+                        int32_t* __restrict__ rec_stable) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int stride = gridDim.x * blockDim.x;
     for (int s = tid; s < n_scenes; s += stride) {
@@ -26,6 +27,8 @@ __global__ void k_reset(int n_scenes, int n_objects, int32_t* __restrict__ n_pla
         const float nan = __builtin_nanf("");
         for (int o = tid; o < n_objects; o += stride) rec[o] = scn_pose_rec{nan, nan, nan, nan, -1, -1};
     }
+    if (rec_stable)
+        for (int o = tid; o < n_objects; o += stride) rec_stable[o] = -1;
 }
 
 __global__ void k_fill_i64(int64_t* p, int n, int64_t v) {
@@ -39,7 +42,7 @@ hipError_t launch_reset(const scn_batch& b, hipStream_t st) {
     int blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, st, b.n_scenes, b.n_objects,
-                       b.n_placed, b.status, b.rec);
+                       b.n_placed, b.status, b.rec, b.rec_stable);
     return hipGetLastError();
 }
 
@@ -66,7 +69,8 @@ __global__ __launch_bounds__(256) void k_sample(
     const float* __restrict__ sup, const float* __restrict__ obj_ratio,
     const int32_t* __restrict__ obj_idx, const int32_t* __restrict__ cand_off, uint64_t seed,
     int attempt, float* __restrict__ ox, float* __restrict__ oy, float* __restrict__ oz,
-    float* __restrict__ oyaw) {
+    float* __restrict__ oyaw, const int32_t* __restrict__ pose_off, const float* __restrict__ stable,
+    int32_t* __restrict__ ok) {
     const int s = blockIdx.x;
     const int o = obj_idx[s];
     if (o < obj_off[s] || o >= obj_off[s + 1]) return;   // -1 or not an object of scene s
@@ -86,13 +90,28 @@ __global__ __launch_bounds__(256) void k_sample(
         }
         ero = obj_ratio[o] * 0.5f * fminf(hx - lx, hy - ly);
     }
-    const Pose P = sample_pose(seed, (uint32_t)s, (uint32_t)(o - obj_off[s]), (uint32_t)attempt,
-                               (uint32_t)(t - c0), U.hx - U.inset - ero, U.hy - U.inset - ero,
-                               U.lift + lift);
+    uint32_t w3;
+    Pose P = sample_pose(seed, (uint32_t)s, (uint32_t)(o - obj_off[s]), (uint32_t)attempt,
+                         (uint32_t)(t - c0), U.hx - U.inset - ero, U.hy - U.inset - ero,
+                         U.lift + lift, &w3);
+    // a stable pose: the lift of the turned sphere set
+    const int row = stable_pick(pose_off, stable, o, w3);
+    if (row >= 0) {
+        const float* R = stable + 12 * row;
+        float l = -__builtin_huge_valf();
+        for (int k = sph_off[o]; k < sph_off[o + 1]; ++k) {
+            const float4 c = tmpl[k];
+            float x, y, z;
+            rest_point(R, c.x, c.y, c.z, x, y, z);
+            l = fmaxf(l, c.w - z);
+        }
+        P.z = U.lift + l;
+    }
     ox[t] = P.x;
     oy[t] = P.y;
     oz[t] = P.z;
     oyaw[t] = P.yaw;
+    if (ok) ok[t] = row;
 }
 
 hipError_t launch_sample(const scn_batch& b, const int32_t* obj_idx, const int32_t* cand_off,
@@ -101,7 +120,8 @@ hipError_t launch_sample(const scn_batch& b, const int32_t* obj_idx, const int32
     dim3 grid(b.n_scenes, (max_cand + 255) / 256);
     hipLaunchKernelGGL(k_sample, grid, dim3(256), 0, st, b.obj_off, b.sph_off,
                        (const float4*)b.tmpl, b.obj_sup, b.sup, b.obj_ratio, obj_idx, cand_off,
-                       seed, attempt, out.x, out.y, out.z, out.yaw);
+                       seed, attempt, out.x, out.y, out.z, out.yaw, b.obj_pose_off, b.stable,
+                       out.stable);
     return hipGetLastError();
 }
 

@@ -14,10 +14,11 @@ namespace {
 // spheres only: batches with voxel grids, or more supports than scenes (some
 // scene's objects on several supports), are outside what it computes.
 int check_single_support(const scn_batch* b) {
-    if (b->obj_rel || b->obj_ratio || b->robot)
+    if (b->obj_rel || b->obj_ratio || b->robot || b->obj_pose_off)
         return scn_fail(SCN_E_UNSUPPORTED,
                         "the learned proposal does not support spatial relations, "
-                        "ratio_on_support or reachability (its bins cover the whole support)");
+                        "ratio_on_support, reachability or stable poses (its bins cover the "
+                        "whole support and turns about z)");
     if (b->grid_off)
         return scn_fail(SCN_E_UNSUPPORTED, "the learned proposal does not support voxel-grid batches");
     if (b->n_supports > b->n_scenes)

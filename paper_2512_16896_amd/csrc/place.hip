@@ -47,6 +47,25 @@ struct RelState {
     float edge[8][4];
 };
 
+// Stable poses of the object being placed (kCons instances): its rows'
+// cumulative weights, rotations and the lift that rests each turned sphere
+// set on the support, staged in LDS by the object's setup.
+struct StableTab {
+    int n, r0;
+    float cum[SCN_MAX_STABLE];
+    float lift[SCN_MAX_STABLE];
+    float R[SCN_MAX_STABLE][9];
+};
+
+// The stable-pose row (local index, -1 none) of the Philox word w3.
+__device__ __forceinline__ int stable_row(const StableTab* st, uint32_t w3) {
+    if (!st || st->n <= 0) return -1;
+    const float u = unit01(w3);
+    int m = 0;
+    while (m < st->n - 1 && !(u <= st->cum[m])) ++m;
+    return m;
+}
+
 // Relation sample from the candidate's Philox words: the pose (z = zc) and
 // whether it lies in the relation's region.
 __device__ __forceinline__ Pose relation_pose(const RelState& R, U4 w, float ax, float ay,
@@ -152,10 +171,14 @@ __device__ void relation_setup(RelState& R, const float* __restrict__ row, int j
 // bin (x cell, y cell, yaw cell of the 32 x 16 x 8 grid) with Philox counter
 // (rank, 0x10000, j, s); the entries after them are the uniform attempts, entry
 // prop_k + a C + i being candidate i of attempt a (counter (i, a, j, s)).
+// With a stable-pose table (st), *row receives the candidate's row (fourth
+// Philox word of its uniform counter; -1 without rows) and z adds that row's
+// lift to zc.
 __device__ __forceinline__ Pose entry_pose(int g, int prop_k, const int32_t* __restrict__ bins,
                                            int C, uint64_t seed, uint32_t s, uint32_t j, float ax,
                                            float ay, float zc, int* att, int* idx,
-                                           const RelState* rs = nullptr, bool* inside = nullptr) {
+                                           const RelState* rs = nullptr, bool* inside = nullptr,
+                                           const StableTab* st = nullptr, int* row = nullptr) {
     if (g < prop_k) {
         const int bin = min(max(bins[g], 0), 4095);
         const U4 w = philox10(U4{(uint32_t)g, 0x10000u, j, s}, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -176,13 +199,22 @@ __device__ __forceinline__ Pose entry_pose(int g, int prop_k, const int32_t* __r
     const int a = e / C, i = e - a * C;
     *att = a;
     *idx = i;
+    Pose p;
+    uint32_t w3;
     if (rs) {
         const U4 w = philox10(U4{(uint32_t)i, (uint32_t)a, j, s}, (uint32_t)seed,
                               (uint32_t)(seed >> 32));
-        return relation_pose(*rs, w, ax, ay, zc, inside);
+        p = relation_pose(*rs, w, ax, ay, zc, inside);
+        w3 = w.d;
+    } else {
+        if (inside) *inside = true;
+        p = sample_pose(seed, s, j, (uint32_t)a, (uint32_t)i, ax, ay, zc, &w3);
     }
-    if (inside) *inside = true;
-    return sample_pose(seed, s, j, (uint32_t)a, (uint32_t)i, ax, ay, zc);
+    if (row) {
+        *row = stable_row(st, w3);
+        if (*row >= 0) p.z = zc + st->lift[*row];
+    }
+    return p;
 }
 
 
@@ -510,11 +542,12 @@ __device__ __forceinline__ void object_info(const float4* __restrict__ tmpl,
     const float* __restrict__ rel, const float* __restrict__ obj_ratio, \
     const float* __restrict__ robot, const float* __restrict__ obj_reach, scn_reach_map rmap, \
     int8_t* __restrict__ map_keep, float4* __restrict__ bnd_keep, const float4* __restrict__ info_keep, \
-    float* __restrict__ hmap
+    float* __restrict__ hmap, const int32_t* __restrict__ pose_off, \
+    const float* __restrict__ stable, int32_t* __restrict__ rec_stable
 #define SCN_PLACE_ARGS \
     obj_off, sph_off, tmpl, obj_sup, obj_ncand, sup, box_off, box, placed, n_placed, status, rec, chosen, counters, order, n_order, seed, margin, retries, default_ncand, max_steps, cap_sph, cap_obj, split, split_sph, prop_bins, prop_k, resume, chunk, j_cap, n_active, \
     grid_off, grid, grid_src, grid_val_off, grid_val, obj_rel, rel, obj_ratio, robot, obj_reach, \
-    rmap, map_keep, bnd_keep, info_keep, hmap
+    rmap, map_keep, bnd_keep, info_keep, hmap, pose_off, stable, rec_stable
 
 template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons>
 __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
@@ -533,10 +566,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     int8_t* lmap = reinterpret_cast<int8_t*>(lbox) + kBoxLdsBytes;
     __shared__ int s_best;
     // the pose of the entry each wave found valid (a wave finds at most one
-    // per object): x, y, z, c, s, yaw, attempt, index
-    __shared__ float s_found[16][8];
+    // per object): x, y, z, c, s, yaw, attempt, index, stable-pose row
+    __shared__ float s_found[16][9];
     __shared__ DepthMap s_dm;   // read where used (volatile), not held in registers
     __shared__ RelState s_rel;  // the current object's spatial relation
+    __shared__ StableTab s_stab;  // the current object's stable poses
 
     // with n_order, only the first *n_order entries of `order` are scenes of
     // this launch (a list compacted on the device); the other workgroups leave
@@ -739,9 +773,17 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         const float lift = uniform_f(I3.x);
         const int oflags = uniform_int(__float_as_int(I3.y));
         const bool two = (oflags & 1) != 0;
+        // stable-pose rows of the object (kCons instances)
+        int nstab = 0;
+        if constexpr (kCons) {
+            if (pose_off) nstab = uniform_int(pose_off[o + 1] - pose_off[o]);
+        }
+        // boxes some candidate can reach (the mask assumes the unturned set:
+        // every box for an object with stable poses)
         const unsigned long long box_rel =
-            ((unsigned long long)(unsigned)uniform_int(__float_as_int(I3.w)) << 32) |
-            (unsigned)uniform_int(__float_as_int(I3.z));
+            nstab > 0 ? (nbox_mask == kWave ? ~0ull : (1ull << nbox_mask) - 1ull)
+                      : (((unsigned long long)(unsigned)uniform_int(__float_as_int(I3.w)) << 32) |
+                         (unsigned)uniform_int(__float_as_int(I3.z)));
         const float prm2 = (probe.w + margin) * (probe.w + margin);
         const float prm2b = (probe2.w + margin) * (probe2.w + margin);
 
@@ -763,7 +805,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 ero = ratio * 0.5f * fminf(ex, ey);
             }
         }
-        const float ax = U.hx - U.inset - ero, ay = U.hy - U.inset - ero, zc = U.lift + lift;
+        // z of the object's frame: the support's lift plus the rest lift of
+        // the sphere set (with stable poses, the row's lift is added per
+        // candidate)
+        const float ax = U.hx - U.inset - ero, ay = U.hy - U.inset - ero;
+        const float zc = U.lift + (nstab > 0 ? 0.f : lift);
         // spatial relations and reachability: instances for batches that
         // have them (kCons)
         const RelState* rs = nullptr;
@@ -774,6 +820,49 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 relation_setup(s_rel, rel + 16 * rel_row, j, o0, obj_sup, o, rec, ax, ay);
             if (rel_row >= 0) rs = &s_rel;
             if (robot && obj_reach) reach_theta = obj_reach[o];
+        }
+        // the object's stable poses: rotations, cumulative weights and the
+        // lift of each turned sphere set (wave 0; the barrier before the
+        // entry loop publishes them)
+        const StableTab* st = nullptr;
+        if constexpr (kCons) {
+            if (nstab > SCN_MAX_STABLE) {   // more rows than the table holds
+                if (threadIdx.x == 0) {
+                    atomicOr(counters + kErrorWord, (unsigned long long)kErrCapacity);
+                    if (chosen) chosen[s] = -2;
+                }
+                fin = SCN_SCENE_INVALID;
+                last = -1;
+                break;
+            }
+            if (nstab > 0) {
+                if (wave == 0) {
+                    const int r0 = pose_off[o];
+                    for (int m = 0; m < nstab; ++m) {
+                        const float* R = stable + 12 * (r0 + m);
+                        float l = -__builtin_huge_valf();
+#pragma unroll
+                        for (int q = 0; q < SPL; ++q) {
+                            if (act[q]) {
+                                float x, y, z;
+                                rest_point(R, cx[q], cy[q], cz[q], x, y, z);
+                                l = fmaxf(l, cr[q] - z);
+                            }
+                        }
+                        l = wave_max(l);
+                        if (lane < 9) s_stab.R[m][lane] = R[lane];
+                        if (lane == 0) {
+                            s_stab.lift[m] = l;
+                            s_stab.cum[m] = R[9];
+                        }
+                    }
+                    if (lane == 0) {
+                        s_stab.n = nstab;
+                        s_stab.r0 = r0;
+                    }
+                }
+                st = &s_stab;
+            }
         }
         // planar form: supports and boxes turn about z only; world z of each
         // sphere, of the bounding centre and of the probe is then the same
@@ -879,24 +968,44 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             const bool live = g < g_hi;
             int ga, gi;
             bool inside;
+            int srow = -1;   // the candidate's stable-pose row (local index), -1 none
             const Pose L = entry_pose(live ? g : 0, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
-                                      ay, zc, &ga, &gi, rs, &inside);
+                                      ay, zc, &ga, &gi, rs, &inside, st, st ? &srow : nullptr);
+            // the bounding centre and probes, turned into the candidate's
+            // resting frame when it takes a stable pose
+            float bx = bc[0], by = bc[1], bz = bc[2];
+            float p1x = probe.x, p1y = probe.y, p1z = probe.z;
+            float p2x = probe2.x, p2y = probe2.y, p2z = probe2.z;
+            if constexpr (kCons) {
+                if (srow >= 0) {
+                    const float* R = s_stab.R[srow];
+                    rest_point(R, bc[0], bc[1], bc[2], bx, by, bz);
+                    rest_point(R, probe.x, probe.y, probe.z, p1x, p1y, p1z);
+                    rest_point(R, probe2.x, probe2.y, probe2.z, p2x, p2y, p2z);
+                }
+            }
             float lx, ly, lz;   // world centre of this candidate's bounding sphere
             float qx, qy, qz;   // world centres of its probe spheres
             float ux, uy, uz;
             Planar M{};         // the candidate's planar motion (kYaw)
             if constexpr (kYaw) {
                 M = planar(U, L);
-                planar_xy(M, bc[0], bc[1], lx, ly);
-                planar_xy(M, probe.x, probe.y, qx, qy);
-                planar_xy(M, probe2.x, probe2.y, ux, uy);
-                lz = bz0;
-                qz = pz0;
-                uz = pz02;
+                planar_xy(M, bx, by, lx, ly);
+                planar_xy(M, p1x, p1y, qx, qy);
+                planar_xy(M, p2x, p2y, ux, uy);
+                if (kCons && srow >= 0) {
+                    lz = (bz + L.z) + U.t[2];
+                    qz = (p1z + L.z) + U.t[2];
+                    uz = (p2z + L.z) + U.t[2];
+                } else {
+                    lz = bz0;
+                    qz = pz0;
+                    uz = pz02;
+                }
             } else {
-                to_world(U, L, bc[0], bc[1], bc[2], lx, ly, lz);
-                to_world(U, L, probe.x, probe.y, probe.z, qx, qy, qz);
-                to_world(U, L, probe2.x, probe2.y, probe2.z, ux, uy, uz);
+                to_world(U, L, bx, by, bz, lx, ly, lz);
+                to_world(U, L, p1x, p1y, p1z, qx, qy, qz);
+                to_world(U, L, p2x, p2y, p2z, ux, uy, uz);
             }
             // rejected: a point outside its relation's region, one the robot
             // cannot reach, or a probe that collides
@@ -905,14 +1014,34 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 if (reach_theta >= 0.f && !sure) {
                     const float* rb = robot + 12 * s;
                     float ox, oy, oz, dx, dy, dz;
+                    // the object's x axis: R_m e_x turned by the candidate
+                    // (e_x without a stable pose)
+                    float v0 = 1.f, v1 = 0.f, v2 = 0.f;
+                    if (srow >= 0) {
+                        const float* R = s_stab.R[srow];
+                        v0 = R[0]; v1 = R[3]; v2 = R[6];
+                    }
                     if constexpr (kYaw) {
-                        ox = M.Tx; oy = M.Ty; oz = zc + U.t[2];
-                        dx = M.C; dy = M.S; dz = 0.f;
+                        ox = M.Tx; oy = M.Ty; oz = L.z + U.t[2];
+                        if (srow >= 0) {
+                            dx = fmaf(M.C, v0, -M.S * v1);
+                            dy = fmaf(M.S, v0, M.C * v1);
+                            dz = v2;
+                        } else {
+                            dx = M.C; dy = M.S; dz = 0.f;
+                        }
                     } else {
                         to_world(U, L, 0.f, 0.f, 0.f, ox, oy, oz);
-                        dx = fmaf(U.R[0], L.c, U.R[1] * L.s);
-                        dy = fmaf(U.R[3], L.c, U.R[4] * L.s);
-                        dz = fmaf(U.R[6], L.c, U.R[7] * L.s);
+                        if (srow >= 0) {
+                            const float l0 = fmaf(L.c, v0, -L.s * v1), l1 = fmaf(L.s, v0, L.c * v1);
+                            dx = fmaf(U.R[0], l0, fmaf(U.R[1], l1, U.R[2] * v2));
+                            dy = fmaf(U.R[3], l0, fmaf(U.R[4], l1, U.R[5] * v2));
+                            dz = fmaf(U.R[6], l0, fmaf(U.R[7], l1, U.R[8] * v2));
+                        } else {
+                            dx = fmaf(U.R[0], L.c, U.R[1] * L.s);
+                            dy = fmaf(U.R[3], L.c, U.R[4] * L.s);
+                            dz = fmaf(U.R[6], L.c, U.R[7] * L.s);
+                        }
                     }
                     sure = !reach_ok(rmap.map, rmap, rb, ox, oy, oz, dx, dy, dz, reach_theta);
                 }
@@ -923,12 +1052,12 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             if (kMap && use_map && j > 0) {
                 const DepthMap dmq = map_params(&s_dm);
                 if (!sure)
-                    sure = map_hit(lmap, dmq, fmaf(L.c, probe.x, fmaf(-L.s, probe.y, L.x)),
-                               fmaf(L.s, probe.x, fmaf(L.c, probe.y, L.y)), probe.z + zc,
+                    sure = map_hit(lmap, dmq, fmaf(L.c, p1x, fmaf(-L.s, p1y, L.x)),
+                               fmaf(L.s, p1x, fmaf(L.c, p1y, L.y)), p1z + L.z,
                                probe.w, margin);
                 if (two && !sure)
-                    sure = map_hit(lmap, dmq, fmaf(L.c, probe2.x, fmaf(-L.s, probe2.y, L.x)),
-                                   fmaf(L.s, probe2.x, fmaf(L.c, probe2.y, L.y)), probe2.z + zc,
+                    sure = map_hit(lmap, dmq, fmaf(L.c, p2x, fmaf(-L.s, p2y, L.x)),
+                                   fmaf(L.s, p2x, fmaf(L.c, p2y, L.y)), p2z + L.z,
                                    probe2.w, margin);
                 n_sphc += (two ? 2u : 1u) * __popcll(__ballot(live));
             }
@@ -991,11 +1120,31 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 }
                 Pose P{};
                 Planar Mt{};
+                // the candidate's stable pose: the lanes' template spheres in
+                // its resting frame and its z (the unturned set otherwise)
+                float tx[SPL], ty[SPL], tz[SPL], twz[SPL];
+                float zt = zc;
+#pragma unroll
+                for (int q = 0; q < SPL; ++q) {
+                    tx[q] = cx[q]; ty[q] = cy[q]; tz[q] = cz[q]; twz[q] = wz0[q];
+                }
+                if constexpr (kCons) {
+                    const int mt = st ? uniform_int(__builtin_amdgcn_readlane(srow, t)) : -1;
+                    if (mt >= 0) {
+                        const float* R = s_stab.R[mt];
+                        zt = bcast(L.z, t);
+#pragma unroll
+                        for (int q = 0; q < SPL; ++q) {
+                            rest_point(R, cx[q], cy[q], cz[q], tx[q], ty[q], tz[q]);
+                            twz[q] = (tz[q] + zt) + U.t[2];
+                        }
+                    }
+                }
                 if constexpr (kYaw) {
                     Mt.C = bcast(M.C, t); Mt.S = bcast(M.S, t);
                     Mt.Tx = bcast(M.Tx, t); Mt.Ty = bcast(M.Ty, t);
                 } else {
-                    P.x = bcast(L.x, t); P.y = bcast(L.y, t); P.z = zc;
+                    P.x = bcast(L.x, t); P.y = bcast(L.y, t); P.z = zt;
                     P.c = bcast(L.c, t); P.s = bcast(L.s, t);
                 }
                 Gx = bcast(lx, t); Gy = bcast(ly, t); Gz = bcast(lz, t);
@@ -1022,10 +1171,10 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 for (int q = 0; q < SPL; ++q) {
                     if (q > 0 && q >= nq) break;
                     if constexpr (kYaw) {
-                        planar_xy(Mt, cx[q], cy[q], wx[q], wy[q]);
-                        wz[q] = wz0[q];
+                        planar_xy(Mt, tx[q], ty[q], wx[q], wy[q]);
+                        wz[q] = twz[q];
                     } else {
-                        to_world(U, P, cx[q], cy[q], cz[q], wx[q], wy[q], wz[q]);
+                        to_world(U, P, tx[q], ty[q], tz[q], wx[q], wy[q], wz[q]);
                     }
                 }
                 bool hit = false;
@@ -1092,7 +1241,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                         if constexpr (kYaw) {
                             sx = fmaf(U.R[0], dx, U.R[3] * dy);
                             sy = fmaf(U.R[1], dx, U.R[4] * dy);
-                            sz = cz[q] + zc;
+                            sz = tz[q] + zt;
                         } else {
                             const float dz = wz[q] - U.t[2];
                             sx = fmaf(U.R[0], dx, fmaf(U.R[3], dy, U.R[6] * dz));
@@ -1129,14 +1278,15 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                     // its pose for the commit, drawn again here (once per
                     // wave and object) rather than by every wave after the
                     // barrier or kept live in registers
-                    int fa, fi;
+                    int fa, fi, fr = -1;
                     bool fin_in;
                     const Pose F = entry_pose(gt, pk, pb, C, seed, (uint32_t)s, (uint32_t)j, ax,
-                                              ay, zc, &fa, &fi, rs, &fin_in);
+                                              ay, zc, &fa, &fi, rs, &fin_in, st, st ? &fr : nullptr);
                     if (lane == 0) {
                         float* f = s_found[wave];
                         f[0] = F.x; f[1] = F.y; f[2] = F.z; f[3] = F.c; f[4] = F.s; f[5] = F.yaw;
                         f[6] = __int_as_float(fa); f[7] = __int_as_float(fi);
+                        f[8] = __int_as_float(fr);
                     }
                     t_end = t + 1;
                     stop = true;
@@ -1159,11 +1309,31 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         if (best == INT_MAX) { fin = SCN_SCENE_INVALID; last = -1; break; }
         // the pose the owning wave tested (entries g_lo + w + W n belong to wave w)
         Pose Pw;
-        int fa, fi;
+        int fa, fi, fr;
         {
             const float* f = s_found[(best - g_lo) % W];
             Pw.x = f[0]; Pw.y = f[1]; Pw.z = f[2]; Pw.c = f[3]; Pw.s = f[4]; Pw.yaw = f[5];
-            fa = __float_as_int(f[6]); fi = __float_as_int(f[7]);
+            fa = __float_as_int(f[6]); fi = __float_as_int(f[7]); fr = __float_as_int(f[8]);
+        }
+        // the winner's sphere set and bounding centre in its resting frame
+        float tx[SPL], ty[SPL], tz[SPL], twz[SPL];
+        float tb[3] = {bc[0], bc[1], bc[2]};
+        float tbz = bz0;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            tx[q] = cx[q]; ty[q] = cy[q]; tz[q] = cz[q]; twz[q] = wz0[q];
+        }
+        if constexpr (kCons) {
+            if (fr >= 0) {
+                const float* R = s_stab.R[fr];
+#pragma unroll
+                for (int q = 0; q < SPL; ++q) {
+                    rest_point(R, cx[q], cy[q], cz[q], tx[q], ty[q], tz[q]);
+                    twz[q] = (tz[q] + Pw.z) + U.t[2];
+                }
+                rest_point(R, bc[0], bc[1], bc[2], tb[0], tb[1], tb[2]);
+                tbz = (tb[2] + Pw.z) + U.t[2];
+            }
         }
         if (wave == 0) {
             const Pose P = Pw;
@@ -1173,10 +1343,10 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 if (act[q]) {
                     float px, py, pz;
                     if constexpr (kYaw) {   // the arithmetic the candidate was tested with
-                        planar_xy(Mc, cx[q], cy[q], px, py);
-                        pz = wz0[q];
+                        planar_xy(Mc, tx[q], ty[q], px, py);
+                        pz = twz[q];
                     } else {
-                        to_world(U, P, cx[q], cy[q], cz[q], px, py, pz);
+                        to_world(U, P, tx[q], ty[q], tz[q], px, py, pz);
                     }
                     const int k = lane + kWave * q;
                     placed[sb + k] = make_float4(px, py, pz, cr[q]);
@@ -1198,14 +1368,15 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             if (lane == 0) {
                 float gx, gy, gz;
                 if constexpr (kYaw) {
-                    planar_xy(Mc, bc[0], bc[1], gx, gy);
-                    gz = bz0;
+                    planar_xy(Mc, tb[0], tb[1], gx, gy);
+                    gz = tbz;
                 } else {
-                    to_world(U, P, bc[0], bc[1], bc[2], gx, gy, gz);
+                    to_world(U, P, tb[0], tb[1], tb[2], gx, gy, gz);
                 }
                 lbnd[j] = make_float4(gx, gy, gz, rho);
                 if (bnd_keep) bnd_keep[o] = make_float4(gx, gy, gz, rho);
                 rec[o] = scn_pose_rec{P.x, P.y, P.z, P.yaw, fa, fi};
+                if (rec_stable) rec_stable[o] = fr >= 0 ? s_stab.r0 + fr : -1;
             }
             ++n_done;
         }
@@ -1217,8 +1388,8 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
 #pragma unroll
             for (int q = 0; q < SPL; ++q)
                 if (act[q])
-                    map_insert(lmap, dm, fmaf(Pw.c, cx[q], fmaf(-Pw.s, cy[q], Pw.x)),
-                               fmaf(Pw.s, cx[q], fmaf(Pw.c, cy[q], Pw.y)), cz[q] + Pw.z, cr[q], wave,
+                    map_insert(lmap, dm, fmaf(Pw.c, tx[q], fmaf(-Pw.s, ty[q], Pw.x)),
+                               fmaf(Pw.s, tx[q], fmaf(Pw.c, ty[q], Pw.y)), tz[q] + Pw.z, cr[q], wave,
                                W);
         }
         last = fi;
@@ -1280,8 +1451,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void 
     place_scenes<SPL, kLds, true, kYaw, false>(SCN_PLACE_ARGS);
 }
 
-// Spatial relations and reachability are compiled only into grid-free
-// instances (kCons); a grid batch with either is refused by the launcher.
+// Spatial relations, reachability and stable poses are compiled only into
+// grid-free instances (kCons); a grid batch with any is refused by the
+// launcher.
 template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons>
 static auto place_kernel() {
     if constexpr (kGrids && SPL <= 2) return k_place_g5<SPL, kLds, kYaw>;
@@ -1294,7 +1466,7 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                    const PlacePlan& plan, int cap_sph, int split, int32_t* chosen,
                                    unsigned long long* ctr, hipStream_t st) {
     const bool yaw = b.geometry == SCN_GEOM_YAW;
-    const bool relp = b.obj_rel != nullptr || b.robot != nullptr;
+    const bool relp = b.obj_rel != nullptr || b.robot != nullptr || b.obj_pose_off != nullptr;
     if (relp && b.grid_off) return hipErrorNotSupported;
     auto kern = b.grid_off ? (yaw ? place_kernel<SPL, kLds, true, true, false>()
                                   : place_kernel<SPL, kLds, true, false, false>())
@@ -1318,7 +1490,8 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                        plan.n_active, b.grid_off, b.grid, b.grid_src,
                        b.grid_val_off, b.grid_val, b.obj_rel, b.rel, b.obj_ratio, b.robot,
                        b.obj_reach, b.reach, (int8_t*)plan.map_keep, (float4*)plan.bnd_keep,
-                       (const float4*)plan.info_keep, plan.hmap);
+                       (const float4*)plan.info_keep, plan.hmap, b.obj_pose_off, b.stable,
+                       b.rec_stable);
     return hipGetLastError();
 }
 

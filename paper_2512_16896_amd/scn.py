@@ -51,7 +51,8 @@ class _Batch(C.Structure):
             "obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
             "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
             "placed", "n_placed", "status", "rec", "obj_rel", "rel", "obj_ratio", "robot",
-            "obj_reach")] + [("reach", _ReachMap)]
+            "obj_reach")] + [("reach", _ReachMap)] + \
+        [(n, C.c_void_p) for n in ("obj_pose_off", "stable", "rec_stable")]
 
 
 class _Joints(C.Structure):
@@ -60,7 +61,8 @@ class _Joints(C.Structure):
 
 
 class _Poses(C.Structure):
-    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("yaw", C.c_void_p)]
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("yaw", C.c_void_p),
+                ("stable", C.c_void_p)]
 
 
 class _GenArgs(C.Structure):
@@ -332,6 +334,12 @@ class DeviceBatch:
             self.robot = t(np.asarray(b.robot, np.float32).reshape(-1, 12), torch.float32)
             self.obj_reach = t(b.obj_reach, torch.float32)
             self.reach_map = t(np.asarray(b.reach_map, np.uint8).ravel(), torch.uint8)
+        self.obj_pose_off = self.stable = self.rec_stable = None
+        if getattr(b, "obj_pose_off", None) is not None:
+            self.obj_pose_off = t(b.obj_pose_off, torch.int32)
+            st = np.asarray(b.stable, np.float32).reshape(-1, 12)
+            self.stable = t(st if len(st) else np.zeros((1, 12), np.float32), torch.float32)
+            self.rec_stable = torch.full((max(b.n_objects, 1),), -1, dtype=torch.int32, device=dev)
         n, n_obj, n_sph = b.n_scenes, b.n_objects, b.n_spheres
         self.placed = torch.full((max(n_sph, 1), 4), float("nan"), dtype=torch.float32, device=dev)
         self.n_placed = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
@@ -354,7 +362,7 @@ class DeviceBatch:
         for name in ("obj_off", "sph_off", "tmpl", "obj_sup", "obj_ncand", "sup", "box_off", "box",
                      "grid_off", "grid", "grid_src", "grid_val_off", "grid_val",
                      "placed", "n_placed", "status", "rec", "obj_rel", "rel", "obj_ratio",
-                     "robot", "obj_reach"):
+                     "robot", "obj_reach", "obj_pose_off", "stable", "rec_stable"):
             setattr(c, name, None if getattr(self, name) is None else getattr(self, name).data_ptr())
         if self.reach_map is not None:
             c.reach = reach_map_struct(self.reach_map, b.reach_geom)
@@ -381,13 +389,18 @@ class DeviceBatch:
 
 # ---------------------------------------------------------------------------
 def sample_poses(ctx: Context, db: DeviceBatch, obj_idx: torch.Tensor, cand_off: torch.Tensor,
-                 total: int, max_cand: int, seed: int, attempt: int, stream=None):
+                 total: int, max_cand: int, seed: int, attempt: int, stream=None,
+                 with_stable: bool = False):
+    """scn_sample_poses: (x, y, z, yaw) per candidate, and with with_stable
+    the stable-pose row of each (-1: none)."""
     out = [torch.empty(max(total, 1), dtype=torch.float32, device=obj_idx.device) for _ in range(4)]
-    p = _Poses(*[o.data_ptr() for o in out])
+    k = torch.empty(max(total, 1), dtype=torch.int32, device=obj_idx.device) if with_stable else None
+    p = _Poses(*[o.data_ptr() for o in out], _ptr(k))
     _ok(_lib.scn_sample_poses(ctx.h, C.byref(db.c), _ptr(obj_idx), _ptr(cand_off), int(total),
                               int(max_cand), int(seed) & (2 ** 64 - 1), int(attempt), p,
                               _stream(stream)))
-    return [o[:total] for o in out]
+    res = [o[:total] for o in out]
+    return res + [k[:total]] if with_stable else res
 
 
 def check_batch(ctx: Context, db: DeviceBatch, obj_idx: torch.Tensor, cand_off: torch.Tensor,
@@ -396,7 +409,7 @@ def check_batch(ctx: Context, db: DeviceBatch, obj_idx: torch.Tensor, cand_off: 
     dev = obj_idx.device
     clr = torch.empty(max(total, 1), dtype=torch.float32, device=dev) if want_clearance else None
     col = torch.empty(max(total, 1), dtype=torch.uint8, device=dev) if want_collide else None
-    p = _Poses(*[q.data_ptr() for q in poses])
+    p = _Poses(*[q.data_ptr() for q in poses[:4]], _ptr(poses[4]) if len(poses) > 4 else None)
     _ok(_lib.scn_check_batch(ctx.h, C.byref(db.c), _ptr(obj_idx), _ptr(cand_off), int(total),
                              int(max_cand), p, float(margin), _ptr(clr), _ptr(col),
                              _stream(stream)))
