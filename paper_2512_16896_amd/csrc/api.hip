@@ -386,7 +386,8 @@ static int plan_place(scn_ctx* c, const scn_batch* b, const scn_gen_args* a, int
     // dynamic LDS available to the place kernel: the block limit minus the
     // kernel's own static shared variables
     const long long lds_cap =
-        c->lds_per_block - 1024 - scn::kBoxLdsBytes - (b->grid_off ? 0 : scn::kMapBytes);
+        c->lds_per_block - scn::kPlaceStaticLds - scn::kBoxLdsBytes -
+        (b->grid_off ? 0 : scn::kMapBytes);
     if (16LL * scn::kObjLds * plan->cap_obj + 16LL * 64 > lds_cap)
         return fail(SCN_E_UNSUPPORTED, "%d objects per scene do not fit the LDS", plan->cap_obj);
     static const int kBudgetKB[] = {0, 32, 48, 64, 80, 96};

@@ -77,6 +77,9 @@ constexpr int kMapBytes = 24576;
 constexpr int kObjLds = 5;
 // the place kernel's LDS copy of a scene's first 64 box rows (16 floats each)
 constexpr int kBoxLdsBytes = 64 * 16 * 4;
+// LDS the place kernel's static shared variables may take (reserved beside
+// its dynamic LDS)
+constexpr int kPlaceStaticLds = 2048;
 
 // Where the fused place kernel keeps a scene's placed spheres.
 enum PlaceMode {

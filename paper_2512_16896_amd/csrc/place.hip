@@ -482,6 +482,12 @@ __device__ __forceinline__ unsigned long long reachable_boxes(const ObjConsts& K
     return __ballot(rel);
 }
 
+// the kernel's static shared variables (s_best, s_found, s_dm, s_rel,
+// s_stab) within the reserve the planner leaves beside the dynamic LDS
+static_assert(sizeof(int) + 16 * 9 * sizeof(float) + sizeof(DepthMap) + sizeof(RelState) +
+                  sizeof(StableTab) + 64 <= kPlaceStaticLds,
+              "static LDS of the place kernel exceeds its reserve");
+
 // The 4 constants the place kernel keeps per object to place (written by
 // lane 0 to I[0..3]): bounding centre and radius, the two probes, and the
 // lift, flags (second probe; non-finite template or support) and the mask of
@@ -1376,7 +1382,9 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                 lbnd[j] = make_float4(gx, gy, gz, rho);
                 if (bnd_keep) bnd_keep[o] = make_float4(gx, gy, gz, rho);
                 rec[o] = scn_pose_rec{P.x, P.y, P.z, P.yaw, fa, fi};
-                if (rec_stable) rec_stable[o] = fr >= 0 ? s_stab.r0 + fr : -1;
+                if constexpr (kCons) {
+                    if (rec_stable) rec_stable[o] = fr >= 0 ? s_stab.r0 + fr : -1;
+                }
             }
             ++n_done;
         }
