@@ -125,6 +125,14 @@ def test_train_step_matches_oracle_adamw(dev):
         wb = net.wb[l].float().cpu().numpy()
         np.testing.assert_array_equal(wb, ol.bf16(nw).astype(np.float32))
         np.testing.assert_array_equal(net.wt[l].float().cpu().numpy(), wb.T)
+        # biases: the same step without weight decay
+        nb = net.b[l].cpu().numpy().astype(np.float64)
+        want_b, _, _ = ol.adamw_step(b[l].astype(np.float64), rgb[l], 0, 0, 0, lr, 0.9, 0.999,
+                                     1e-8, 0.0)
+        gb = np.abs(rgb[l])
+        sure_b = gb > 0.1 * np.sqrt(np.mean(gb * gb))
+        assert sure_b.sum() > 0.5 * gb.size
+        assert _rel((nb - b[l])[sure_b], (want_b - b[l])[sure_b]) < 0.02, l
 
 
 def test_init_is_kaiming_uniform(dev):
