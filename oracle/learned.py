@@ -58,17 +58,24 @@ def descriptor(tmpl: np.ndarray) -> np.ndarray:
     return d
 
 
-def _support(b, s):
-    o = int(b.obj_off[s])
-    row = np.asarray(b.sup[int(b.obj_sup[o])], np.float64)
-    return row[:9].reshape(3, 3), row[9:12], row[12], row[13]
+def state_support(b, s: int, n_state: int) -> int:
+    """The support a state's height map covers: that of the scene's next
+    object (object n_state), or of its last one when every object is placed."""
+    o0, o1 = int(b.obj_off[s]), int(b.obj_off[s + 1])
+    o = min(o0 + n_state, o1 - 1) if o1 > o0 else o0
+    return int(b.obj_sup[o])
 
 
-def heightmap(b, placed: np.ndarray, s: int, n_state: int) -> np.ndarray:
-    """Height map [64,64] (metres above the support plane) of scene s with its
-    first n_state objects placed (world spheres in `placed`, parallel to the
-    templates).  Cell (ix, iy) centre (-hx + (ix+1/2) 2hx/64, -hy + ...)."""
-    R, t, hx, hy = _support(b, s)
+def heightmap(b, placed: np.ndarray, s: int, n_state: int, u: int = None) -> np.ndarray:
+    """Height map [64,64] (metres above the support plane) over support u
+    (default: the state's, see state_support) of scene s with its first
+    n_state objects placed (world spheres in `placed`, parallel to the
+    templates): the scene's boxes, and the placed objects that rest on u.
+    Cell (ix, iy) centre (-hx + (ix+1/2) 2hx/64, -hy + ...)."""
+    if u is None:
+        u = state_support(b, s, n_state)
+    row = np.asarray(b.sup[int(u)], np.float64)
+    R, t, hx, hy = row[:9].reshape(3, 3), row[9:12], row[12], row[13]
     ix = np.arange(HMAP)
     cx = -hx + (ix + 0.5) * (2 * hx / HMAP)
     cy = -hy + (ix + 0.5) * (2 * hy / HMAP)
@@ -85,8 +92,9 @@ def heightmap(b, placed: np.ndarray, s: int, n_state: int) -> np.ndarray:
         top = cl[2] + np.abs(Rl[2, :]) @ h
         H = np.where((np.abs(qx) <= h[0]) & (np.abs(qy) <= h[1]), np.maximum(H, top), H)
     o0 = int(b.obj_off[s])
-    k0, k1 = int(b.sph_off[o0]), int(b.sph_off[o0 + n_state])
-    for q in np.asarray(placed[k0:k1], np.float64):
+    on_u = [o for o in range(o0, o0 + n_state) if int(b.obj_sup[o]) == int(u)]
+    rows = [np.asarray(placed[int(b.sph_off[o]):int(b.sph_off[o + 1])], np.float64) for o in on_u]
+    for q in (np.concatenate(rows) if rows else np.zeros((0, 4))):
         p = R.T @ (q[:3] - t)
         d2 = (X - p[0]) ** 2 + (Y - p[1]) ** 2
         inside = d2 < q[3] ** 2
