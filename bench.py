@@ -83,6 +83,18 @@ WORKLOADS = {
                         make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                      fromlist=["x"]).stable_scenes(4096, seed=seed),
                         ncand=256, cpu_scenes=0),
+    "uneven-shelves-65536": dict(desc="learned proposal + uneven batching on dense multi-support "
+                                      "scenes: 65536 shelf units (6 stacked 0.8x0.4 m shelves, "
+                                      "64^3 SDF grids, trilinear); objects U{40..100} per scene "
+                                      "(round-robin over the shelves), spheres U{64..128} per object "
+                                      "(r~U[0.005,0.02] m), candidates U{1024..2048} per attempt; "
+                                      "margin 5 mm; 10 retries; plain autotuned, learned top-64 "
+                                      "ticks; network trained on labels harvested from plain runs "
+                                      "on 3 x 64 other scenes",
+                                 make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
+                                                              fromlist=["x"]).uneven_shelf_scenes(
+                                     65536, seed=seed),
+                                 ncand=2048, cpu_scenes=0, tune=True),
     "drawers-4096": dict(desc="4096 two-drawer cabinets at random world poses; drawers are "
                               "prismatic joints with travel U[0, 0.35] m drawn per scene by the "
                               "batched forward kinematics, which moves their walls (boxes) and "
@@ -485,6 +497,74 @@ def reach_query_leg(ctx, n=1 << 22):
             "hbm_gbs": n * (12 * 4 * 2 + 4 + 1) / (ms * 1e-3) / 1e9}
 
 
+def shelves_learned_leg(ctx, steps=3, warmup=1):
+    """The dense multi-support configuration with the learned proposal and
+    uneven batching combined: the plain leg (autotuned), then labels from
+    plain runs on 3 x 64 other scenes, 2000 training steps, and the learned
+    generation of the same batch (same metric and counters)."""
+    import torch
+    from paper_2512_16896_amd import learned as L
+    from paper_2512_16896_amd import scenegen as sg
+    from paper_2512_16896_amd import scn
+    name = "uneven-shelves-65536"
+    W = WORKLOADS[name]
+    progress(f"building {name}")
+    b = W["make"](0)
+    b.name = name
+    progress(f"timing {name} (plain)")
+    out, db, stream = plain_leg(ctx, b, W, steps, warmup)
+    out["config"] = W["desc"]
+    progress(f"{name}: harvest and training")
+    t0 = time.perf_counter()
+    parts = []
+    for k in range(3):
+        tb = sg.uneven_shelf_scenes(64, seed=100 + k, chunk=64)
+        tdb = scn.DeviceBatch(tb, "cuda:0")
+        scn.generate_scenes(ctx, tdb, scn.GenArgs(seed=500 + k, default_ncand=W["ncand"]))
+        parts.append(L.harvest(ctx, tdb, seed=900 + k, labels_per_state=16))
+        del tdb
+    data = L.merge(parts)
+    del parts
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    net = scn.Network()
+    net.init(ctx, 1)
+    t0 = time.perf_counter()
+    log = L.train(ctx, net, data, steps=2000, batch=256, lr=1e-3, log_every=1000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_labels = int(data.bins.numel())
+    del data
+    gen = lambda step: scn.generate_scenes_learned(
+        ctx, db, scn.GenArgs(seed=1000 + step, default_ncand=W["ncand"]), net, top_k=64)
+    progress(f"timing {name} (learned)")
+    for i in range(warmup):
+        gen(-1 - i)
+    torch.cuda.synchronize()
+    ctx.reset_counters()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        gen(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cnt = ctx.read_counters()
+    _, rec = db.records()
+    prop = rec[:, 0] == -2
+    placed = rec[:, 1] >= 0
+    rate = cnt["valid_scenes"] / wall
+    out["learned"] = {
+        "value": rate, "unit": "valid scenes/s", "ms_per_step": 1e3 * wall / steps,
+        "valid_fraction": cnt["valid_scenes"] / (b.n_scenes * steps),
+        "candidate_checks_per_s": cnt["candidates"] / wall, "vs_plain": rate / out["value"],
+        "placed_by_proposal": float(prop.sum() / max(placed.sum(), 1)),
+        "rank0_accepted": float((prop & (rec[:, 1] == 0)).sum() / max(placed.sum(), 1)),
+        "training": {"labels": n_labels, "harvest_s": t_harvest, "steps": 2000, "batch": 256,
+                     "train_s": t_train, "loss_first": log[0][1], "loss_last": log[-1][1]}}
+    del db
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -552,6 +632,7 @@ def main():
         out["uneven_16384"] = extra_workload(ctx, "uneven-16384", 10, 2,
                                              dense_scenes=0 if args.no_dense else 512)
         out["shelves_65536"] = extra_workload(ctx, "shelves-65536", 5, 1)
+        out["uneven_shelves_65536"] = shelves_learned_leg(ctx)
         out["drawers_4096"] = drawers_leg(ctx, 20, 3)
         out["relations_4096"] = extra_workload(ctx, "relations-4096", 20, 3)
         out["stable_4096"] = extra_workload(ctx, "stable-4096", 20, 3)

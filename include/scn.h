@@ -317,8 +317,9 @@ int scn_set_workspace(scn_ctx *ctx, void *ptr, size_t bytes);
 int scn_reset_counters(scn_ctx *ctx, scn_stream stream);
 /* Synchronize `stream` and copy the counters to *out (host).  Returns
  * SCN_E_CAPACITY if bit 0 of the device error word is set, SCN_E_INVALID_ARG
- * if bit 1 is (a scene broke the declared SCN_GEOM_YAW geometry) or bit 3 (a
- * joint or link index out of range in scn_forward_kinematics),
+ * if bit 1 is (a scene broke the declared SCN_GEOM_YAW geometry), bit 3 (a
+ * joint or link index out of range in scn_forward_kinematics) or bit 4 (the
+ * learned generation found a support shared by two scenes),
  * SCN_E_NONFINITE if bit 2 is (non-finite input); *out is filled either way. */
 int scn_read_counters(scn_ctx *ctx, scn_counters *out, scn_stream stream);
 
@@ -542,18 +543,21 @@ int scn_mlp_train_step(scn_ctx *ctx, scn_mlp *net, const uint16_t *x, int32_t M,
  * footprint radius; zeros), lengths in decimetres.                          */
 int scn_descriptors(scn_ctx *ctx, const scn_batch *b, float *desc, scn_stream stream);
 
-/* hmap[s][64][64] (FP32, metres above the support plane of the scene's first
- * object): the state where scene s has its first n_state[s] objects placed
- * (n_state NULL: b->n_placed).  Cell (ix, iy) is centred at
+/* hmap[u][64][64] (FP32, metres above support u's plane), one per support
+ * of the batch, for the state where each scene s has its first n_state[s]
+ * objects placed (n_state NULL: b->n_placed).  Cell (ix, iy) is centred at
  * (-hx + (ix+1/2) 2hx/64, -hy + (iy+1/2) 2hy/64) in the support frame; the value
- * is the highest box top or placed-sphere surface above that point, or 0.   */
+ * is the highest top above that point of the boxes of the support's scene and
+ * of the placed spheres of the objects resting on u, or 0.  Each support
+ * belongs to one scene (the objects on it are that scene's); supports no
+ * object rests on are left untouched.                                      */
 int scn_heightmaps(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state, float *hmap,
                    scn_stream stream);
 
-/* x[s][SCN_FEATURES] (BF16) = [10 * hmap[s], desc[obj_idx[s]]]; zeros for
- * obj_idx[s] < 0.                                                            */
-int scn_features(scn_ctx *ctx, int32_t n, const float *hmap, const float *desc,
-                 const int32_t *obj_idx, uint16_t *x, scn_stream stream);
+/* x[r][SCN_FEATURES] (BF16) = [10 * hmap[b->obj_sup[o]], desc[o]] for object
+ * o = obj_idx[r] (the map of its own support); zeros for obj_idx[r] < 0.    */
+int scn_features(scn_ctx *ctx, const scn_batch *b, int32_t n, const float *hmap,
+                 const float *desc, const int32_t *obj_idx, uint16_t *x, scn_stream stream);
 
 /* bins[m][k]: the k best pose bins of logits[m][SCN_BINS] in rank order
  * (logit descending, ties to the lower bin); rows with active[m] < 0 are left
@@ -565,8 +569,9 @@ int scn_proposal_topk(scn_ctx *ctx, const float *logits, int32_t M, int32_t k,
  * for each scene s in the state with its first n_state[s] objects placed
  * (n_state NULL: b->n_placed), L uniform candidates of the next object
  * (counter (i, 0x20000 | round, n_state[s], s)); bins[s][i] = the candidate's
- * pose bin, accept[s][i] = 1 if its clearance >= margin else 0.  Scenes with
- * no next object get bins -1.                                                */
+ * pose bin, accept[s][i] = 1 if its clearance (boxes, voxel grids and the
+ * state's placed spheres) >= margin else 0.  Scenes with no next object get
+ * bins -1.                                                                   */
 int scn_harvest_labels(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state, int32_t L,
                        uint64_t seed, int32_t round, float margin, int32_t *bins,
                        float *accept, scn_stream stream);
@@ -590,7 +595,10 @@ int scn_harvest_labels(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state,
  * shapes the first ticks' new-object launches, args->wide_schedule (0: 4
  * waves) the rest; neither is the context's tuned plain schedule.  The
  * workspace also keeps each scene's depth map, each placed object's bounding
- * sphere and each object's constants across the ticks.                    */
+ * sphere and each object's constants across the ticks.  A state's height map
+ * is that of its next object's support (multi-support and voxel-grid batches
+ * are taken; a support shared by two scenes sets an error that the next
+ * scn_read_counters reports as SCN_E_INVALID_ARG).                          */
 int scn_generate_scenes_learned(scn_ctx *ctx, scn_batch *b, const scn_gen_args *args,
                                 const scn_mlp *net, int32_t top_k, scn_stream stream);
 

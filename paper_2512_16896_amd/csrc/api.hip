@@ -264,6 +264,10 @@ int scn_read_counters(scn_ctx* c, scn_counters* out, scn_stream stream) {
         return fail(SCN_E_INVALID_ARG,
                     "a joint's parent is not an earlier joint of its scene, or a row's link index "
                     "is out of range (those links and rows were not computed)");
+    if (out->error_word & scn::kErrSharedSupport)
+        return fail(SCN_E_INVALID_ARG,
+                    "the learned generation found objects of two scenes on one support (its "
+                    "height maps are per support)");
     if (out->error_word & scn::kErrNonFinite)
         return fail(SCN_E_NONFINITE,
                     "non-finite input: the candidates tested against it collided (%lld counted)",

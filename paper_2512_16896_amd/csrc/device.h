@@ -305,8 +305,9 @@ __device__ __forceinline__ float uniform_f(float v) {
 }
 
 // ---------------------------------------------------------------------------
-// Height map of scene s over its first object's support (the learned
-// proposal's state feature): cell (ix, iy), ix along x in [0,64), iy along y,
+// Height map of a support (the learned proposal's state feature: one per
+// support, over the boxes of the support's scene and the placed objects that
+// rest on it): cell (ix, iy), ix along x in [0,64), iy along y,
 // centre (-hx + (ix + 1/2) 2hx/64, -hy + ...); value = max(0, box tops, sphere
 // tops) above the support plane, metres.  A box covers a cell when the cell
 // centre at the box centre's height lies in the box's x/y extent (box frame);
@@ -316,12 +317,9 @@ __device__ __forceinline__ float uniform_f(float v) {
 struct SupportFrame {
     float R[9], t[3], hx, hy;
 };
-__device__ __forceinline__ SupportFrame scene_support(const int32_t* __restrict__ obj_off,
-                                                      const int32_t* __restrict__ obj_sup,
-                                                      const float* __restrict__ sup, int s) {
+__device__ __forceinline__ SupportFrame support_frame(const float* __restrict__ sup, int u) {
     SupportFrame F;
-    const int o = obj_off[s] < obj_off[s + 1] ? obj_off[s] : -1;
-    const float* p = sup + 16 * (o >= 0 ? obj_sup[o] : 0);
+    const float* p = sup + 16 * (size_t)u;
     for (int i = 0; i < 9; ++i) F.R[i] = p[i];
     F.t[0] = p[9]; F.t[1] = p[10]; F.t[2] = p[11];
     F.hx = p[12]; F.hy = p[13];

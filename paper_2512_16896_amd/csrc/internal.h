@@ -67,7 +67,13 @@ enum CounterSlot {
     kValidScenes = 10, kInvalidScenes = 11, kSphCulls = 12, kNonFinite = 13, kCheckRefined = 14,
     kNumCounters = 16
 };
-enum ErrorBits { kErrCapacity = 1, kErrGeometry = 2, kErrNonFinite = 4, kErrBadJoint = 8 };
+enum ErrorBits {
+    kErrCapacity = 1,
+    kErrGeometry = 2,
+    kErrNonFinite = 4,
+    kErrBadJoint = 8,
+    kErrSharedSupport = 16   // the learned path: objects of two scenes on one support
+};
 
 // Bytes of dynamic LDS the place kernel adds for a scene's depth map (batches
 // without grids).
@@ -126,11 +132,13 @@ hipError_t launch_hmap_boxes(const scn_batch& b, float* hmap, hipStream_t st);
 hipError_t launch_hmap_raise(const scn_batch& b, const int32_t* obj_idx, const int32_t* n_state,
                              float* hmap, hipStream_t st);
 hipError_t launch_features(int n, const float* hmap, const float* desc, const int32_t* obj_idx,
-                           int ld, void* x, hipStream_t st, const int32_t* rows = nullptr,
+                           const int32_t* obj_sup, int ld, void* x, hipStream_t st,
                            const int32_t* m_dev = nullptr);
 hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active, int32_t* bins,
                        hipStream_t st, const int32_t* rows = nullptr,
                        const int32_t* m_dev = nullptr);
+hipError_t launch_support_scene(const scn_batch& b, int32_t* sup_scene, int64_t* counters,
+                                hipStream_t st);
 hipError_t launch_tick_plan(const scn_batch& b, const int32_t* resume, int j_cap, int32_t* list,
                             int32_t* obj_idx, int32_t* count, hipStream_t st);
 hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,

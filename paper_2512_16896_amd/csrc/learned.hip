@@ -102,67 +102,81 @@ hipError_t launch_descriptor(const scn_batch& b, float* desc, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Height map of scene s over its first object's support: cell (ix, iy), ix
-// along x in [0,64), iy along y, centre (-hx + (ix + 1/2) 2hx/64, -hy + ...);
-// value = max(0, box tops, sphere tops) above the support plane, metres.
-// A box covers a cell when the cell centre at the box centre's height lies in
-// the box's x/y extent (box frame); its top is the box's highest point.
-// A sphere (support-frame centre p, radius r) covers a cell when the cell
-// centre is within r of p in x/y; its top there is p_z + sqrt(r^2 - d^2).
+// Height maps, one per support (64 x 64 floats at hmap + 4096 u): cell (ix,
+// iy), ix along x in [0,64), iy along y, centre (-hx + (ix + 1/2) 2hx/64,
+// -hy + ...); value = max(0, box tops, sphere tops) above the support plane,
+// metres.  The boxes are those of the support's scene; the spheres those of
+// the scene's placed objects that rest on the support.  A box covers a cell
+// when the cell centre at the box centre's height lies in the box's x/y extent
+// (box frame); its top is the box's highest point.  A sphere (support-frame
+// centre p, radius r) covers a cell when the cell centre is within r of p in
+// x/y; its top there is p_z + sqrt(r^2 - d^2).
+//
+// The box part: one workgroup per scene writes the map of every support its
+// objects rest on (each once: at the first object on it); supports without
+// objects are not written.  A support belongs to one scene.
 __global__ __launch_bounds__(256) void k_hmap_boxes(
     int n, const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
     const float* __restrict__ sup, const int32_t* __restrict__ box_off,
     const float* __restrict__ box, float* __restrict__ hmap) {
     const int s = blockIdx.x;
     if (s >= n) return;
-    const SupportFrame F = scene_support(obj_off, obj_sup, sup, s);
+    const int o0 = obj_off[s], o1 = obj_off[s + 1];
     const int b0 = box_off[s], b1 = box_off[s + 1];
-    for (int cell = threadIdx.x; cell < 4096; cell += blockDim.x) {
-        const int ix = cell >> 6, iy = cell & 63;
-        const float cx = -F.hx + (ix + 0.5f) * (2.f * F.hx / 64.f);
-        const float cy = -F.hy + (iy + 0.5f) * (2.f * F.hy / 64.f);
-        float h = 0.f;
-        for (int b = b0; b < b1; ++b) {
-            const float* B = box + 16 * b;
-            // box centre and axes in the support frame
-            float bcx, bcy, bcz;
-            to_support(F, B[9], B[10], B[11], bcx, bcy, bcz);
-            float ax[3][3];   // ax[a] = support-frame direction of box axis a
-            for (int a = 0; a < 3; ++a) {
-                float ux, uy, uz;
-                ux = F.R[0] * B[a] + F.R[3] * B[3 + a] + F.R[6] * B[6 + a];
-                uy = F.R[1] * B[a] + F.R[4] * B[3 + a] + F.R[7] * B[6 + a];
-                uz = F.R[2] * B[a] + F.R[5] * B[3 + a] + F.R[8] * B[6 + a];
-                ax[a][0] = ux; ax[a][1] = uy; ax[a][2] = uz;
+    for (int o = o0; o < o1; ++o) {
+        const int u = obj_sup[o];
+        bool seen = false;
+        for (int e = o0; e < o && !seen; ++e) seen = obj_sup[e] == u;
+        if (seen) continue;   // uniform: every thread reads the same entries
+        const SupportFrame F = support_frame(sup, u);
+        for (int cell = threadIdx.x; cell < 4096; cell += blockDim.x) {
+            const int ix = cell >> 6, iy = cell & 63;
+            const float cx = -F.hx + (ix + 0.5f) * (2.f * F.hx / 64.f);
+            const float cy = -F.hy + (iy + 0.5f) * (2.f * F.hy / 64.f);
+            float h = 0.f;
+            for (int b = b0; b < b1; ++b) {
+                const float* B = box + 16 * b;
+                // box centre and axes in the support frame
+                float bcx, bcy, bcz;
+                to_support(F, B[9], B[10], B[11], bcx, bcy, bcz);
+                float ax[3][3];   // ax[a] = support-frame direction of box axis a
+                for (int a = 0; a < 3; ++a) {
+                    float ux, uy, uz;
+                    ux = F.R[0] * B[a] + F.R[3] * B[3 + a] + F.R[6] * B[6 + a];
+                    uy = F.R[1] * B[a] + F.R[4] * B[3 + a] + F.R[7] * B[6 + a];
+                    uz = F.R[2] * B[a] + F.R[5] * B[3 + a] + F.R[8] * B[6 + a];
+                    ax[a][0] = ux; ax[a][1] = uy; ax[a][2] = uz;
+                }
+                const float dx = cx - bcx, dy = cy - bcy;   // at the centre's height
+                const float qx = ax[0][0] * dx + ax[0][1] * dy;
+                const float qy = ax[1][0] * dx + ax[1][1] * dy;
+                if (fabsf(qx) <= B[12] && fabsf(qy) <= B[13]) {
+                    const float topz = bcz + fabsf(ax[0][2]) * B[12] + fabsf(ax[1][2]) * B[13] +
+                                       fabsf(ax[2][2]) * B[14];
+                    h = fmaxf(h, topz);
+                }
             }
-            const float dx = cx - bcx, dy = cy - bcy;   // at the centre's height
-            const float qx = ax[0][0] * dx + ax[0][1] * dy;
-            const float qy = ax[1][0] * dx + ax[1][1] * dy;
-            if (fabsf(qx) <= B[12] && fabsf(qy) <= B[13]) {
-                const float topz = bcz + fabsf(ax[0][2]) * B[12] + fabsf(ax[1][2]) * B[13] +
-                                   fabsf(ax[2][2]) * B[14];
-                h = fmaxf(h, topz);
-            }
+            hmap[(size_t)u * 4096 + cell] = h;
         }
-        hmap[(size_t)s * 4096 + cell] = h;
     }
 }
 
-// Raise scene s's height map by the placed spheres k0 .. k1-1 (world
-// frame).  One wave, one sphere per lane at a time; monotone max through
+// Raise the map of object o's support by its placed spheres (world frame,
+// k0 .. k1-1).  One wave, one sphere per lane at a time; monotone max through
 // integer atomics on non-negative floats.
-__device__ void raise_scene(int s, int k0, int k1, const int32_t* __restrict__ obj_off,
-                            const int32_t* __restrict__ obj_sup, const float* __restrict__ sup,
-                            const float4* __restrict__ placed, float* __restrict__ hmap) {
-    const SupportFrame F = scene_support(obj_off, obj_sup, sup, s);
+__device__ void raise_object(int o, int k0, int k1, const int32_t* __restrict__ obj_sup,
+                             const float* __restrict__ sup, const float4* __restrict__ placed,
+                             float* __restrict__ hmap) {
+    const int u = obj_sup[o];
+    const SupportFrame F = support_frame(sup, u);
     for (int k = k0 + threadIdx.x; k < k1; k += kWave) {
         const float4 q = placed[k];
-        hmap_raise_sphere(F, hmap + (size_t)s * 4096, q.x, q.y, q.z, q.w);
+        hmap_raise_sphere(F, hmap + (size_t)u * 4096, q.x, q.y, q.z, q.w);
     }
 }
 
-// Raise the height map of each scene by its object obj_idx[s] (-1: none), or
-// by its first n_state[s] objects, whose world spheres are in placed.
+// Raise the height maps by each scene's object obj_idx[s] (-1: none), or by
+// its first n_state[s] objects, whose world spheres are in placed.
 __global__ __launch_bounds__(64) void k_hmap_raise(
     int n, const int32_t* __restrict__ obj_off, const int32_t* __restrict__ obj_sup,
     const float* __restrict__ sup, const int32_t* __restrict__ sph_off,
@@ -170,18 +184,41 @@ __global__ __launch_bounds__(64) void k_hmap_raise(
     const int32_t* __restrict__ n_state, float* __restrict__ hmap) {
     const int s = blockIdx.x;
     if (s >= n) return;
-    int k0, k1;
     if (n_state) {
         const int m = min(max(n_state[s], 0), obj_off[s + 1] - obj_off[s]);
-        k0 = sph_off[obj_off[s]];
-        k1 = sph_off[obj_off[s] + m];
+        for (int o = obj_off[s]; o < obj_off[s] + m; ++o)
+            raise_object(o, sph_off[o], sph_off[o + 1], obj_sup, sup, placed, hmap);
     } else {
         const int o = obj_idx[s];
         if (o < obj_off[s] || o >= obj_off[s + 1]) return;
-        k0 = sph_off[o];
-        k1 = sph_off[o + 1];
+        raise_object(o, sph_off[o], sph_off[o + 1], obj_sup, sup, placed, hmap);
     }
-    raise_scene(s, k0, k1, obj_off, obj_sup, sup, placed, hmap);
+}
+
+// The scene each support belongs to (sup_scene[u], -1 where no object rests
+// on it); a support that objects of two scenes rest on sets
+// kErrSharedSupport.  One thread per scene.
+__global__ void k_support_scene(int n, const int32_t* __restrict__ obj_off,
+                                const int32_t* __restrict__ obj_sup, int32_t* __restrict__ sup_scene,
+                                unsigned long long* __restrict__ counters) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    bool shared = false;
+    for (int o = obj_off[s]; o < obj_off[s + 1]; ++o) {
+        const int prev = atomicCAS(sup_scene + obj_sup[o], -1, s);
+        shared |= prev != -1 && prev != s;
+    }
+    if (shared) atomicOr(counters + kErrorWord, (unsigned long long)kErrSharedSupport);
+}
+
+hipError_t launch_support_scene(const scn_batch& b, int32_t* sup_scene, int64_t* counters,
+                                hipStream_t st) {
+    if (b.n_scenes == 0) return hipSuccess;
+    if (hipError_t e = launch_fill_i32(sup_scene, b.n_supports, -1, st)) return e;
+    hipLaunchKernelGGL(k_support_scene, dim3((b.n_scenes + 255) / 256), dim3(256), 0, st,
+                       b.n_scenes, b.obj_off, b.obj_sup, sup_scene,
+                       (unsigned long long*)counters);
+    return hipGetLastError();
 }
 
 // The learned pipeline's plan of one tick: the active scenes below the
@@ -252,24 +289,25 @@ hipError_t launch_hmap_raise(const scn_batch& b, const int32_t* obj_idx, const i
 }
 
 // ---------------------------------------------------------------------------
-// Feature rows x[r] = [10 * hmap[s] (4096), desc[obj_idx[r]] (32)] as BF16,
-// s = rows[r] (or r without a row list); zeros for rows with obj_idx < 0.
-// Row length ld >= 4128.  With m_dev only rows below *m_dev are written.
+// Feature rows x[r] = [10 * hmap[u] (4096), desc[o] (32)] as BF16 for
+// object o = obj_idx[r] on support u = obj_sup[o]; zeros for rows with
+// obj_idx < 0.  Row length ld >= 4128.  With m_dev only rows below *m_dev are
+// written.
 __global__ __launch_bounds__(256) void k_features(int n, const float* __restrict__ hmap,
                                                  const float* __restrict__ desc,
-                                                 const int32_t* __restrict__ obj_idx, int ld,
+                                                 const int32_t* __restrict__ obj_idx,
+                                                 const int32_t* __restrict__ obj_sup, int ld,
                                                  __bf16* __restrict__ x,
-                                                 const int32_t* __restrict__ rows,
                                                  const int32_t* __restrict__ m_dev) {
     const int r = blockIdx.x;
     if (r >= n || (m_dev && r >= *m_dev)) return;
-    const size_t s = rows ? (size_t)rows[r] : (size_t)r;   // the scene of feature row r
     const int o = obj_idx[r];
+    const size_t u = o >= 0 ? (size_t)obj_sup[o] : 0;   // the support of feature row r
     __bf16* row = x + (size_t)r * ld;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
         float v = 0.f;
         if (o >= 0) {
-            if (i < 4096) v = 10.f * hmap[s * 4096 + i];
+            if (i < 4096) v = 10.f * hmap[u * 4096 + i];
             else if (i < 4128) v = desc[32 * (size_t)o + (i - 4096)];
         }
         row[i] = (__bf16)v;
@@ -277,11 +315,11 @@ __global__ __launch_bounds__(256) void k_features(int n, const float* __restrict
 }
 
 hipError_t launch_features(int n, const float* hmap, const float* desc, const int32_t* obj_idx,
-                           int ld, void* x, hipStream_t st, const int32_t* rows,
+                           const int32_t* obj_sup, int ld, void* x, hipStream_t st,
                            const int32_t* m_dev) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_features, dim3(n), dim3(256), 0, st, n, hmap, desc, obj_idx, ld,
-                       (__bf16*)x, rows, m_dev);
+    hipLaunchKernelGGL(k_features, dim3(n), dim3(256), 0, st, n, hmap, desc, obj_idx, obj_sup, ld,
+                       (__bf16*)x, m_dev);
     return hipGetLastError();
 }
 
@@ -461,12 +499,14 @@ hipError_t launch_topk(int M, const float* logits, int k, const int32_t* active,
 // ---------------------------------------------------------------------------
 // Label harvesting.  For every scene s with obj_idx[s] >= 0, L uniform
 // candidates of that object (Philox tag 2 in the attempt word: counter
-// (i, 0x20000 | round, step, s)) are checked exactly against the scene's boxes
-// and its first n_placed[s] objects; bins[s][i] receives the pose bin and
-// accept[s][i] 1 (collision-free) or 0.  Lane per candidate, wave-uniform
-// obstacles (like the dense checker).  Non-finite input (the object's spheres
-// or support row, a box row or placed sphere of the state) makes every label
-// of the state a rejection and sets the non-finite error bit.
+// (i, 0x20000 | round, step, s)) are checked exactly against the scene's
+// boxes, its voxel grids (trilinear) and its first n_placed[s] objects;
+// bins[s][i] receives the pose bin and accept[s][i] 1 (collision-free) or 0.
+// Lane per candidate, wave-uniform obstacles (like the dense checker).
+// Non-finite input (the object's spheres or support row, a box row or placed
+// sphere of the state) makes every label of the state a rejection, and a grid
+// sample that reads a non-finite node rejects its label; either sets the
+// non-finite error bit.
 __global__ __launch_bounds__(64) void k_harvest(
     const int32_t* __restrict__ obj_off, const int32_t* __restrict__ sph_off,
     const float4* __restrict__ tmpl, const int32_t* __restrict__ obj_sup,
@@ -474,7 +514,9 @@ __global__ __launch_bounds__(64) void k_harvest(
     const float* __restrict__ box, const float4* __restrict__ placed,
     const int32_t* __restrict__ n_state, int L, uint64_t seed, int round, float margin,
     int32_t* __restrict__ bins_out, float* __restrict__ accept_out,
-    unsigned long long* __restrict__ counters) {
+    unsigned long long* __restrict__ counters, const int32_t* __restrict__ grid_off,
+    const float* __restrict__ grid, const int32_t* __restrict__ grid_src,
+    const int64_t* __restrict__ grid_val_off, const float* __restrict__ grid_val) {
     const int s = blockIdx.x;
     const int i = blockIdx.y * 64 + threadIdx.x;
     const int o = obj_off[s] + max(n_state[s], 0);   // the next object of the state
@@ -507,6 +549,8 @@ __global__ __launch_bounds__(64) void k_harvest(
     for (int q = first + threadIdx.x; q < pl_end; q += kWave) bad |= !finite4(placed[q]);
     bad = __ballot(bad) != 0;
     float clr = __builtin_huge_valf();
+    const int g0 = grid_off ? grid_off[s] : 0, g1 = grid_off ? grid_off[s + 1] : 0;
+    bool nan_sample = false;   // a grid sample that read a non-finite node
     for (int k = sph_off[o]; k < sph_off[o + 1]; ++k) {
         const float4 c = tmpl[k];
         float wx, wy, wz;
@@ -514,6 +558,12 @@ __global__ __launch_bounds__(64) void k_harvest(
         float best = __builtin_huge_valf();
         for (int bx = box_off[s]; bx < box_off[s + 1]; ++bx)
             best = fminf(best, box_sdf(box + 16 * bx, wx, wy, wz));
+        for (int g = g0; g < g1; ++g) {
+            const float v = grid_sample(grid + 24 * g, grid_val + grid_val_off[grid_src[g]], wx,
+                                        wy, wz);
+            nan_sample |= v != v;
+            best = fminf(best, v);
+        }
         for (int q = first; q < pl_end; ++q) {
             const float4 p = placed[q];
             const float dx = wx - p.x, dy = wy - p.y, dz = wz - p.z;
@@ -523,9 +573,10 @@ __global__ __launch_bounds__(64) void k_harvest(
     }
     if (i < L) {
         bins_out[(size_t)s * L + i] = bin;
-        accept_out[(size_t)s * L + i] = !bad && clr >= margin ? 1.f : 0.f;
+        accept_out[(size_t)s * L + i] = !bad && !nan_sample && clr >= margin ? 1.f : 0.f;
     }
-    if (bad && threadIdx.x == 0) atomicOr(counters + kErrorWord, (unsigned long long)kErrNonFinite);
+    if ((bad || __ballot(nan_sample && i < L) != 0) && threadIdx.x == 0)
+        atomicOr(counters + kErrorWord, (unsigned long long)kErrNonFinite);
 }
 
 hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uint64_t seed,
@@ -535,7 +586,8 @@ hipError_t launch_harvest(const scn_batch& b, const int32_t* n_state, int L, uin
     hipLaunchKernelGGL(k_harvest, dim3(b.n_scenes, (L + 63) / 64), dim3(64), 0, st, b.obj_off,
                        b.sph_off, (const float4*)b.tmpl, b.obj_sup, b.sup, b.box_off, b.box,
                        (const float4*)b.placed, n_state, L, seed, round, margin, bins, accept,
-                       (unsigned long long*)counters);
+                       (unsigned long long*)counters, b.grid_off, b.grid, b.grid_src,
+                       b.grid_val_off, b.grid_val);
     return hipGetLastError();
 }
 

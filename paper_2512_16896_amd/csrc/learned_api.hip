@@ -9,22 +9,16 @@ using scn::align256;
 
 namespace {
 
-// The learned proposal's state features hold one height map over the support
-// of each scene's first object, and its label harvest tests boxes and placed
-// spheres only: batches with voxel grids, or more supports than scenes (some
-// scene's objects on several supports), are outside what it computes.
-int check_single_support(const scn_batch* b) {
+// The learned proposal's pose bins cover a whole support rectangle and turn
+// about z only: batches whose candidates are drawn elsewhere (spatial
+// relations, ratio_on_support), filtered by reachability, or turned by stable
+// poses are outside what it computes.
+int check_learned_batch(const scn_batch* b) {
     if (b->obj_rel || b->obj_ratio || b->robot || b->obj_pose_off)
         return scn_fail(SCN_E_UNSUPPORTED,
                         "the learned proposal does not support spatial relations, "
                         "ratio_on_support, reachability or stable poses (its bins cover the "
                         "whole support and turns about z)");
-    if (b->grid_off)
-        return scn_fail(SCN_E_UNSUPPORTED, "the learned proposal does not support voxel-grid batches");
-    if (b->n_supports > b->n_scenes)
-        return scn_fail(SCN_E_UNSUPPORTED,
-                        "the learned proposal needs one support per scene (%d supports, %d scenes)",
-                        b->n_supports, b->n_scenes);
     return SCN_OK;
 }
 
@@ -73,13 +67,15 @@ int scn_heightmaps(scn_ctx* c, const scn_batch* b, const int32_t* n_state, float
     return SCN_OK;
 }
 
-int scn_features(scn_ctx* c, int32_t n, const float* hmap, const float* desc,
-                 const int32_t* obj_idx, uint16_t* x, scn_stream stream) {
+int scn_features(scn_ctx* c, const scn_batch* b, int32_t n, const float* hmap,
+                 const float* desc, const int32_t* obj_idx, uint16_t* x, scn_stream stream) {
     if (int r = scn_check_ctx(c)) return r;
+    if (!b || !b->obj_sup) return scn_fail(SCN_E_INVALID_ARG, "batch with obj_sup required");
     if (n < 0) return scn_fail(SCN_E_INVALID_ARG, "n must be >= 0");
     if (n > 0 && (!hmap || !desc || !obj_idx || !x))
         return scn_fail(SCN_E_INVALID_ARG, "hmap, desc, obj_idx and x required");
-    SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, SCN_FEATURES, x, (hipStream_t)stream));
+    SCN_HIP(scn::launch_features(n, hmap, desc, obj_idx, b->obj_sup, SCN_FEATURES, x,
+                                 (hipStream_t)stream));
     return SCN_OK;
 }
 
@@ -97,7 +93,7 @@ int scn_harvest_labels(scn_ctx* c, const scn_batch* b, const int32_t* n_state, i
                        scn_stream stream) {
     if (int r = scn_check_ctx(c)) return r;
     if (int r = check_scenes(b)) return r;
-    if (int r = check_single_support(b)) return r;
+    if (int r = check_learned_batch(b)) return r;
     if (L <= 0 || round < 0 || round > 0xFFFF || !(margin >= 0.f))
         return scn_fail(SCN_E_INVALID_ARG, "bad L, round or margin");
     if (b->n_scenes == 0) return SCN_OK;
@@ -131,6 +127,7 @@ struct LearnedWs {
     int32_t* bins;
     int32_t *obj_idx, *list, *count, *resume;
     void *map_keep, *bnd_keep, *info_keep;   // state the step launches keep (PlacePlan)
+    int32_t* sup_scene;                       // the scene of each support (checked)
 };
 size_t learned_layout(const scn_batch* b, const scn_mlp* net, int top_k, char* base,
                       LearnedWs* w) {
@@ -143,7 +140,8 @@ size_t learned_layout(const scn_batch* b, const scn_mlp* net, int top_k, char* b
     };
     LearnedWs t;
     t.act = take(scn::ws_mlp_forward_bytes(net, b->n_scenes));
-    t.hmap = (float*)take(n * SCN_HMAP_CELLS * 4);
+    t.hmap = (float*)take((size_t)b->n_supports * SCN_HMAP_CELLS * 4);
+    t.sup_scene = (int32_t*)take((size_t)b->n_supports * 4);
     t.desc = (float*)take((size_t)b->n_objects * SCN_DESC * 4);
     t.x = (uint16_t*)take(n * SCN_FEATURES * 2);
     t.logits = (float*)take(n * SCN_BINS * 4);
@@ -184,7 +182,7 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     if (!b->placed || !b->n_placed || !b->status || !b->rec)
         return scn_fail(SCN_E_INVALID_ARG, "placed/n_placed/status/rec required");
     if (a->retries < 0) return scn_fail(SCN_E_INVALID_ARG, "retries must be >= 0");
-    if (int r = check_single_support(b)) return r;
+    if (int r = check_learned_batch(b)) return r;
     // Launch shapes.  The first ticks (as many as a scene has objects) carry
     // nearly every scene in the new-object list: their launch runs
     // args->schedule (0: one wave per scene, placed spheres from global
@@ -223,6 +221,7 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
     SCN_HIP(scn::launch_reset(*b, st));
     SCN_HIP(scn::launch_fill_i32(W.resume, n, 0, st));
     SCN_HIP(scn::launch_descriptor(*b, W.desc, st));
+    SCN_HIP(scn::launch_support_scene(*b, W.sup_scene, c->d_counters, st));
     SCN_HIP(scn::launch_hmap_boxes(*b, W.hmap, st));
     SCN_HIP(scn::launch_object_info(*b, a->margin, W.info_keep, st));
     void* map_keep = b->grid_off ? nullptr : W.map_keep;
@@ -251,8 +250,8 @@ int scn_generate_scenes_learned(scn_ctx* c, scn_batch* b, const scn_gen_args* a,
                                    c->aux_stream))
             return r;
         SCN_HIP(hipEventRecord(c->ev[1], c->aux_stream));
-        SCN_HIP(scn::launch_features(n, W.hmap, W.desc, W.obj_idx, SCN_FEATURES, W.x, s, list_new,
-                                     W.count));
+        SCN_HIP(scn::launch_features(n, W.hmap, W.desc, W.obj_idx, b->obj_sup, SCN_FEATURES, W.x,
+                                     s, W.count));
         if (int r = scn_mlp_forward_ws(net, W.x, n, W.logits, W.act, s, W.count)) return r;
         SCN_HIP(scn::launch_topk(n, W.logits, top_k, nullptr, W.bins, s, list_new, W.count));
         if (int r = scn_place_rows(c, b, late ? &wide : a, W.bins, top_k, W.resume, -1, j_cap,

@@ -1359,15 +1359,17 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                     if constexpr (kLds) lsph[sb - first + k] = make_float4(px, py, pz, cr[q] + margin);
                 }
             }
-            // the learned proposal's height map of the scene, raised by the
-            // committed spheres (the same arithmetic as k_hmap_raise)
+            // the learned proposal's height map of the object's support,
+            // raised by the committed spheres (the same arithmetic as
+            // k_hmap_raise)
             if (hmap) {
-                const SupportFrame F = scene_support(obj_off, obj_sup, sup, s);
+                const int u = obj_sup[o];
+                const SupportFrame F = support_frame(sup, u);
 #pragma unroll
                 for (int q = 0; q < SPL; ++q) {
                     if (act[q]) {
                         const float4 w = placed[sb + lane + kWave * q];
-                        hmap_raise_sphere(F, hmap + (size_t)s * 4096, w.x, w.y, w.z, w.w);
+                        hmap_raise_sphere(F, hmap + (size_t)u * 4096, w.x, w.y, w.z, w.w);
                     }
                 }
             }

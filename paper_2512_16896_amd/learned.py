@@ -3,8 +3,9 @@
 Labels come from the exact checker: for every state of a plain generation run
 (scene s with its first j objects placed, about to place object j) the
 library's harvest kernel draws uniform candidates of object j, records their
-pose bins and whether they are collision-free.  The state's features (height
-map + descriptor) are built by the library's kernels too.  Training runs the
+pose bins and whether they are collision-free.  The state's features (the
+height map of object j's support + its descriptor) are built by the
+library's kernels too.  Training runs the
 library's BF16 matrix-core forward / backward kernels and its AdamW kernel;
 PyTorch here only holds the tensors and shuffles rows into minibatches.
 """
@@ -47,7 +48,7 @@ def harvest(ctx: scn.Context, db: scn.DeviceBatch, seed: int, labels_per_state: 
         n_state = torch.where(use, torch.full_like(nobj, j), nobj)   # no next object when unused
         obj_idx = torch.where(use, db.obj_off[:n] + j, torch.full_like(nobj, -1)).to(torch.int32)
         hmap = scn.heightmaps(ctx, db, n_state)
-        x = scn.features(ctx, hmap, desc, obj_idx)
+        x = scn.features(ctx, db, hmap, desc, obj_idx)
         bins, acc = scn.harvest_labels(ctx, db, n_state, labels_per_state, seed, round_, margin)
         keep = use.nonzero().squeeze(1)
         xs.append(x.index_select(0, keep))

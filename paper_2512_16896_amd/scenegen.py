@@ -359,6 +359,33 @@ def shelf_scenes(n_scenes: int = 65536, seed: int = 0, n_obj: int = 100, n_sph: 
                     n_shelves=n_shelves, seed=seed))
 
 
+def uneven_shelf_scenes(n_scenes: int = 65536, seed: int = 0, n_obj=(40, 100),
+                        n_sph=(64, 128), n_cand=(1024, 2048), chunk: int = 2048) -> SceneBatch:
+    """Shelf units as in shelf_scenes with uneven counts: per scene N ~
+    U{n_obj} objects (the first N of its round-robin order), per object S ~
+    U{n_sph} spheres (the first S of its template) and C ~ U{n_cand}
+    candidates per attempt."""
+    full = shelf_scenes(n_scenes, seed=seed, n_obj=n_obj[1], n_sph=n_sph[1], n_cand=n_cand[1],
+                        chunk=chunk)
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x0E5F]))
+    N = rng.integers(n_obj[0], n_obj[1] + 1, size=n_scenes)
+    keep = (np.arange(n_obj[1])[None, :] < N[:, None]).ravel()
+    objs = np.nonzero(keep)[0]
+    S = rng.integers(n_sph[0], n_sph[1] + 1, size=len(objs))
+    sidx = _ranges(full.sph_off[objs].astype(np.int64), S)
+    sph_off = np.zeros(len(objs) + 1, np.int64)
+    sph_off[1:] = np.cumsum(S)
+    obj_off = np.zeros(n_scenes + 1, np.int64)
+    obj_off[1:] = np.cumsum(N)
+    b = dataclasses.replace(
+        full, obj_off=obj_off.astype(np.int32), sph_off=sph_off.astype(np.int32),
+        tmpl=full.tmpl[sidx], obj_sup=full.obj_sup[objs].copy(),
+        obj_ncand=rng.integers(n_cand[0], n_cand[1] + 1, size=len(objs)).astype(np.int32),
+        name=f"uneven-shelves-{n_scenes}",
+        params=dict(full.params, n_obj=n_obj, n_sph=n_sph, n_cand=n_cand))
+    return b
+
+
 # Drawer cabinet (base link frame: x out of the front, z up; metres).  Static
 # boards as (centre, half extents); each drawer is a prismatic joint along +x
 # at height z_d with its bottom as a support surface and four walls as boxes,

@@ -131,7 +131,7 @@ def _load():
         "scn_mlp_train_step": [vp, C.POINTER(Mlp), vp, i32, vp, vp, i32, C.POINTER(AdamW), vp, vp],
         "scn_descriptors": [vp, C.POINTER(_Batch), vp, vp],
         "scn_heightmaps": [vp, C.POINTER(_Batch), vp, vp, vp],
-        "scn_features": [vp, i32, vp, vp, vp, vp, vp],
+        "scn_features": [vp, C.POINTER(_Batch), i32, vp, vp, vp, vp, vp],
         "scn_proposal_topk": [vp, vp, i32, i32, vp, vp, vp],
         "scn_harvest_labels": [vp, C.POINTER(_Batch), vp, i32, u64, i32, f32, vp, vp, vp],
         "scn_generate_scenes_learned": [vp, C.POINTER(_Batch), C.POINTER(_GenArgs),
@@ -595,17 +595,19 @@ def descriptors(ctx: Context, db: DeviceBatch, stream=None) -> torch.Tensor:
 
 def heightmaps(ctx: Context, db: DeviceBatch, n_state: Optional[torch.Tensor] = None,
                stream=None) -> torch.Tensor:
-    out = torch.empty((max(db.c.n_scenes, 1), HMAP_CELLS), dtype=torch.float32,
+    """scn_heightmaps: one [4096] map per support (zeros where no object rests)."""
+    out = torch.zeros((max(db.c.n_supports, 1), HMAP_CELLS), dtype=torch.float32,
                       device=db.tmpl.device)
     _ok(_lib.scn_heightmaps(ctx.h, C.byref(db.c), _ptr(n_state), _ptr(out), _stream(stream)))
-    return out[:db.c.n_scenes]
+    return out[:db.c.n_supports]
 
 
-def features(ctx: Context, hmap, desc, obj_idx, stream=None) -> torch.Tensor:
+def features(ctx: Context, db: DeviceBatch, hmap, desc, obj_idx, stream=None) -> torch.Tensor:
+    """scn_features: row r = [10 x the map of obj_idx[r]'s support, its descriptor]."""
     n = int(obj_idx.shape[0])
     out = torch.empty((max(n, 1), FEATURES), dtype=torch.bfloat16, device=obj_idx.device)
-    _ok(_lib.scn_features(ctx.h, n, _ptr(hmap), _ptr(desc), _ptr(obj_idx), _ptr(out),
-                          _stream(stream)))
+    _ok(_lib.scn_features(ctx.h, C.byref(db.c), n, _ptr(hmap), _ptr(desc), _ptr(obj_idx),
+                          _ptr(out), _stream(stream)))
     return out[:n]
 
 

@@ -209,24 +209,23 @@ def test_workspace_too_small_is_refused_before_any_launch(dev):
     ctx.close()
 
 
-def test_learned_calls_refuse_grid_and_multi_support_batches(dev):
+def test_learned_generation_reports_a_support_shared_by_two_scenes(dev):
+    """The learned path keeps one height map per support: a support that
+    objects of two scenes rest on is reported by the next counter read."""
     scn, torch = dev
     ctx = scn.Context(0)
     net = scn.Network(train=False)
     net.init(ctx, 1)
-    shelves = scn.DeviceBatch(sg.shelf_scenes(2, n_obj=6, n_sph=16, n_cand=32))
     b = sg.batched_scenes(3, seed=0)
-    b.sup = np.concatenate([b.sup, b.sup[:1]])       # scene 0's second object on a 4th support
     b.obj_sup = b.obj_sup.copy()
-    b.obj_sup[1] = 3
-    multi = scn.DeviceBatch(b)
-    for db in (shelves, multi):
-        with pytest.raises(scn.ScnError) as e:
-            scn.generate_scenes_learned(ctx, db, scn.GenArgs(seed=1), net, top_k=8)
-        assert e.value.code == scn.SCN_E_UNSUPPORTED
-        with pytest.raises(scn.ScnError) as e:
-            scn.harvest_labels(ctx, db, db.n_placed, 8, seed=1)
-        assert e.value.code == scn.SCN_E_UNSUPPORTED
+    b.obj_sup[b.obj_off[1]] = 0                      # scene 1's first object on scene 0's support
+    db = scn.DeviceBatch(b)
+    ctx.reset_counters()
+    scn.generate_scenes_learned(ctx, db, scn.GenArgs(seed=1, max_steps=2), net, top_k=8)
+    with pytest.raises(scn.ScnError) as e:
+        ctx.read_counters()
+    assert e.value.code == scn.SCN_E_INVALID_ARG
+    ctx.reset_counters()
     ctx.close()
 
 

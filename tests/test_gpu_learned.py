@@ -131,8 +131,12 @@ def test_train_step_matches_oracle_adamw(dev):
                                      1e-8, 0.0)
         gb = np.abs(rgb[l])
         sure_b = gb > 0.1 * np.sqrt(np.mean(gb * gb))
-        assert sure_b.sum() > 0.5 * gb.size
+        assert sure_b.sum() >= 32
         assert _rel((nb - b[l])[sure_b], (want_b - b[l])[sure_b]) < 0.02, l
+        # a bias whose gradient is exactly zero (the logits' bins no label
+        # names) does not move: no decay on biases
+        zero = rgb[l] == 0
+        np.testing.assert_array_equal(nb[zero], b[l].astype(np.float64)[zero])
 
 
 def test_init_is_kaiming_uniform(dev):
@@ -176,7 +180,7 @@ def test_heightmaps_and_features_match_oracle(dev, orc):
     H = scn.heightmaps(ctx, db, torch.tensor(n_state, device="cuda")).cpu().numpy()
     desc = scn.descriptors(ctx, db)
     obj_idx = np.where(n_state < 20, b.obj_off[:-1] + n_state, -1).astype(np.int32)
-    X = scn.features(ctx, torch.tensor(H, device="cuda"), desc,
+    X = scn.features(ctx, db, torch.tensor(H, device="cuda"), desc,
                      torch.tensor(obj_idx, device="cuda")).float().cpu().numpy()
     for s in range(b.n_scenes):
         ref = ol.heightmap(b, placed.astype(np.float64), s, int(n_state[s])).reshape(-1)
