@@ -442,9 +442,12 @@ __attribute__((visibility("hidden"))) int scn_place_rows(
     scn_ctx* c, scn_batch* b, const scn_gen_args* a, const int32_t* prop_bins, int prop_k,
     int32_t* resume, int chunk, int j_cap, const int32_t* rows, const int32_t* n_rows,
     void* map_keep, void* bnd_keep, const void* info_keep, float* hmap, hipStream_t st) {
-    // the launch order is the list's: no longest-first order is computed
+    // the launch order is the list's: no longest-first order is computed; the
+    // placed spheres stay in global memory (the kept state assumes it)
     scn_gen_args a1 = *a;
-    if (a1.schedule != 0) a1.schedule &= ~SCN_SCHED_LONGEST_FIRST;
+    if (a1.schedule == 0) a1.schedule = kDefaultSchedule;
+    a1.schedule = (a1.schedule & ~(SCN_SCHED_LONGEST_FIRST | SCN_SCHED_LDS_MASK)) |
+                  (SCN_SCHED_LDS_NONE << SCN_SCHED_LDS_SHIFT);
     a = &a1;
     scn::PlacePlan plan;
     if (int r = plan_place(c, b, a, 1, &plan, nullptr)) return r;

@@ -336,8 +336,14 @@ __device__ __forceinline__ void to_support(const SupportFrame& F, float x, float
 // Raise a scene's height map (64 x 64 floats at hm) by one world sphere:
 // a monotone max through integer atomics on non-negative floats, so the
 // result does not depend on the order of the spheres or of the callers.
+// With a tile (T, an LDS window of tw x th cells from cell (tx0, ty0),
+// i-major), cells inside the window are raised there and the rest in hm; the
+// caller then raises hm by the window (hmap_flush_tile).  Every cell value is
+// the same either way.
 __device__ __forceinline__ void hmap_raise_sphere(const SupportFrame& F, float* __restrict__ hm,
-                                                  float x, float y, float z, float r) {
+                                                  float x, float y, float z, float r,
+                                                  int* T = nullptr, int tx0 = 0, int ty0 = 0,
+                                                  int tw = 0, int th = 0) {
     const float cw = 2.f * F.hx / 64.f, ch = 2.f * F.hy / 64.f;
     int* H = (int*)hm;
     float px, py, pz;
@@ -354,7 +360,13 @@ __device__ __forceinline__ void hmap_raise_sphere(const SupportFrame& F, float* 
             const float d2 = (cx - px) * (cx - px) + (cy - py) * (cy - py);
             if (d2 < r * r) {
                 const float top = pz + sqrtf(r * r - d2);
-                if (top > 0.f) atomicMax(H + ix * 64 + iy, __float_as_int(top));
+                if (top > 0.f) {
+                    const int wx = ix - tx0, wy = iy - ty0;
+                    if ((unsigned)wx < (unsigned)tw && (unsigned)wy < (unsigned)th)
+                        atomicMax(T + wx * th + wy, __float_as_int(top));
+                    else
+                        atomicMax(H + ix * 64 + iy, __float_as_int(top));
+                }
             }
         }
     }

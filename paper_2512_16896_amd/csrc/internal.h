@@ -83,6 +83,9 @@ constexpr int kMapBytes = 24576;
 constexpr int kObjLds = 5;
 // the place kernel's LDS copy of a scene's first 64 box rows (16 floats each)
 constexpr int kBoxLdsBytes = 64 * 16 * 4;
+// cells of the height-map window the place kernel raises in LDS at a commit
+// (it reuses the box rows' space)
+constexpr int kHmapTileCells = kBoxLdsBytes / 4;
 // LDS the place kernel's static shared variables may take (reserved beside
 // its dynamic LDS)
 constexpr int kPlaceStaticLds = 2048;

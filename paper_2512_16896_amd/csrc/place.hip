@@ -25,6 +25,7 @@
 // a wave stops once the best entry is below its next one, so every entry
 // before the winner has been decided and the result is exactly the first
 // collision-free one, whatever the number of waves.
+#include <algorithm>
 #include <climits>
 
 #include "device.h"
@@ -280,6 +281,34 @@ __device__ __forceinline__ bool map_geometry(float ax, float ay, DepthMap& m) {
 // r + kMapReach of its centre.  The caller writes the (i, j) columns c of the
 // covering cube with c % parts == part; each column visits only the z range
 // of that ball.
+// The depth map's initial LDS contents: a copy of src (a map kept by an
+// earlier launch) or empty (every voxel at the lowest depth).  16-byte words,
+// eight loads in flight per thread before their stores, so a one-wave
+// workgroup waits on three rounds of loads instead of one per word; the
+// region ends on a 16-byte boundary inside kMapBytes.
+static_assert(kMapBytes % 16 == 0 && kBoxLdsBytes % 16 == 0, "16-byte map words");
+__device__ __forceinline__ void map_fill(int8_t* __restrict__ M, const DepthMap& m,
+                                         const int8_t* __restrict__ src) {
+    const int w16 = (m.nx * m.ny * m.nz + 15) >> 4;
+    int4* mw = reinterpret_cast<int4*>(M);
+    const int4* sw = reinterpret_cast<const int4*>(src);
+    const int e = (int)0x80808080u;
+    const int step = (int)blockDim.x;
+    for (int i0 = (int)threadIdx.x; i0 < w16; i0 += 8 * step) {
+        int4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * step;
+            v[u] = src && i < w16 ? sw[i] : make_int4(e, e, e, e);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * step;
+            if (i < w16) mw[i] = v[u];
+        }
+    }
+}
+
 __device__ __forceinline__ void map_insert(int8_t* __restrict__ M, const DepthMap& m, float cx,
                                            float cy, float cz, float r, int part, int parts) {
     if (!(fabsf(cx) < 1e4f && fabsf(cy) < 1e4f && fabsf(cz) < 1e4f && r >= 0.f && r < 1e3f)) return;
@@ -555,8 +584,12 @@ __device__ __forceinline__ void object_info(const float4* __restrict__ tmpl,
     grid_off, grid, grid_src, grid_val_off, grid_val, obj_rel, rel, obj_ratio, robot, obj_reach, \
     rmap, map_keep, bnd_keep, info_keep, hmap, pose_off, stable, rec_stable
 
-template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons>
+// kHmap: instances of the learned launches, which raise the height map of the
+// object's support at each commit (placed spheres in global memory, no
+// constraints)
+template <int SPL, bool kLds, bool kGrids, bool kYaw, bool kCons, bool kHmap = false>
 __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
+    static_assert(!kHmap || (!kLds && !kCons), "height-map instances keep spheres in global memory");
     // placed objects covered by a candidate's object mask: 64 per word; the
     // dense multi-shelf (grid) scenes carry 100 objects, so they get two words
     constexpr int kObjWords = kGrids ? 2 : 1;
@@ -564,9 +597,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     float4* lsph = lds;                        // placed spheres: (x, y, z, r + margin)
     float4* lbnd = lds + (kLds ? cap_sph : 0); // world bounding sphere of each placed object
     // per object to place: 4 constants (bounds, probes, lift and flags)
+    // (a launch that places at most max_steps objects keeps that many)
     float4* linfo = lbnd + cap_obj;
+    const int n_info = max_steps > 0 ? min(cap_obj, max_steps) : cap_obj;
     // the rows of the scene's first 64 boxes (kBoxLdsBytes)
-    float* lbox = reinterpret_cast<float*>(linfo + 4 * cap_obj);
+    float* lbox = reinterpret_cast<float*>(linfo + 4 * n_info);
     // scenes without grids: the depth map after them (kMapBytes)
     constexpr bool kMap = !kGrids;
     int8_t* lmap = reinterpret_cast<int8_t*>(lbox) + kBoxLdsBytes;
@@ -579,28 +614,39 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     __shared__ StableTab s_stab;  // the current object's stable poses
 
     // with n_order, only the first *n_order entries of `order` are scenes of
-    // this launch (a list compacted on the device); the other workgroups leave
-    if (n_order && (int)blockIdx.x >= *n_order) return;
+    // this launch (a list compacted on the device); the other workgroups leave.
+    // The scene's header words are read up front, so that these independent
+    // loads are in flight together instead of costing a round trip each.
+    const int n_live = n_order ? *n_order : INT_MAX;
     const int s = order ? order[blockIdx.x] : (int)blockIdx.x;
+    if ((int)blockIdx.x >= n_live) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform_int(threadIdx.x >> 6);
     const int W = blockDim.x >> 6;
 
     const int o0 = obj_off[s], o1 = obj_off[s + 1];
+    const int8_t status0 = status[s];
+    const int placed0 = n_placed[s];
+    const int resume_s = resume ? resume[s] : 0;
+    const int b0 = box_off[s], b1 = box_off[s + 1];
+    const int g0 = grid_off ? grid_off[s] : 0;
+    const int g1 = grid_off ? grid_off[s + 1] : 0;
     const int nobj = o1 - o0;
     const int first = sph_off[o0];
     const int nsph = sph_off[o1] - first;
     if (split) {   // which of the two launches owns this scene
         if (kLds ? nsph > split_sph : nsph <= split_sph) return;
     }
-    if (status[s] != SCN_SCENE_ACTIVE) {
+    if (status0 != SCN_SCENE_ACTIVE) {
         if (chosen && threadIdx.x == 0) chosen[s] = -2;
         return;
     }
+    // (every wave checks every object: no barrier, and the same answer in
+    // each wave)
     int too_big = 0;
-    for (int ob = o0 + (int)threadIdx.x; ob < o1; ob += blockDim.x)
+    for (int ob = o0 + lane; ob < o1; ob += kWave)
         too_big |= (sph_off[ob + 1] - sph_off[ob]) > kWave * SPL;
-    too_big = __syncthreads_or(too_big);
+    too_big = __ballot(too_big) != 0;
     if (too_big || (kLds && nsph > cap_sph) || nobj > cap_obj) {
         if (threadIdx.x == 0) {
             atomicOr(counters + kErrorWord, (unsigned long long)kErrCapacity);
@@ -608,7 +654,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         }
         return;
     }
-    int j = min(max(n_placed[s], 0), nobj);
+    int j = min(max(placed0, 0), nobj);
     int j_end = max_steps > 0 ? min(nobj, j + max_steps) : nobj;
     if (j_cap > 0) j_end = min(j_end, j_cap);
     if (j >= j_end && j < nobj) {   // the objects-per-scene cap stops this scene
@@ -616,7 +662,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         return;
     }
     // entry of the current object's list to resume at (learned path)
-    const int resume0 = resume ? max(resume[s], 0) : 0;
+    const int resume0 = max(resume_s, 0);
     const int j_start = j;
     int pend = 0;
     // placed sphere k of this scene, radius grown by the margin
@@ -676,16 +722,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             use_map = map_geometry(U0.hx - U0.inset, U0.hy - U0.inset, dm);
             if (use_map) {
                 if (threadIdx.x == 0) s_dm = dm;
-                const int words = (dm.nx * dm.ny * dm.nz + 3) >> 2;
-                int* mw = reinterpret_cast<int*>(lmap);
                 const int n_old = sph_off[o0 + j] - first;
                 // with map_keep, the map the launch that placed the scene's
                 // last object stored (every placing launch stores it)
                 const bool kept = map_keep && j > 0;
-                const int* src = kept ? reinterpret_cast<const int*>(map_keep + (size_t)s * kMapBytes)
-                                      : nullptr;
-                for (int i = threadIdx.x; i < words; i += blockDim.x)
-                    mw[i] = kept ? src[i] : (int)0x80808080u;
+                map_fill(lmap, dm, kept ? map_keep + (size_t)s * kMapBytes : nullptr);
                 __syncthreads();
                 for (int i = kept ? n_old : (int)threadIdx.x; i < n_old; i += blockDim.x) {
                     const float4 q = placed[first + i];
@@ -704,7 +745,6 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     unsigned lane_boxp = 0;   // per-lane share of n_boxp
     int8_t fin = SCN_SCENE_ACTIVE;
     int last = -2;
-    const int b0 = box_off[s], b1 = box_off[s + 1];
     const int nbox_mask = min(b1 - b0, kWave);   // boxes covered by the batch masks
     // the first 64 box rows into LDS: the batch and candidate phases read
     // them there (the barrier below publishes them)
@@ -718,20 +758,17 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     // are only copied.
     if (info_keep) {
         for (int i = threadIdx.x; i < 4 * (j_end - j); i += blockDim.x)
-            linfo[4 * j + i] = info_keep[4 * (size_t)(o0 + j) + i];
+            linfo[i] = info_keep[4 * (size_t)(o0 + j) + i];
     } else {
         for (int jj = j + wave; jj < j_end; jj += W)
             object_info<SPL, !kGrids>(tmpl, sph_off, obj_sup, sup, box, o0 + jj, b0, nbox_mask,
-                                      margin, lane, linfo + 4 * jj);
+                                      margin, lane, linfo + 4 * (jj - j));
     }
     // the scene's boxes all turn about z only (then, with a support that does
-    // too, the entry loop runs its planar form); the barrier also publishes
-    // the object constants
-    const int g0 = grid_off ? grid_off[s] : 0;
-    const int g1 = grid_off ? grid_off[s + 1] : 0;
+    // too, the entry loop runs its planar form); each wave reads every row
     const int ngrid_mask = kGrids ? min(g1 - g0, kWave) : 0;   // grids covered by the masks
     int tilted = 0, bad_in = 0;
-    for (int bi = b0 + (int)threadIdx.x; bi < b1; bi += blockDim.x) {
+    for (int bi = b0 + lane; bi < b1; bi += kWave) {
         tilted |= !yaw_box(box + 16 * bi);
         bad_in |= !all_finite(box + 16 * bi, 15);
     }
@@ -739,16 +776,21 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     // instance rows, spheres placed before this launch): every candidate of
     // every remaining object collides
     if constexpr (kGrids)
-        for (int gi = g0 + (int)threadIdx.x; gi < g1; gi += blockDim.x)
-            bad_in |= !all_finite(grid + 24 * gi, 19);
+        for (int gi = g0 + lane; gi < g1; gi += kWave) bad_in |= !all_finite(grid + 24 * gi, 19);
+    const bool boxes_yaw = __ballot(tilted) == 0;
+    const bool rows_bad = __ballot(bad_in) != 0;
     // (with bnd_keep every placed sphere comes from an earlier launch of the
     // same generation, which placed it only from a finite template, support
-    // and pose)
-    if (!bnd_keep)
+    // and pose); the barrier also publishes the box rows and object constants
+    bool scene_bad = rows_bad;
+    if (bnd_keep) {
+        __syncthreads();
+    } else {
+        int bad_placed = 0;
         for (int i = threadIdx.x; i < sph_off[o0 + j] - first; i += blockDim.x)
-            bad_in |= !finite4(placed[first + i]);
-    const bool boxes_yaw = !__syncthreads_or(tilted);
-    const bool scene_bad = __syncthreads_or(bad_in) != 0;
+            bad_placed |= !finite4(placed[first + i]);
+        scene_bad = (__syncthreads_or(bad_placed) != 0) || rows_bad;
+    }
 
     for (; j < j_end; ++j) {
         const int o = o0 + j;
@@ -769,7 +811,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             rm2[q] = act[q] ? (c.w + margin) * (c.w + margin) : 0.f;
         }
         // the object's constants, computed in the prologue
-        const float4* I = linfo + 4 * j;
+        const float4* I = linfo + 4 * (j - j_start);
         const float4 I0 = I[0], I1 = I[1], I2 = I[2], I3 = I[3];
         const float bc[3] = {uniform_f(I0.x), uniform_f(I0.y), uniform_f(I0.z)};
         const float rho = uniform_f(I0.w);
@@ -1344,6 +1386,39 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         if (wave == 0) {
             const Pose P = Pw;
             const Planar Mc = planar(U, P);   // the planar form
+            // world bounding sphere of the placed object
+            float gx, gy, gz;
+            if constexpr (kYaw) {
+                planar_xy(Mc, tb[0], tb[1], gx, gy);
+                gz = tbz;
+            } else {
+                to_world(U, P, tb[0], tb[1], tb[2], gx, gy, gz);
+            }
+            // The learned proposal's height map of the object's support is
+            // raised by the committed spheres (the arithmetic of k_hmap_raise).
+            // The cells under the object's bounding sphere are raised in an
+            // LDS window first (the box rows' space, free during the commit
+            // and read again below when this launch places another object),
+            // then the map once per covered cell: far fewer global atomics
+            // than one per sphere and cell.
+            SupportFrame F{};
+            float* H = nullptr;
+            int* T = reinterpret_cast<int*>(lbox);
+            int tx0 = 0, ty0 = 0, tw = 0, th = 0;
+            if (kHmap && hmap) {
+                const int u = obj_sup[o];
+                F = support_frame(sup, u);
+                H = hmap + (size_t)u * 4096;
+                float qx, qy, qz;
+                to_support(F, gx, gy, gz, qx, qy, qz);
+                const float cw = 2.f * F.hx / 64.f, ch = 2.f * F.hy / 64.f;
+                tx0 = max(0, (int)floorf((qx - rho + F.hx) / cw - 0.5f));
+                ty0 = max(0, (int)floorf((qy - rho + F.hy) / ch - 0.5f));
+                tw = min(63, (int)ceilf((qx + rho + F.hx) / cw - 0.5f)) - tx0 + 1;
+                th = min(63, (int)ceilf((qy + rho + F.hy) / ch - 0.5f)) - ty0 + 1;
+                if (tw <= 0 || th <= 0 || tw * th > kHmapTileCells) tw = th = 0;   // no window
+                for (int c = lane; c < tw * th; c += kWave) T[c] = 0;
+            }
 #pragma unroll
             for (int q = 0; q < SPL; ++q) {
                 if (act[q]) {
@@ -1357,30 +1432,26 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
                     const int k = lane + kWave * q;
                     placed[sb + k] = make_float4(px, py, pz, cr[q]);
                     if constexpr (kLds) lsph[sb - first + k] = make_float4(px, py, pz, cr[q] + margin);
+                    if (kHmap && hmap) hmap_raise_sphere(F, H, px, py, pz, cr[q], T, tx0, ty0, tw, th);
                 }
             }
-            // the learned proposal's height map of the object's support,
-            // raised by the committed spheres (the same arithmetic as
-            // k_hmap_raise)
-            if (hmap) {
-                const int u = obj_sup[o];
-                const SupportFrame F = support_frame(sup, u);
-#pragma unroll
-                for (int q = 0; q < SPL; ++q) {
-                    if (act[q]) {
-                        const float4 w = placed[sb + lane + kWave * q];
-                        hmap_raise_sphere(F, hmap + (size_t)u * 4096, w.x, w.y, w.z, w.w);
+            if (kHmap && hmap) {
+                // window cell c = wx th + wy (c < 2^10: the float quotient
+                // truncates exactly)
+                const int ncell = tw * th;
+                const float rth = 1.f / (float)max(th, 1);
+                for (int c = lane; c < ncell; c += kWave) {
+                    const int v = T[c];
+                    if (v > 0) {
+                        const int wx = (int)(((float)c + 0.5f) * rth), wy = c - wx * th;
+                        atomicMax(reinterpret_cast<int*>(H) + (tx0 + wx) * 64 + ty0 + wy, v);
                     }
                 }
+                if (ncell > 0 && j + 1 < j_end)   // the box rows back for the next object
+                    for (int i = lane; i < 16 * nbox_mask; i += kWave)
+                        T[i] = __float_as_int(box[16 * b0 + i]);
             }
             if (lane == 0) {
-                float gx, gy, gz;
-                if constexpr (kYaw) {
-                    planar_xy(Mc, tb[0], tb[1], gx, gy);
-                    gz = tbz;
-                } else {
-                    to_world(U, P, tb[0], tb[1], tb[2], gx, gy, gz);
-                }
                 lbnd[j] = make_float4(gx, gy, gz, rho);
                 if (bnd_keep) bnd_keep[o] = make_float4(gx, gy, gz, rho);
                 rec[o] = scn_pose_rec{P.x, P.y, P.z, P.yaw, fa, fi};
@@ -1410,10 +1481,10 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     if constexpr (kMap) {
         if (map_keep && use_map && j > j_start) {
             const DepthMap dm = map_params(&s_dm);
-            const int words = (dm.nx * dm.ny * dm.nz + 3) >> 2;
-            int* dst = reinterpret_cast<int*>(map_keep + (size_t)s * kMapBytes);
-            const int* mw = reinterpret_cast<const int*>(lmap);
-            for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = mw[i];
+            const int w16 = (dm.nx * dm.ny * dm.nz + 15) >> 4;
+            int4* dst = reinterpret_cast<int4*>(map_keep + (size_t)s * kMapBytes);
+            const int4* mw = reinterpret_cast<const int4*>(lmap);
+            for (int i = threadIdx.x; i < w16; i += blockDim.x) dst[i] = mw[i];
         }
     }
     if (threadIdx.x == 0) {
@@ -1460,6 +1531,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void 
     SCN_PLACE_PARAMS) {
     place_scenes<SPL, kLds, true, kYaw, false>(SCN_PLACE_ARGS);
 }
+// the learned launches' instances (height-map raise), likewise
+template <int SPL, bool kGrids, bool kYaw>
+__global__ __launch_bounds__(1024) void k_place_h(SCN_PLACE_PARAMS) {
+    place_scenes<SPL, false, kGrids, kYaw, false, true>(SCN_PLACE_ARGS);
+}
+template <int SPL, bool kYaw>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_place_hg5(
+    SCN_PLACE_PARAMS) {
+    place_scenes<SPL, false, true, kYaw, false, true>(SCN_PLACE_ARGS);
+}
 
 // Spatial relations, reachability and stable poses are compiled only into
 // grid-free instances (kCons); a grid batch with any is refused by the
@@ -1470,6 +1551,11 @@ static auto place_kernel() {
     else if constexpr (kGrids) return k_place<SPL, kLds, true, kYaw, false>;
     else return k_place<SPL, kLds, false, kYaw, kCons>;
 }
+template <int SPL, bool kGrids, bool kYaw>
+static auto place_kernel_h() {
+    if constexpr (kGrids && SPL <= 2) return k_place_hg5<SPL, kYaw>;
+    else return k_place_h<SPL, kGrids, kYaw>;
+}
 
 template <int SPL, bool kLds>
 static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
@@ -1478,13 +1564,27 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
     const bool yaw = b.geometry == SCN_GEOM_YAW;
     const bool relp = b.obj_rel != nullptr || b.robot != nullptr || b.obj_pose_off != nullptr;
     if (relp && b.grid_off) return hipErrorNotSupported;
+    // the height-map raise is compiled into global-sphere, constraint-free
+    // instances only
+    if (plan.hmap && (kLds || relp)) return hipErrorNotSupported;
     auto kern = b.grid_off ? (yaw ? place_kernel<SPL, kLds, true, true, false>()
                                   : place_kernel<SPL, kLds, true, false, false>())
                 : relp     ? (yaw ? place_kernel<SPL, kLds, false, true, true>()
                                   : place_kernel<SPL, kLds, false, false, true>())
                            : (yaw ? place_kernel<SPL, kLds, false, true, false>()
                                   : place_kernel<SPL, kLds, false, false, false>());
-    const int bytes = 16 * ((kLds ? cap_sph : 0) + kObjLds * plan.cap_obj) + kBoxLdsBytes +
+    if constexpr (!kLds) {
+        if (plan.hmap)
+            kern = b.grid_off ? (yaw ? place_kernel_h<SPL, true, true>()
+                                     : place_kernel_h<SPL, true, false>())
+                              : (yaw ? place_kernel_h<SPL, false, true>()
+                                     : place_kernel_h<SPL, false, false>());
+    }
+    // the kernel's layout: placed spheres (LDS instances), a bounding sphere
+    // per object, 4 constants per object the launch may place, box rows,
+    // depth map (grid-free batches)
+    const int n_info = plan.max_steps > 0 ? std::min(plan.cap_obj, plan.max_steps) : plan.cap_obj;
+    const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj + 4 * n_info) + kBoxLdsBytes +
                       (b.grid_off ? 0 : kMapBytes);
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
