@@ -356,6 +356,64 @@ def test_learned_generation_random_network_matches_oracle(dev, orc):
     assert n_cmp >= 30 and n_rank >= 10
 
 
+def _window_cells(b):
+    """Cells of the height-map window the place kernel raises in LDS at each
+    commit: the object's bounding sphere (about the centre of its spheres'
+    box, radius to the farthest sphere surface) over the 64 x 64 grid of its
+    support."""
+    out = []
+    for o in range(b.n_objects):
+        t = b.tmpl[b.sph_off[o]:b.sph_off[o + 1]].astype(np.float64)
+        lo, hi = (t[:, :3] - t[:, 3:]).min(0), (t[:, :3] + t[:, 3:]).max(0)
+        c = 0.5 * (lo + hi)
+        rho = float(np.max(np.linalg.norm(t[:, :3] - c, axis=1) + t[:, 3]))
+        hx, hy = b.sup[b.obj_sup[o], 12], b.sup[b.obj_sup[o], 13]
+        nx = min(64, math.ceil(2 * rho / (2 * hx / 64)) + 2)
+        ny = min(64, math.ceil(2 * rho / (2 * hy / 64)) + 2)
+        out.append(nx * ny)
+    return np.array(out)
+
+
+def test_learned_generation_small_supports_matches_oracle(dev, orc):
+    """Uneven scenes on small supports with objects of up to 200 spheres (four
+    per lane): the commit raises the height map through its LDS window for
+    small objects and cell by cell in the map for objects whose window would
+    exceed the 1024 cells it holds.  A random network ranks by the state, so
+    a wrong raise changes the proposals; every decision the oracle calls sure
+    is compared."""
+    scn, ctx, torch = dev
+    b = sg.uneven_batch(16, seed=31, n_obj=(5, 10), n_sph=(16, 200), n_cand=(64, 256),
+                        n_box=(4, 8))
+    cells = _window_cells(b)
+    assert np.any(cells > 1024) and np.any(cells <= 1024)   # both paths are exercised
+    W, bb = _weights(26)
+    net = _net(scn, torch, W, bb)
+    db = scn.DeviceBatch(b)
+    scn.generate_scenes_learned(ctx, db, scn.GenArgs(seed=41), net, top_k=64)
+    torch.cuda.synchronize()
+    rec_f, rec_i = db.records()
+    ref = ol.generate_learned(b, [w.astype(np.float64) for w in W], [v.astype(np.float64) for v in bb],
+                              41, 64, orc)
+    n_cmp = n_big = 0
+    for s in range(b.n_scenes):
+        for o in range(b.obj_off[s], b.obj_off[s + 1]):
+            if ref["unsure"][o]:
+                if tuple(rec_i[o]) != tuple(ref["rec"][o]) or ref["rec"][o][1] < 0:
+                    break
+                continue
+            assert tuple(rec_i[o]) == tuple(ref["rec"][o]), (s, o - b.obj_off[s])
+            if ref["rec"][o][1] >= 0:
+                np.testing.assert_allclose(rec_f[o], ref["pose"][o], atol=2e-6, rtol=0)
+            n_cmp += 1
+            # a decision after a placement raised cell by cell
+            n_big += o > b.obj_off[s] and cells[o - 1] > 1024
+            if ref["rec"][o][1] < 0:
+                break
+    print(f"compared {n_cmp} of {b.n_objects} objects ({n_big} after a cell-by-cell raise)",
+          flush=True)
+    assert n_cmp >= 16 and n_big >= 2
+
+
 def test_learned_generation_chunking_is_invisible(dev):
     """The step launches try the proposals plus a chunk of the uniform
     fallback and resume the rest later; any chunk gives the placements of one
