@@ -78,9 +78,10 @@ enum ErrorBits {
 // Bytes of dynamic LDS the place kernel adds for a scene's depth map (batches
 // without grids).
 constexpr int kMapBytes = 24576;
-// float4 slots per object in the place kernel's LDS: its world bounding
-// sphere once placed, and 4 constants while it is to be placed
-constexpr int kObjLds = 5;
+// 16-byte slots per object in the place kernel's LDS: its world bounding
+// sphere once placed, and 4 constants and an index row while it is to be
+// placed
+constexpr int kObjLds = 6;
 // the place kernel's LDS copy of a scene's first 64 box rows (16 floats each)
 constexpr int kBoxLdsBytes = 64 * 16 * 4;
 // cells of the height-map window the place kernel raises in LDS at a commit

@@ -601,7 +601,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     float4* linfo = lbnd + cap_obj;
     const int n_info = max_steps > 0 ? min(cap_obj, max_steps) : cap_obj;
     // the rows of the scene's first 64 boxes (kBoxLdsBytes)
-    float* lbox = reinterpret_cast<float*>(linfo + 4 * n_info);
+    // per object the launch may place: first template sphere, sphere count,
+    // candidates per attempt and support, staged once so that an object's
+    // start reads them from LDS instead of through a chain of scalar loads
+    int4* lobj = reinterpret_cast<int4*>(linfo + 4 * n_info);
+    float* lbox = reinterpret_cast<float*>(lobj + n_info);
     // scenes without grids: the depth map after them (kMapBytes)
     constexpr bool kMap = !kGrids;
     int8_t* lmap = reinterpret_cast<int8_t*>(lbox) + kBoxLdsBytes;
@@ -756,6 +760,11 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
     // collide, and its registers would cost occupancy.
     // With info_keep (computed once per generation by k_object_info) they
     // are only copied.
+    for (int jj = j + (int)threadIdx.x; jj < j_end; jj += blockDim.x) {
+        const int oo = o0 + jj, a = sph_off[oo];
+        lobj[jj - j] = make_int4(a, sph_off[oo + 1] - a, obj_ncand ? obj_ncand[oo] : default_ncand,
+                                 obj_sup[oo]);
+    }
     if (info_keep) {
         for (int i = threadIdx.x; i < 4 * (j_end - j); i += blockDim.x)
             linfo[i] = info_keep[4 * (size_t)(o0 + j) + i];
@@ -794,8 +803,10 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
 
     for (; j < j_end; ++j) {
         const int o = o0 + j;
-        const int sb = sph_off[o];
-        const int S = sph_off[o + 1] - sb;
+        const int4 od = lobj[j - j_start];
+        const int sb = uniform_int(od.x);
+        const int S = uniform_int(od.y);
+        const int osup = uniform_int(od.w);
         const int nq = (S + kWave - 1) / kWave;   // sphere slots per lane this object uses
         float cx[SPL], cy[SPL], cz[SPL], cr[SPL], rm2[SPL];
         bool act[SPL];
@@ -835,7 +846,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         const float prm2 = (probe.w + margin) * (probe.w + margin);
         const float prm2b = (probe2.w + margin) * (probe2.w + margin);
 
-        const Support U = load_support(sup, obj_sup[o]);
+        const Support U = load_support(sup, osup);
         // ratio_on_support (Sec. IV-F): the support eroded by ratio x half
         // the shorter x / y extent of the object's sphere set
         float ero = 0.f;
@@ -935,7 +946,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
         for (int q = 0; q < SPL; ++q) wz0[q] = (cz[q] + zc) + U.t[2];
         const float bz0 = (bc[2] + zc) + U.t[2], pz0 = (probe.z + zc) + U.t[2];
         const float pz02 = (probe2.z + zc) + U.t[2];
-        const int C = obj_ncand ? obj_ncand[o] : default_ncand;
+        const int C = uniform_int(od.z);
         // proposals of this scene (only when it has them this step)
         const int pk = prop_bins ? prop_k : 0;
         const int32_t* pb = prop_bins ? prop_bins + (size_t)s * prop_k : nullptr;
@@ -1406,7 +1417,7 @@ __device__ __forceinline__ void place_scenes(SCN_PLACE_PARAMS) {
             int* T = reinterpret_cast<int*>(lbox);
             int tx0 = 0, ty0 = 0, tw = 0, th = 0;
             if (kHmap && hmap) {
-                const int u = obj_sup[o];
+                const int u = osup;
                 F = support_frame(sup, u);
                 H = hmap + (size_t)u * 4096;
                 float qx, qy, qz;
@@ -1581,10 +1592,10 @@ static hipError_t launch_place_one(const scn_batch& b, const scn_gen_args& a,
                                      : place_kernel_h<SPL, false, false>());
     }
     // the kernel's layout: placed spheres (LDS instances), a bounding sphere
-    // per object, 4 constants per object the launch may place, box rows,
-    // depth map (grid-free batches)
+    // per object, 4 constants and one index row per object the launch may
+    // place, box rows, depth map (grid-free batches)
     const int n_info = plan.max_steps > 0 ? std::min(plan.cap_obj, plan.max_steps) : plan.cap_obj;
-    const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj + 4 * n_info) + kBoxLdsBytes +
+    const int bytes = 16 * ((kLds ? cap_sph : 0) + plan.cap_obj + 5 * n_info) + kBoxLdsBytes +
                       (b.grid_off ? 0 : kMapBytes);
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
