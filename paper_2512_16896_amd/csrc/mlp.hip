@@ -53,7 +53,20 @@ __global__ __launch_bounds__(256) void k_gemm(int M, const int32_t* __restrict__
     __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN * kLdsRow];
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
-    const int bm = blockIdx.y * BM, bn = blockIdx.x * BN;
+    // XCD-aware tile order.  The chip deals workgroup L (in launch order) to
+    // XCD L % 8, each XCD with its own L2.  With a multiple of 8 row blocks,
+    // XCD x takes row blocks x, x + 8, x + 16, ... with all their column
+    // tiles, so a row block's A panel is fetched into one L2 and reused by its
+    // column tiles there, and the live row blocks of a short (device-counted)
+    // batch still spread over all XCDs.  Which workgroup computes a tile does
+    // not change its result.
+    int tm = blockIdx.y, tn = blockIdx.x;
+    if ((gridDim.y & 7) == 0) {
+        const int L = blockIdx.y * gridDim.x + blockIdx.x, slot = L >> 3;
+        tm = (L & 7) + 8 * (slot / (int)gridDim.x);
+        tn = slot % (int)gridDim.x;
+    }
+    const int bm = tm * BM, bn = tn * BN;
     if (m_dev) M = min(M, *m_dev);
     if (bm >= M) return;   // the whole workgroup, before any barrier
     const int r = lane & 15, kq = (lane >> 4) * 8;
