@@ -124,7 +124,7 @@ def recorded_traffic(key: str, path: str = None):
 
 
 def dense_equivalent(b, db, ncand, retries=10):
-    """Survey definition of the generation roofline: the FLOP a dense check of
+    """Dense-equivalent work of a generation: the FLOP a dense check of
     every candidate a first-valid scan must decide would compute (entries up
     to and including the accepted one; all (R+1) C entries of an object that
     fails), at 11 per sphere pair, 26 per sphere-box test, 10 per sphere
