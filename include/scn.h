@@ -593,7 +593,9 @@ int scn_harvest_labels(scn_ctx *ctx, const scn_batch *b, const int32_t *n_state,
  * as long as a scene's object count, then every 8 ticks, so the call
  * returns with the stream drained.  args->schedule (0: one wave per scene)
  * shapes the first ticks' new-object launches, args->wide_schedule (0: 4
- * waves) the rest; neither is the context's tuned plain schedule.  The
+ * waves) the rest; neither is the context's tuned plain schedule, and of
+ * either only the waves count (placed spheres stay in global memory and the
+ * scenes run in list order, whatever the LDS and order bits say).  The
  * workspace also keeps each scene's depth map, each placed object's bounding
  * sphere and each object's constants across the ticks.  A state's height map
  * is that of its next object's support (multi-support and voxel-grid batches
