@@ -37,7 +37,7 @@ WORKLOADS = {
                               "(half extents U[0.05,0.5] m, random yaw); margin 5 mm; 10 retries",
                          make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                       fromlist=["x"]).batched_scenes(4096, seed=seed),
-                         ncand=1024, cpu_scenes=160, learned=True, dense=True),
+                         ncand=1024, cpu_scenes=160, learned=True, dense=True, tune=True),
     "table-1": dict(desc="1 scene; 1.2x0.8 m table; 8 objects x 32 spheres; 256 candidates; "
                          "4 cuboids; margin 5 mm; 10 retries",
                     make=lambda seed: __import__("paper_2512_16896_amd.scenegen",

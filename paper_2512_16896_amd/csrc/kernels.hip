@@ -492,23 +492,78 @@ hipError_t launch_check(const scn_batch& b, const int32_t* obj_idx, const int32_
 
 // ---------------------------------------------------------------------------
 // Longest-first order.  Work estimate of a scene: its objects times its
-// spheres (the pair work of a scene grows with both); 256 log-spaced buckets,
-// largest first; scenes inside a bucket in arbitrary order (results do not
-// depend on the order: scenes are independent).
+// spheres (the pair work of a scene grows with both), scaled by how crowded
+// its first object's support is with boxes: the footprints of the boxes'
+// support-frame bounding boxes that reach above the plane, clipped to the
+// support rectangle, as a fraction c of its area (overlaps counted twice).
+// On a crowded support more objects exhaust their attempts, and a scene
+// with an object that does runs several times longer; the scale is
+// 1 + 3 min(c, 1.5).  256 log-spaced buckets, largest first; scenes inside a
+// bucket in arbitrary order (results do not depend on the order: scenes are
+// independent).
 __device__ __forceinline__ int work_bucket(const int32_t* __restrict__ obj_off,
                                            const int32_t* __restrict__ sph_off,
-                                           const int32_t* __restrict__ box_off, int s) {
+                                           const int32_t* __restrict__ box_off,
+                                           const int32_t* __restrict__ obj_sup,
+                                           const float* __restrict__ sup,
+                                           const float* __restrict__ box, int s) {
     const int o0 = obj_off[s], o1 = obj_off[s + 1];
-    const float w = (float)(o1 - o0) * (float)(sph_off[o1] - sph_off[o0] + 16 * (box_off[s + 1] - box_off[s])) + 1.f;
+    const int b0 = box_off[s], b1 = box_off[s + 1];
+    float crowd = 0.f;
+    if (o1 > o0 && b1 > b0) {
+        const float* U = sup + 16 * (size_t)obj_sup[o0];
+        const float hx = U[12], hy = U[13];
+        float cover = 0.f;
+        // (unrolled: the boxes' row loads in flight together)
+#pragma unroll 4
+        for (int bi = b0; bi < b1; ++bi) {
+            const float* B = box + 16 * (size_t)bi;
+            // box centre and bounding half extents in the support frame
+            const float dx = B[9] - U[9], dy = B[10] - U[10], dz = B[11] - U[11];
+            float c[3], e[3];
+            for (int a = 0; a < 3; ++a) {
+                c[a] = U[a] * dx + U[3 + a] * dy + U[6 + a] * dz;
+                // row a of U^T B_R, absolute, times the half extents
+                float ea = 0.f;
+                for (int k = 0; k < 3; ++k) {
+                    const float m = U[a] * B[k] + U[3 + a] * B[3 + k] + U[6 + a] * B[6 + k];
+                    ea += fabsf(m) * B[12 + k];
+                }
+                e[a] = ea;
+            }
+            if (!(c[2] + e[2] > 0.f)) continue;
+            const float ox = fminf(hx, c[0] + e[0]) - fmaxf(-hx, c[0] - e[0]);
+            const float oy = fminf(hy, c[1] + e[1]) - fmaxf(-hy, c[1] - e[1]);
+            if (ox > 0.f && oy > 0.f) cover += ox * oy;
+        }
+        const float area = 4.f * hx * hy, f = cover / area;
+        crowd = f > 0.f ? fminf(f, 1.5f) : 0.f;   // non-finite rows: no scaling
+    }
+    const float w = (float)(o1 - o0) * (float)(sph_off[o1] - sph_off[o0] + 16 * (b1 - b0)) *
+                        (1.f + 3.f * crowd) + 1.f;
     const int bk = (int)(__log2f(w) * 6.0f);
     return kOrderBuckets - 1 - min(max(bk, 0), kOrderBuckets - 1);
 }
 
-__global__ void k_order_hist(int n, const int32_t* __restrict__ obj_off,
-                             const int32_t* __restrict__ sph_off,
-                             const int32_t* __restrict__ box_off, int32_t* __restrict__ hist) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n) atomicAdd(hist + work_bucket(obj_off, sph_off, box_off, s), 1);
+static_assert(kOrderBuckets == 256, "the order kernels run one thread per bucket (256)");
+// Many scenes share a bucket: each workgroup counts its scenes per bucket in
+// LDS first and adds its counts to the global histogram with one atomic per
+// bucket it uses.
+__global__ __launch_bounds__(256) void k_order_hist(int n, const int32_t* __restrict__ obj_off,
+                                                    const int32_t* __restrict__ sph_off,
+                                                    const int32_t* __restrict__ box_off,
+                                                    const int32_t* __restrict__ obj_sup,
+                                                    const float* __restrict__ sup,
+                                                    const float* __restrict__ box,
+                                                    int32_t* __restrict__ hist) {
+    __shared__ int cnt[kOrderBuckets];
+    const int t = threadIdx.x;
+    cnt[t] = 0;
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + t;
+    if (s < n) atomicAdd(&cnt[work_bucket(obj_off, sph_off, box_off, obj_sup, sup, box, s)], 1);
+    __syncthreads();
+    if (cnt[t] > 0) atomicAdd(hist + t, cnt[t]);
 }
 
 // exclusive scan of the 256 bucket counts, one workgroup of 256 threads
@@ -526,12 +581,28 @@ __global__ void k_order_scan(int32_t* __restrict__ hist) {
     hist[t] = t == 0 ? 0 : v[t - 1];
 }
 
-__global__ void k_order_scatter(int n, const int32_t* __restrict__ obj_off,
-                                const int32_t* __restrict__ sph_off,
-                                const int32_t* __restrict__ box_off, int32_t* __restrict__ hist,
-                                int32_t* __restrict__ order) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n) order[atomicAdd(hist + work_bucket(obj_off, sph_off, box_off, s), 1)] = s;
+// The scatter: each workgroup reserves, per bucket it uses, a run of slots
+// with one atomic on the scanned histogram, and hands them out to its scenes
+// by LDS atomics.
+__global__ __launch_bounds__(256) void k_order_scatter(int n, const int32_t* __restrict__ obj_off,
+                                                       const int32_t* __restrict__ sph_off,
+                                                       const int32_t* __restrict__ box_off,
+                                                       const int32_t* __restrict__ obj_sup,
+                                                       const float* __restrict__ sup,
+                                                       const float* __restrict__ box,
+                                                       int32_t* __restrict__ hist,
+                                                       int32_t* __restrict__ order) {
+    __shared__ int cnt[kOrderBuckets], base[kOrderBuckets];
+    const int t = threadIdx.x;
+    cnt[t] = 0;
+    __syncthreads();
+    const int s = blockIdx.x * blockDim.x + t;
+    const int bk = s < n ? work_bucket(obj_off, sph_off, box_off, obj_sup, sup, box, s) : 0;
+    if (s < n) atomicAdd(&cnt[bk], 1);
+    __syncthreads();
+    base[t] = cnt[t] > 0 ? atomicAdd(hist + t, cnt[t]) : 0;
+    __syncthreads();
+    if (s < n) order[atomicAdd(&base[bk], 1)] = s;
 }
 
 __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
@@ -552,10 +623,10 @@ hipError_t launch_longest_first(const scn_batch& b, int32_t* order, int32_t* his
     const int g = (n + 255) / 256;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kOrderBuckets), 0, st, hist, kOrderBuckets, 0);
     hipLaunchKernelGGL(k_order_hist, dim3(g), dim3(256), 0, st, n, b.obj_off, b.sph_off,
-                       b.box_off, hist);
+                       b.box_off, b.obj_sup, b.sup, b.box, hist);
     hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBuckets), 0, st, hist);
     hipLaunchKernelGGL(k_order_scatter, dim3(g), dim3(256), 0, st, n, b.obj_off, b.sph_off,
-                       b.box_off, hist, order);
+                       b.box_off, b.obj_sup, b.sup, b.box, hist, order);
     return hipGetLastError();
 }
 
