@@ -139,3 +139,45 @@ def test_learned_generation_on_uneven_shelves_matches_oracle(dev, orc, kind):
     assert n_prop > 0
     assert n_cmp >= (0.5 * b.n_objects if kind == "separated" else 20)
     audit_placements(b, db.placed.cpu().numpy(), db.n_placed.cpu().numpy())
+
+
+def test_learned_generation_full_size_sampled(dev, orc):
+    """uneven-shelves-65536 at full size, in the benchmark's launch
+    configuration (learned ticks with the default launch shapes, every
+    object's own candidate count): the placements of two sampled units, the
+    fullest one and one drawn at random, are replayed by the oracle one by
+    one (with their scene indices) and compared wherever it is sure."""
+    scn, ctx, torch = dev
+    b = sg.uneven_shelf_scenes(65536, seed=0)
+    W, bb = _separated_net(27, sg.subset(b, list(range(16)))[0])
+    net = _net(scn, torch, W, bb)
+    db = scn.DeviceBatch(b)
+    scn.generate_scenes_learned(ctx, db, scn.GenArgs(seed=43, default_ncand=2048), net, top_k=64)
+    torch.cuda.synchronize()
+    ctx.read_counters()
+    rec_f, rec_i = db.records()
+    nobj = np.diff(b.obj_off)
+    rng = np.random.default_rng(8)
+    pick = sorted({int(np.argmax(nobj)), int(rng.integers(b.n_scenes))})
+    sub, ids = sg.subset(b, pick)
+    ref = ol.generate_learned(sub, [w.astype(np.float64) for w in W],
+                              [v.astype(np.float64) for v in bb], 43, 64, orc, rank_tol=0.02,
+                              scene_id=ids)
+    n_cmp = n_prop = 0
+    for k, s in enumerate(pick):
+        for j in range(int(nobj[s])):
+            o, r = int(b.obj_off[s]) + j, int(sub.obj_off[k]) + j
+            if ref["unsure"][r]:
+                if tuple(rec_i[o]) != tuple(ref["rec"][r]) or ref["rec"][r][1] < 0:
+                    break
+                continue
+            assert tuple(rec_i[o]) == tuple(ref["rec"][r]), (s, j)
+            if ref["rec"][r][1] >= 0:
+                np.testing.assert_allclose(rec_f[o], ref["pose"][r], atol=2e-6, rtol=0)
+                n_prop += ref["rec"][r][0] == -2
+            n_cmp += 1
+            if ref["rec"][r][1] < 0:
+                break
+    print(f"full size: compared {n_cmp} of {int(nobj[pick].sum())} objects of units {pick}, "
+          f"{n_prop} proposal picks", flush=True)
+    assert n_prop > 0 and n_cmp >= 0.5 * int(nobj[pick].sum())
