@@ -315,6 +315,47 @@ def test_learned_generation_matches_oracle(dev, orc):
     assert n_cmp > 0.5 * b.n_objects and n_prop > 0
 
 
+def test_learned_generation_full_size_sampled(dev, orc):
+    """batched-4096 at full size in the benchmark's launch configuration
+    (learned ticks with the default launch shapes, 1024 candidates per
+    attempt): eight sampled scenes are replayed by the oracle one by one
+    (with their scene indices) and compared wherever it is sure."""
+    scn, ctx, torch = dev
+    b = sg.batched_scenes(4096, seed=0)
+    W, bb = _separated_net(21, sg.subset(b, list(range(12)))[0])
+    net = _net(scn, torch, W, bb)
+    db = scn.DeviceBatch(b)
+    scn.generate_scenes_learned(ctx, db, scn.GenArgs(seed=37, default_ncand=1024), net, top_k=64)
+    torch.cuda.synchronize()
+    rec_f, rec_i = db.records()
+    status = db.status.cpu().numpy()
+    pick = sorted(np.random.default_rng(9).choice(b.n_scenes, 8, replace=False).tolist())
+    sub, ids = sg.subset(b, pick)
+    ref = ol.generate_learned(sub, [w.astype(np.float64) for w in W],
+                              [v.astype(np.float64) for v in bb], 37, 64, orc, rank_tol=0.02,
+                              scene_id=ids)
+    n_cmp = n_prop = 0
+    for k, s in enumerate(pick):
+        sure = True
+        for j in range(int(b.obj_off[s + 1] - b.obj_off[s])):
+            o, r = int(b.obj_off[s]) + j, int(sub.obj_off[k]) + j
+            if ref["unsure"][r]:
+                sure = False
+                break
+            assert tuple(rec_i[o]) == tuple(ref["rec"][r]), (s, j)
+            if ref["rec"][r][1] >= 0:
+                np.testing.assert_allclose(rec_f[o], ref["pose"][r], atol=2e-6, rtol=0)
+                n_prop += ref["rec"][r][0] == -2
+            n_cmp += 1
+            if ref["rec"][r][1] < 0:
+                break
+        if sure:
+            assert status[s] == ref["status"][k]
+    print(f"full size: compared {n_cmp} of {sub.n_objects} objects of scenes {pick}, "
+          f"{n_prop} proposal picks", flush=True)
+    assert n_cmp > 0.5 * sub.n_objects and n_prop > 0
+
+
 def test_learned_generation_random_network_matches_oracle(dev, orc):
     """An unseparated (random) network: the ranking follows each scene's
     state.  Every decision the oracle calls sure (no near-tie of the logits
