@@ -42,7 +42,7 @@ WORKLOADS = {
                          "4 cuboids; margin 5 mm; 10 retries",
                     make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                  fromlist=["x"]).table_scene(seed=seed),
-                    ncand=256, cpu_scenes=1),
+                    ncand=256, cpu_scenes=1, tune=True),
     "uneven-16384": dict(desc="16384 uneven scenes in one autotuned persistent launch: objects "
                               "U{5..60}, spheres per object U{16..256}, candidates per attempt "
                               "U{512..4096}, cuboids U{4..32}; support 2.0x1.0 m scaled by "
