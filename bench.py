@@ -67,14 +67,14 @@ WORKLOADS = {
                                 "free objects; 256 candidates per attempt; margin 5 mm; 10 retries",
                            make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                         fromlist=["x"]).relation_scenes(4096, seed=seed),
-                           ncand=256, cpu_scenes=0),
+                           ncand=256, cpu_scenes=0, tune=True),
     "reach-4096": dict(desc="4096 robot tables (1.2x0.8 m, 4 cuboids, robot base 0.15 m off the "
                             "near edge); 8 objects x 32 spheres that must be reachable on a "
                             "24x9x64x64 base-symmetric 4-D map (6 from above, 2 at 45 deg); 256 "
                             "candidates per attempt; margin 5 mm; 10 retries",
                        make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                     fromlist=["x"]).reach_scenes(4096, seed=seed),
-                       ncand=256, cpu_scenes=0),
+                       ncand=256, cpu_scenes=0, tune=True),
     "stable-4096": dict(desc="4096 tables (1.6x1.0 m, 6 cuboids); 12 objects x 32 spheres, of "
                              "every three one turning about z only, one resting on a face of its "
                              "bounding box (6 stable poses weighted by face area), one in one of "
@@ -82,7 +82,7 @@ WORKLOADS = {
                              "5 mm; 10 retries",
                         make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                      fromlist=["x"]).stable_scenes(4096, seed=seed),
-                        ncand=256, cpu_scenes=0),
+                        ncand=256, cpu_scenes=0, tune=True),
     "uneven-shelves-65536": dict(desc="learned proposal + uneven batching on dense multi-support "
                                       "scenes: 65536 shelf units (6 stacked 0.8x0.4 m shelves, "
                                       "64^3 SDF grids, trilinear); objects U{40..100} per scene "
@@ -103,7 +103,7 @@ WORKLOADS = {
                               "6 static cabinet boards; margin 5 mm; 10 retries",
                          make=lambda seed: __import__("paper_2512_16896_amd.scenegen",
                                                       fromlist=["x"]).drawer_scenes(4096, seed=seed),
-                         ncand=256, cpu_scenes=0),
+                         ncand=256, cpu_scenes=0, tune=True),
 }
 
 
