@@ -590,7 +590,7 @@ int scn_autotune(scn_ctx* c, scn_batch* b, const scn_gen_args* a, int32_t* best_
     const int lpt = SCN_SCHED_LONGEST_FIRST;
     for (int code : {0, 2, 4, (int)SCN_SCHED_LDS_NONE}) consider(4 | lpt | (code << SCN_SCHED_LDS_SHIFT));
     const int lds_bits = best & SCN_SCHED_LDS_MASK;
-    for (int w : {2, 8, 16}) consider(w | lpt | lds_bits);
+    for (int w : {1, 2, 8, 16}) consider(w | lpt | lds_bits);
     consider(best & ~SCN_SCHED_LONGEST_FIRST);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
