@@ -448,7 +448,10 @@ int scn_forward_kinematics(scn_ctx *ctx, const scn_joints *joints, uint64_t seed
  * spheres from global memory):
  *   bits 0-4  waves per workgroup: candidates of one scene in flight
  *             (1..16)
- *   bit  5    longest-first scene order (larger scenes start first)
+ *   bit  5    longest-first scene order: scenes with more work start
+ *             first, the work estimated as objects x (spheres + 16 boxes)
+ *             scaled by how crowded the support is with boxes (crowded
+ *             supports are where objects exhaust their attempts)
  *   bits 8-11 LDS budget for a scene's placed spheres: 0 = sized for the
  *             largest scene (every scene LDS-resident); 1..5 = 32, 48, 64,
  *             80, 96 KB (larger scenes read their placed spheres from global
